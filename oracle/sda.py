@@ -1,0 +1,39 @@
+"""Smooth data annealing (SDA) moments and tempering updates (test infrastructure).
+
+Section 3.1: with Omega_k = -log p(y_{1:M_{k-1}} | theta) on the data already
+annealed in and Omega^_k = -log p(y_{M_{k-1}+1:M_k} | theta) on the newest
+mini-batch, the tempering exponent beta is moved so that the entropy changes
+at a constant rate dS.  Weighted moments use the normalised weights (Eq. E{XY}
+and the lines before it).
+
+Readings: the update without new data is Eq. beta_initial_data_k and the
+update after a mini-batch was appended is Eq. beta_annealed_k; if an update
+would not increase beta the sign of dS is flipped (equivalently the magnitude
+of the step is used); beta is clipped to 1, and after it reaches 1 a new
+mini-batch is appended and beta restarts at 0.1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def weighted_moments(w, omega, omega_hat):
+    """(Var(Omega^), Cov(Omega, Omega^)) under normalised weights w."""
+    w = np.asarray(w, dtype=np.float64)
+    a = np.asarray(omega, dtype=np.float64)
+    b = np.asarray(omega_hat, dtype=np.float64)
+    e_b = np.sum(w * b)
+    var_b = np.sum(w * b * b) - e_b * e_b
+    e_a = np.sum(w * a)
+    cov = np.sum(w * a * b) - e_a * e_b
+    return var_b, cov
+
+
+def next_beta(beta, w, omega, omega_hat, annealed: bool, dS: float = 1.0):
+    """beta_{k+1} from beta_k (Eqs. beta_initial_data_k, beta_annealed_k)."""
+    var_b, cov = weighted_moments(w, omega, omega_hat)
+    denom = var_b + cov if annealed else var_b
+    step = -dS / denom
+    if not np.isfinite(step) or step <= 0.0:
+        step = abs(dS / denom) if np.isfinite(denom) and denom != 0.0 else 1.0
+    return min(1.0, beta + step)

@@ -1,0 +1,124 @@
+"""Pins for the oracle's learned proposal density, network gradient and Adam (CPU only)."""
+import math
+
+import numpy as np
+
+from oracle import learned, mlp, smc
+import smc_inputs
+
+
+def _sampler(h=0.01):
+    X, y = smc_inputs.blobs(128, seed=0)
+    return smc.Sampler(X, y, [2, 16, 2], "tanh", step_size=h, leapfrog_steps=1), X, y
+
+
+def test_group_index():
+    gid = learned.group_index([2, 3, 2])
+    # layer 1: 3 rows of [w w b]; layer 2: 2 rows of [w w w b]
+    assert gid.tolist() == [0, 0, 1] * 3 + [2, 2, 2, 3] * 2
+    assert learned.blob_size(4) == 8 + 256 + 64 + 4096 + 64 + 5 * 64 + 5
+
+
+def test_constant_outputs_reduce_to_fixed_step_langevin():
+    # zero output layer -> o = 0 -> h = h0, m = 1: the learned move and its Gaussian
+    # forward/reverse densities must reproduce the fixed-step S = 1 update exactly
+    h0 = 0.02
+    G = learned.n_groups([2, 16, 2])
+    blob = learned.init_blob(G, seed=0)
+    p = learned.unpack_blob(blob, G)
+    p["W3"][:] = 0.0
+    p["b3"][:] = 0.0
+    th0 = smc_inputs.prior_draw(1, 16, 82, 1.0)
+    xi = smc_inputs.momenta(2, (16, 82))
+    a, _, _ = _sampler(h0)
+    b, _, _ = _sampler(h0)
+    a.init(th0, 64, 2.0)
+    b.init(th0, 64, 2.0)
+    a.step(96, 128 / 96, xi)
+    learned.learned_step(b, 96, 128 / 96, xi, blob, h0, k=1, K=10, N=128)
+    np.testing.assert_allclose(b.theta, a.theta, rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(b.last_increment, a.last_increment, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(b.logw, a.logw, atol=1e-9)
+
+
+def _log_ratio(s, theta, theta1, blob, h0, m, lam, G, gid):
+    """log L(theta | theta1) - log q(theta1 | theta) with the learned scales."""
+    ll0, g0 = s.loglik_grad(theta, m, lam)
+    ll1, g1 = s.loglik_grad(theta1, m, lam)
+    h, mg = learned.scales(learned.net_forward(blob, learned.features(ll0, g0, m, 1, 10, 128), G)[0], h0)
+    h1, mg1 = learned.scales(learned.net_forward(blob, learned.features(ll1, g1, m, 1, 10, 128), G)[0], h0)
+    me, me1 = mg[:, gid], mg1[:, gid]
+    mf = theta + 0.5 * (h * h)[:, None] * g0 / me
+    mr = theta1 + 0.5 * (h1 * h1)[:, None] * g1 / me1
+    lq = np.sum(-0.5 * math.log(2 * math.pi) - np.log(h[:, None] / np.sqrt(me))
+                - 0.5 * ((theta1 - mf) * np.sqrt(me) / h[:, None]) ** 2, axis=1)
+    ll = np.sum(-0.5 * math.log(2 * math.pi) - np.log(h1[:, None] / np.sqrt(me1))
+                - 0.5 * ((theta - mr) * np.sqrt(me1) / h1[:, None]) ** 2, axis=1)
+    return ll - lq
+
+
+def test_density_ratio_is_antisymmetric():
+    G = learned.n_groups([2, 16, 2])
+    gid = learned.group_index([2, 16, 2])
+    blob = learned.init_blob(G, seed=3)
+    s, _, _ = _sampler()
+    th = smc_inputs.prior_draw(4, 5, 82, 1.0).astype(np.float64)
+    th1 = th + 0.01 * smc_inputs.momenta(5, th.shape)
+    r01 = _log_ratio(s, th, th1, blob, 0.01, 64, 2.0, G, gid)
+    r10 = _log_ratio(s, th1, th, blob, 0.01, 64, 2.0, G, gid)
+    np.testing.assert_allclose(r01, -r10, rtol=1e-10, atol=1e-10)
+
+
+def test_learned_step_uses_general_weight_form():
+    # the learned step's increment equals log pi_k(theta') - lp + log L - log q with
+    # densities evaluated independently here
+    G = learned.n_groups([2, 16, 2])
+    gid = learned.group_index([2, 16, 2])
+    blob = learned.init_blob(G, seed=8)
+    s, _, _ = _sampler()
+    th0 = smc_inputs.prior_draw(6, 6, 82, 1.0)
+    s.init(th0, 64, 2.0)
+    theta, lp = s.theta.copy(), s.lp.copy()
+    learned.learned_step(s, 64, 2.0, smc_inputs.momenta(9, (6, 82)), blob, 0.01, k=1, K=10, N=128)
+    r = _log_ratio(s, theta, s.theta, blob, 0.01, 64, 2.0, G, gid)
+    np.testing.assert_allclose(s.last_increment, s.lp - lp + r, rtol=1e-9, atol=1e-9)
+
+
+def test_mse_gradient_matches_finite_differences():
+    G = 4
+    blob = learned.init_blob(G, seed=1, mu=[0.1, -0.2, 0.5, 0.3], sd=[1.5, 0.7, 0.3, 0.4])
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal((11, 4))
+    t = rng.standard_normal((11, 5))
+    _, g = learned.mse_loss_grad(blob, f, t, G)
+    idx = rng.choice(np.arange(8, blob.shape[0]), 60, replace=False)
+    for k in idx:
+        bp = blob.copy(); bp[k] += 1e-6
+        bm = blob.copy(); bm[k] -= 1e-6
+        fd = (learned.mse_loss_grad(bp, f, t, G)[0] - learned.mse_loss_grad(bm, f, t, G)[0]) / 2e-6
+        assert abs(fd - g[k]) < 1e-7 + 1e-6 * abs(fd)
+    assert np.all(g[:8] == 0.0)
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    # after one step the bias-corrected moments are g and g^2: the update is lr * g / (|g| + eps)
+    blob = np.array([1.0, -2.0, 3.0])
+    grad = np.array([0.5, -4.0, 1e-3])
+    new, _ = learned.adam_update(blob, grad, (np.zeros(3), np.zeros(3), 0), lr=0.1)
+    np.testing.assert_allclose(new, blob - 0.1 * grad / (np.abs(grad) + 1e-8), rtol=1e-12)
+
+
+def test_scales_fallback_and_bounds():
+    o = np.array([[0.0, 0.0], [50.0, -50.0], [np.nan, 1.0]])
+    h, mg = learned.scales(o, 0.01)
+    np.testing.assert_allclose(h, [0.01, 0.1, 0.01], rtol=1e-12)
+    np.testing.assert_allclose(mg[:, 0], [1.0, 0.1, 1.0], rtol=1e-12)
+
+
+def test_step_size_targets_prefer_stable_steps():
+    # on a sharply curved target, very large steps are rejected by the Metropolis factor
+    s, _, _ = _sampler(0.01)
+    s.init(smc_inputs.prior_draw(3, 12, 82, 1.0), 128, 1.0)
+    logh, logm = learned.step_size_targets(s, 128, 1.0, smc_inputs.momenta(4, (12, 82)), 0.01)
+    assert np.all(logh >= math.log(0.01 / 8) - 1e-12) and np.all(logh <= math.log(0.08) + 1e-12)
+    np.testing.assert_allclose(logm.mean(axis=1), 0.0, atol=1e-12)
