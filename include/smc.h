@@ -1,0 +1,259 @@
+/*
+ * smc.h - C ABI of the MI355X (gfx950) data-annealed SMC sampler for
+ * Bayesian neural-network posteriors.
+ *
+ * The method (Millard, Murphy, Green, Maskell, "Investigating Batch Inference
+ * in a Sequential Monte Carlo Framework for Neural Networks"):
+ *   - J weighted particles theta_j target pi(theta) ~ p(y_{1:N} | theta) q0(theta)
+ *     (Section 2);
+ *   - each iteration moves the particles with S leapfrog steps of a
+ *     gradient-based Markov kernel (Section 2.1, Eqs. mom_first, pos_update,
+ *     mom_second; Langevin dynamics is S = 1) and reweights them with the
+ *     reversed-momentum L-kernel (Eq. weight_update_fp);
+ *   - weights are normalised (Eq. normalise), the effective sample size is
+ *     computed (Eq. jeff) and the population is resampled when it drops below
+ *     a fraction of J (Section 2);
+ *   - log-likelihoods and gradients are evaluated on a growing prefix
+ *     y_{1:M_k} of the data and scaled by lambda_k = N / M_k
+ *     (Section 3, Eq. approx-grad; data annealing, Section 3.1).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_dev are device (HBM) pointers; all other pointers are
+ *     host pointers.  Sizes are element counts.
+ *   - All device work is enqueued on the HIP stream given to smc_init (or to
+ *     the stateless call).  Calls that return values through host pointers
+ *     synchronise that stream; calls without host outputs do not.
+ *   - Buffers passed in belong to the caller.  smc_init borrows x_dev/y_dev
+ *     only for the duration of the call (it makes its own padded copies); the
+ *     library owns all particle state and frees it in smc_destroy.
+ *   - No exception or abort crosses the ABI: every function returns an
+ *     smc_status; smc_status_string gives a message, smc_last_error gives the
+ *     detail of the most recent failure on the calling thread.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *
+ * Parameter layout of one particle (D floats): for each layer l = 1..L with
+ * n_{l-1} inputs and n_l outputs, the block [W_l | b_l] of shape
+ * [n_l x (n_{l-1} + 1)], row-major: each output unit's n_{l-1} weights
+ * followed by its bias.  Populations are [J x D] row-major float32.
+ */
+#ifndef SMC_H_
+#define SMC_H_
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define SMC_API __attribute__((visibility("default")))
+#else
+#define SMC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum smc_status {
+  SMC_OK = 0,
+  SMC_ERR_ARG = 1,          /* invalid argument (size, pointer, mode, subset order) */
+  SMC_ERR_OOM = 2,          /* device allocation failed */
+  SMC_ERR_DEVICE = 3,       /* a HIP call failed */
+  SMC_ERR_STATE = 4,        /* call not valid in the handle's current state */
+  SMC_ERR_NONFINITE = 5,    /* every particle has a non-finite log-weight */
+  SMC_ERR_UNSUPPORTED = 6,  /* configuration not supported by this build */
+  SMC_ERR_NOLIB = 7         /* reserved for bindings: library not loaded */
+} smc_status;
+
+enum { SMC_ACT_TANH = 0, SMC_ACT_RELU = 1 };
+enum { SMC_LIK_CATEGORICAL = 0, SMC_LIK_GAUSSIAN = 1 };
+enum { SMC_PREC_FP32 = 0, SMC_PREC_BF16 = 1 };
+enum { SMC_PROPOSAL_FIXED = 0, SMC_PROPOSAL_LEARNED = 1 };
+enum { SMC_MODEL_MLP = 0, SMC_MODEL_CNN = 1 };
+enum { SMC_RESAMPLE_IF_NEEDED = 0, SMC_RESAMPLE_ALWAYS = 1, SMC_RESAMPLE_NEVER = 2 };
+
+#define SMC_MAX_LAYERS 8
+
+typedef struct smc_config {
+  int32_t n_particles;                 /* J >= 1 (at most 8192) */
+  int32_t n_layers;                    /* L >= 1 weight layers (at most SMC_MAX_LAYERS) */
+  int32_t widths[SMC_MAX_LAYERS + 1];  /* n_0 = input features, ..., n_L = outputs */
+  int32_t activation;                  /* hidden activation: SMC_ACT_TANH | SMC_ACT_RELU */
+  int32_t model_kind;                  /* SMC_MODEL_MLP (SMC_MODEL_CNN: see smc_cnn.h) */
+  int32_t likelihood;                  /* SMC_LIK_CATEGORICAL (n_L <= 16 classes) | SMC_LIK_GAUSSIAN (n_L = 1) */
+  int32_t precision;                   /* GEMM operand precision; accumulation is always FP32 */
+  int32_t proposal;                    /* SMC_PROPOSAL_FIXED | SMC_PROPOSAL_LEARNED (needs S = 1) */
+  int32_t leapfrog_steps;              /* S >= 1 (Section 2.1) */
+  int32_t reserved0;
+  double step_size;                    /* h (Section 2.1) */
+  double prior_std;                    /* q0 = N(0, prior_std^2 I) */
+  double noise_std;                    /* sigma of the Gaussian likelihood */
+  double ess_frac;                     /* resample when ESS < ess_frac * J (Section 2: 0.5) */
+  uint64_t seed;                       /* key of the device Philox-4x32-10 generator */
+  int64_t act_budget_bytes;            /* activation memory of one gradient pass; 0 = 8 GiB */
+} smc_config;
+
+typedef struct smc_step_info {
+  double ess;                /* J_eff after reweighting (Eq. jeff) */
+  double log_z_increment;    /* log sum_j w~_{k-1,j} * exp(increment_j) */
+  double mean_loglik;        /* mean over particles of the subset log-likelihood LL_k */
+  double max_loglik;
+  int32_t n_nonfinite;       /* particles whose weight was set to zero (log w = -inf) */
+  int32_t resample_recommended; /* ESS < ess_frac * J */
+  int64_t grad_evals;        /* particle-sample gradient evaluations done by this call */
+} smc_step_info;
+
+typedef struct smc_handle* smc_t;
+
+SMC_API const char* smc_status_string(smc_status s);
+/* Detail of the last error raised on the calling thread ("" if none). */
+SMC_API const char* smc_last_error(void);
+
+/*
+ * Create a sampler and apply the initial weighting (Section 2, Eq. init_weight).
+ *   x_dev      [n_data x n_0] float32 row-major, already in annealing order
+ *              (the subset at iteration k is rows [0, M_k); Section 3).
+ *   y_dev      [n_data] int32 class labels (categorical) or float32 targets (Gaussian).
+ *   theta0_dev [J x D] float32 initial particles, or NULL to draw theta_0 ~ q0
+ *              on the device.
+ *   m0, lambda0  initial subset size M_0 (1 <= m0 <= n_data) and scale.
+ *   hip_stream hipStream_t (NULL = default stream).
+ * On success *out receives the handle.  Errors: SMC_ERR_ARG for invalid
+ * configuration or sizes, SMC_ERR_OOM, SMC_ERR_DEVICE, SMC_ERR_NONFINITE.
+ */
+SMC_API smc_status smc_init(const smc_config* cfg, const float* x_dev, const void* y_dev, int64_t n_data,
+                    const float* theta0_dev, int64_t m0, double lambda0, void* hip_stream, smc_t* out);
+SMC_API void smc_destroy(smc_t h);
+
+/*
+ * One SMC iteration on the subset [0, m_k) with scale lambda_k: if the subset
+ * or lambda changed, the gradient at the current particles is recomputed on
+ * the new subset; then S leapfrog steps (Section 2.1), the L-kernel weight
+ * update (Eq. weight_update_fp; the learned proposal uses the general form of
+ * Eq. weight_update), normalisation (Eq. normalise) and the ESS (Eq. jeff).
+ * m_k must not decrease (append-only annealing, Section 3) and must be
+ * <= n_data.  info (host, nullable) receives statistics; passing it
+ * synchronises the stream.  SMC_ERR_NONFINITE if every weight became zero.
+ */
+SMC_API smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info);
+
+/*
+ * Systematic resampling (Section 2 resamples when J_eff < J/2).
+ *   mode      SMC_RESAMPLE_IF_NEEDED (decided on the device: ESS < ess_frac*J),
+ *             SMC_RESAMPLE_ALWAYS or SMC_RESAMPLE_NEVER.
+ *   u         host pointer to the offset u in [0, 1), or NULL to draw it on the device.
+ *   resampled (host, nullable) receives 1 if the population was resampled.
+ *   ancestors_host (host, nullable) [J] receives the sorted systematic ancestors
+ *             (identity if not resampled).  Non-null host outputs synchronise.
+ * Survivors keep their slot; dead slots receive the surplus copies (in-place).
+ * Weights are reset to 1/J after resampling.
+ */
+SMC_API smc_status smc_resample(smc_t h, int32_t mode, const double* u, int32_t* resampled, int32_t* ancestors_host);
+
+/*
+ * Posterior predictive p(y | x) = sum_j w~_j softmax(f_{theta_j}(x)) (Section 2,
+ * posterior estimates) on n test inputs.
+ *   x_dev [n x n_0] float32; y_dev [n] int32 labels or NULL;
+ *   probs_dev [n x n_L] float32 or NULL;
+ *   accuracy / mean_log_pred (host, nullable; need y_dev): arg-max accuracy
+ *   (lowest class on ties) and mean_i log sum_j w~_j p(y_i | x_i, theta_j).
+ */
+SMC_API smc_status smc_posterior_predict(smc_t h, const float* x_dev, const int32_t* y_dev, int64_t n,
+                                 float* probs_dev, double* accuracy, double* mean_log_pred);
+
+/* Weighted posterior mean sum_j w~_j theta_j (Section 2), [D] float64 on the device. */
+SMC_API smc_status smc_posterior_mean(smc_t h, double* mean_dev);
+
+/*
+ * Copy the population out (any pointer may be NULL):
+ *   theta_dev [J x D] float32, logw_dev [J] normalised log-weights (float64),
+ *   loglik_dev [J] subset log-likelihoods LL_k (float64),
+ *   logpi_dev [J] cached log pi_k(theta_k) (float64),
+ *   grad_dev [J x D] float32 gradient of log pi_k at theta_k (prior included).
+ */
+SMC_API smc_status smc_get_state(smc_t h, float* theta_dev, double* logw_dev, double* loglik_dev,
+                         double* logpi_dev, float* grad_dev);
+
+/*
+ * Replace the population (checkpoint restore).  theta_dev is required; the
+ * log-likelihood and gradient are recomputed on the current subset; logw_dev
+ * (normalised log-weights) and logpi_dev may be NULL (then log w = lambda LL
+ * as at initialisation and log pi is recomputed).  rng_counter restores the
+ * device generator position (iteration counter).
+ */
+SMC_API smc_status smc_set_state(smc_t h, const float* theta_dev, const double* logw_dev, const double* logpi_dev,
+                         uint64_t rng_counter);
+
+/* Device generator position (advanced once per smc_step and per device-drawn u). */
+SMC_API smc_status smc_get_rng_counter(smc_t h, uint64_t* counter);
+
+/*
+ * Use momenta_dev [J x D] float32 as the standard-normal draw of the next
+ * smc_step instead of the device generator (the initial momentum P_{k-1} of
+ * Eq. mom_first, or the noise xi of the learned move).  Consumed by that step.
+ */
+SMC_API smc_status smc_set_noise(smc_t h, const float* momenta_dev);
+
+/*
+ * Learned proposal-scale network (an extension: the paper's move uses a fixed
+ * step).  params_dev is the flat float32 blob
+ *   mu[4], sd[4], W1[64x4], b1[64], W2[64x64], b2[64], W3[(1+G)x64], b3[1+G]
+ * with G = 2L parameter groups; h0 is the base step size.  The handle copies it.
+ */
+SMC_API smc_status smc_set_proposal_net(smc_t h, const float* params_dev, int32_t n_params, double h0);
+
+/*
+ * Per-particle features of the learned proposal at the current state,
+ * [J x 4] float64: (log |grad log pi|, LL / M_k, k / K, M_k / N) with
+ * k_over_K and m_over_N supplied by the caller.
+ */
+SMC_API smc_status smc_proposal_features(smc_t h, double k_over_K, double m_over_N, double* feat_dev);
+
+/*
+ * Stand-alone network pass for a population theta_dev [J x D] on the first m
+ * samples of the handle's data (the handle's particles are not touched):
+ *   smc_nn_forward:  ll_dev [J] = sum_{i<m} log p(y_i | x_i, theta_j)  (float64)
+ *   smc_nn_backward: additionally grad_dev [J x D] = scale_j * d LL_j / d theta_j
+ *                    (float32; scale_dev [J] float64 or NULL for 1).  The forward
+ *                    activations are recomputed chunk by chunk inside the backward.
+ */
+SMC_API smc_status smc_nn_forward(smc_t h, const float* theta_dev, int64_t m, double* ll_dev);
+SMC_API smc_status smc_nn_backward(smc_t h, const float* theta_dev, int64_t m, const double* scale_dev,
+                           double* ll_dev, float* grad_dev);
+
+/* Number of parameters D of one particle for the handle's network. */
+SMC_API int64_t smc_n_params(smc_t h);
+/* Samples per activation chunk chosen from act_budget_bytes (for tests). */
+SMC_API int64_t smc_chunk_samples(smc_t h);
+
+/* ---------------------------------------------------------------- stateless kernels */
+
+/*
+ * Normalise J log-weights in FP64 (Eq. normalise, log domain) and compute the
+ * ESS (Eq. jeff).  logw_out_dev [J] receives log w~; stats_dev [4] receives
+ * (log sum_j w_j, ESS, number of -inf/NaN entries, max log w).  In-place
+ * (logw_out_dev == logw_dev) is allowed.
+ */
+SMC_API smc_status smc_normalise(const double* logw_dev, int32_t J, double* logw_out_dev, double* stats_dev,
+                         void* hip_stream);
+
+/*
+ * Systematic resampling of normalised weights w_dev [J] (float64) with offset
+ * u in [0, 1), exact integer rule: Q_j = floor(w_j 2^50), S = inclusive prefix
+ * sums, T = S_{J-1}, R = min(floor(u T), T - 1), t_k = floor((k T + R) / J),
+ * ancestor_k = #{j : S_j <= t_k}.  ancestors_dev [J] int32 receives the sorted
+ * ancestors; placement_dev [J] int32 (nullable) the in-place arrangement
+ * (survivors keep their slot, dead slots take the surplus copies in order).
+ */
+SMC_API smc_status smc_systematic_resample(const double* w_dev, int32_t J, double u, int32_t* ancestors_dev,
+                                   int32_t* placement_dev, void* hip_stream);
+
+/*
+ * Raw Philox-4x32-10 blocks: for i in [0, n_blocks) out_dev[4i..4i+3] =
+ * philox(ctr = (i, c1, c2, c3), key = (key0, key1)).
+ */
+SMC_API smc_status smc_philox(uint32_t key0, uint32_t key1, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n_blocks,
+                      uint32_t* out_dev, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMC_H_ */

@@ -1,0 +1,295 @@
+// MFMA GEMM kernels for gfx950 (CDNA4).
+//
+// Tiling: a 256-thread workgroup (4 wave64s) computes a BM x BN tile; each wave
+// owns a WM x WN sub-tile made of 32x32 MFMA blocks.  Every K step stages a
+// 128-byte-deep slice of A and B (64 bf16 or 32 fp32) in LDS with a 16-byte row
+// pad (row stride 144 B, so the 16-byte fragment reads of 16 consecutive rows hit
+// distinct banks) and double-buffers it, prefetching the next slice into
+// registers while the current one feeds the matrix cores.
+//
+// MFMA forms:
+//   bf16: v_mfma_f32_32x32x16_bf16 - each lane supplies 8 consecutive K values
+//   fp32: v_mfma_f32_32x32x2_f32   - each lane reads 4 consecutive K values and
+//         issues 4 MFMAs, instruction c taking component c (lane halves cover
+//         k and k+4), so one 16-byte LDS read feeds 4 instructions.
+// Both operands use the same lane->k assignment, so any such assignment yields
+// the same sum; only the row/column lane mapping (row = lane % 32) and the
+// accumulator layout (row = 8*(q/4) + 4*(lane/32) + q%4, col = lane % 32) matter.
+#include "gemm.h"
+
+#include <type_traits>
+
+namespace smc {
+
+namespace {
+
+constexpr int THREADS = 256;
+constexpr int ROW_BYTES = 128;          // K slice per stage, in bytes
+constexpr int LDS_ROW = ROW_BYTES + 16; // padded LDS row stride
+constexpr int ROWV = ROW_BYTES / 16;    // 16-byte vectors per row
+
+template <typename T> struct Mf;
+template <> struct Mf<__bf16> {
+  static constexpr int VEC = 8;
+  __device__ static __forceinline__ f32x16 mma(const u32x4& a, const u32x4& b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                    0, 0, 0);
+  }
+};
+template <> struct Mf<float> {
+  static constexpr int VEC = 4;
+  __device__ static __forceinline__ f32x16 mma(const u32x4& a, const u32x4& b, f32x16 c) {
+    const f32x4 av = __builtin_bit_cast(f32x4, a);
+    const f32x4 bv = __builtin_bit_cast(f32x4, b);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bv[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[1], bv[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[2], bv[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[3], bv[3], c, 0, 0, 0);
+    return c;
+  }
+};
+
+struct SplitIdx {
+  int64_t colpart;  // (col / cs) * sC + (col % cs) * cstr + b * sb
+  int rq, rr;       // row / rs, row % rs for the base row
+};
+
+__device__ __forceinline__ SplitIdx split_base(const OutDesc& d, int b, int rbase, int col) {
+  SplitIdx s;
+  s.colpart = (int64_t)b * d.sb + (int64_t)(col / d.cs) * d.sC + (int64_t)(col % d.cs) * d.cstr;
+  s.rq = rbase / d.rs;
+  s.rr = rbase - s.rq * d.rs;
+  return s;
+}
+__device__ __forceinline__ int64_t split_at(const OutDesc& d, const SplitIdx& s, int drow) {
+  int rq = s.rq, rr = s.rr + drow;
+  while (rr >= d.rs) { rr -= d.rs; ++rq; }
+  return s.colpart + (int64_t)rq * d.sR + (int64_t)rr * d.rstr;
+}
+
+template <typename T, int BM, int BN, int WM, int WN, int EPI>
+__global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
+  constexpr int VEC = Mf<T>::VEC;
+  constexpr int BKE = ROW_BYTES / (int)sizeof(T);
+  constexpr int NWN = BN / WN;
+  constexpr int FM = WM / 32, FN = WN / 32;
+  constexpr int AV = BM * ROWV / THREADS;
+  constexpr int BV = BN * ROWV / THREADS;
+  constexpr int STAGE = (BM + BN) * LDS_ROW;
+  static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
+  static_assert(AV >= 1 && BV >= 1, "tile too small");
+
+  __shared__ __attribute__((aligned(16))) char smem[2 * STAGE];
+
+  const int b = blockIdx.z;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / NWN, wn = wave % NWN;
+  const T* __restrict__ A = (const T*)p.A + (int64_t)b * p.sAb;
+  const T* __restrict__ B = (const T*)p.B + (int64_t)b * p.sBb;
+  const int M = p.M, N = p.N, K = p.K;
+
+  // per-thread global source rows (clamped into range; results outside are not stored)
+  const T* arow[AV];
+  const T* brow[BV];
+#pragma unroll
+  for (int i = 0; i < AV; ++i) {
+    const int r = (tid + i * THREADS) / ROWV;
+    const int gr = min(m0 + r, M - 1);
+    arow[i] = A + (int64_t)gr * p.lda + ((tid + i * THREADS) % ROWV) * VEC;
+  }
+#pragma unroll
+  for (int i = 0; i < BV; ++i) {
+    const int r = (tid + i * THREADS) / ROWV;
+    const int gr = min(n0 + r, N - 1);
+    brow[i] = B + (int64_t)gr * p.ldb + ((tid + i * THREADS) % ROWV) * VEC;
+  }
+  const int kvec = (tid % ROWV) * VEC;  // same for every i since THREADS % ROWV == 0
+
+  u32x4 ra[AV], rb[BV];
+  auto gload = [&](int kt) {
+    const int k = kt * BKE + kvec;
+    const bool ok = k < K;
+#pragma unroll
+    for (int i = 0; i < AV; ++i) {
+      ra[i] = ok ? *(const u32x4*)(arow[i] + (int64_t)kt * BKE) : u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int i = 0; i < BV; ++i) {
+      rb[i] = ok ? *(const u32x4*)(brow[i] + (int64_t)kt * BKE) : u32x4{0u, 0u, 0u, 0u};
+    }
+  };
+  auto sstore = [&](int buf) {
+    char* base = smem + buf * STAGE;
+#pragma unroll
+    for (int i = 0; i < AV; ++i) {
+      const int v = tid + i * THREADS;
+      *(u32x4*)(base + (v / ROWV) * LDS_ROW + (v % ROWV) * 16) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < BV; ++i) {
+      const int v = tid + i * THREADS;
+      *(u32x4*)(base + (BM + v / ROWV) * LDS_ROW + (v % ROWV) * 16) = rb[i];
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
+
+  const int nk = (K + BKE - 1) / BKE;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+
+  const int frow = lane & 31;
+  const int fhalf = (lane >> 5) * 16;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+    const char* base = smem + buf * STAGE;
+#pragma unroll
+    for (int ks = 0; ks < ROW_BYTES / 32; ++ks) {
+      u32x4 fa[FM], fb[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        fa[i] = *(const u32x4*)(base + (wm * WM + i * 32 + frow) * LDS_ROW + ks * 32 + fhalf);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        fb[j] = *(const u32x4*)(base + (BM + wn * WN + j * 32 + frow) * LDS_ROW + ks * 32 + fhalf);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = Mf<T>::mma(fa[i], fb[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ------------------------------------------------------------------ epilogue
+  // Staged path: outputs without column split or second output go through LDS so
+  // that each output row segment is written by consecutive lanes (coalesced).
+  if (p.out0.cs == (1 << 30) && p.out0.cstr == 1 && (EPI == EPI_GRAD || (EPI == EPI_FWD && !p.out1.ptr))) {
+    typedef typename std::conditional<EPI == EPI_GRAD, float, T>::type O;
+    constexpr int SROW = BN + 16 / (int)sizeof(O);  // padded LDS row, in elements
+    O* slab = (O*)smem;                              // [NWM*32][SROW]
+    constexpr int NWM = BM / WM;
+    constexpr int SLAB_BYTES = NWM * 32 * SROW * (int)sizeof(O);
+    static_assert(SLAB_BYTES + NWM * 32 * 8 <= 2 * STAGE, "slab does not fit in LDS");
+    static_assert(THREADS % BN == 0, "copy loop assumes BN divides the workgroup");
+    int64_t* rowaddr = (int64_t*)(smem + SLAB_BYTES);
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      // each wave drops its 32-row block i into the slab
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int lc = wn * WN + j * 32 + (lane & 31);
+        const int col = n0 + lc;
+        float bias = 0.0f;
+        if (EPI == EPI_FWD && p.bias && col < N) bias = p.bias[(int64_t)b * p.sbias + col];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int lr = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+          float v = acc[i][j][q];
+          if (EPI == EPI_FWD) {
+            v += bias;
+            if (p.act >= 0) v = act_fwd(v, p.act);
+          }
+          slab[lr * SROW + lc] = cvt_out<O>(v);
+        }
+      }
+      if (tid < NWM * 32) {
+        const int row = m0 + (tid >> 5) * WM + i * 32 + (tid & 31);
+        const int rq = row / p.out0.rs, rr = row - rq * p.out0.rs;
+        rowaddr[tid] = row < M ? (int64_t)b * p.out0.sb + (int64_t)rq * p.out0.sR + (int64_t)rr * p.out0.rstr : -1;
+      }
+      __syncthreads();
+      // the whole workgroup copies the slab rows out, consecutive lanes on consecutive columns
+      const int lc = tid % BN;
+      const int col = n0 + lc;
+      if (col < N) {
+        for (int lr = tid / BN; lr < NWM * 32; lr += THREADS / BN) {
+          const int64_t ra = rowaddr[lr];
+          if (ra < 0) continue;
+          O* dst = (O*)p.out0.ptr + ra + col;
+          if (EPI == EPI_GRAD) {
+            const float v = cvt_in<O>(slab[lr * SROW + lc]);
+            *dst = p.beta ? *dst + v : v;
+          } else {
+            *dst = slab[lr * SROW + lc];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * WN + j * 32 + (lane & 31);
+      const int rbase = m0 + wm * WM + i * 32 + 4 * (lane >> 5);
+      if (col >= N) continue;
+      const SplitIdx s0 = split_base(p.out0, b, rbase, col);
+      SplitIdx s1 = s0, sa = s0;
+      if (EPI != EPI_GRAD && p.out1.ptr) s1 = split_base(p.out1, b, rbase, col);
+      if (EPI == EPI_DELTA) sa = split_base(p.aux, b, rbase, col);
+      float bias = 0.0f;
+      if (EPI == EPI_FWD && p.bias) bias = p.bias[(int64_t)b * p.sbias + col];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int dr = 8 * (q >> 2) + (q & 3);
+        if (rbase + dr >= M) continue;
+        float v = acc[i][j][q];
+        if (EPI == EPI_GRAD) {
+          float* g = (float*)p.out0.ptr + split_at(p.out0, s0, dr);
+          *g = p.beta ? *g + v : v;
+        } else {
+          if (EPI == EPI_FWD) {
+            v += bias;
+            if (p.act >= 0) v = act_fwd(v, p.act);
+          } else {
+            const float a = cvt_in<T>(*((const T*)p.aux.ptr + split_at(p.aux, sa, dr)));
+            v *= act_grad_from_out(a, p.act);
+          }
+          *((T*)p.out0.ptr + split_at(p.out0, s0, dr)) = cvt_out<T>(v);
+          if (p.out1.ptr) *((T*)p.out1.ptr + split_at(p.out1, s1, dr)) = cvt_out<T>(v);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int BM, int BN, int WM, int WN>
+hipError_t launch_cfg(const GemmParams& p, hipStream_t s) {
+  dim3 grid((p.N + BN - 1) / BN, (p.M + BM - 1) / BM, p.batch);
+  switch (p.epi) {
+    case EPI_FWD: hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI_FWD>), grid, dim3(THREADS), 0, s, p); break;
+    case EPI_GRAD: hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI_GRAD>), grid, dim3(THREADS), 0, s, p); break;
+    case EPI_DELTA: hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI_DELTA>), grid, dim3(THREADS), 0, s, p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t gemm_run(const GemmParams& p, int type, hipStream_t stream) {
+  if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return hipSuccess;
+  if (p.K <= 0) return hipErrorInvalidValue;
+  const int vec = type == GEMM_BF16 ? 8 : 4;
+  if (p.K % vec || p.lda % vec || p.ldb % vec) return hipErrorInvalidValue;
+  if (((uintptr_t)p.A | (uintptr_t)p.B) & 15) return hipErrorInvalidValue;
+  const bool big = (int64_t)p.M * p.N >= (int64_t)256 * 128 * 512;
+  if (type == GEMM_BF16) {
+    return big ? launch_cfg<__bf16, 256, 128, 128, 64>(p, stream) : launch_cfg<__bf16, 128, 128, 64, 64>(p, stream);
+  }
+  return big ? launch_cfg<float, 256, 128, 128, 64>(p, stream) : launch_cfg<float, 128, 128, 64, 64>(p, stream);
+}
+
+}  // namespace smc

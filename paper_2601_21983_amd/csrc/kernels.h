@@ -1,0 +1,145 @@
+// Launch interfaces of the SMC kernels (internal to libsmc).
+#pragma once
+
+#include "common.h"
+#include "gemm.h"
+
+namespace smc {
+
+constexpr int MAX_LAYERS = 8;
+constexpr int MAX_J = 4096;      // population size handled by the single-workgroup kernels
+constexpr int MOVE_ELEMS = 1024; // parameters per move workgroup (256 threads x 4)
+
+enum { HEAD_TRAIN = 0, HEAD_FORWARD = 1, HEAD_PREDICT = 2 };
+enum { MOVE_FIRST = 0, MOVE_MID = 1, MOVE_LAST = 2 };
+enum { TAG_MOMENTUM = 1, TAG_RESAMPLE_U = 2, TAG_PRIOR = 3 };
+
+struct HeadArgs {
+  const void* A = nullptr;          // activation (j, m, h) at A + j*sAj + m*sAm + h
+  int64_t sAj = 0, sAm = 0;
+  const float* theta = nullptr;     // master parameters [J x D]
+  int64_t D = 0, offL = 0;          // output-layer block offset
+  int H = 0, C = 0, J = 0;
+  int m_valid = 0;                  // valid samples of this chunk
+  int64_t c0 = 0;                   // first sample of this chunk (label index base)
+  int tiles_per_split = 1, nsplit = 1;
+  const int32_t* ylab = nullptr;
+  const float* yreal = nullptr;
+  int likelihood = 0;
+  float inv_var = 1.0f, gauss_c = 0.0f;
+  double lambda = 1.0;
+  const double* scale = nullptr;    // per-particle gradient scale (overrides lambda)
+  int act = 0;
+  void* dT = nullptr;               // delta_{L-1} transposed: dT + j*sdTj + h*sdTh + m
+  int64_t sdTj = 0, sdTh = 0;
+  void* dR = nullptr;               // optional row layout: dR + j*sdRj + m*sdRm + h
+  int64_t sdRj = 0, sdRm = 0;
+  double* llpart = nullptr;         // [J x nsplit]
+  float* dWpart = nullptr;          // [J x nsplit x C(H+1)]
+  double* ll_acc = nullptr;         // [J]
+  float* grad = nullptr;            // [J x D]
+  int beta = 0;                     // 0: overwrite totals, 1: accumulate (later chunks)
+  float* logp = nullptr;            // predict: logp[(j*ld_logp + c0 + m)*C + c]
+  int64_t ld_logp = 0;
+};
+
+size_t head_smem_bytes(int H, int C);
+int head_max_pairs();
+hipError_t head_run(const HeadArgs& a, int mode, int bf16, hipStream_t s);
+hipError_t head_set_smem_limits();
+
+// Network shape shared by the elementwise kernels.
+struct NetShape {
+  int L = 0;
+  int nin[MAX_LAYERS] = {0}, nout[MAX_LAYERS] = {0};
+  int64_t off[MAX_LAYERS + 1] = {0};  // parameter offsets of each layer block; off[L] = D
+  int ldw[MAX_LAYERS] = {0};          // padded row length of the GEMM weight copy
+  float rinv[MAX_LAYERS] = {0};       // 1 / (nin + 1)
+  void* w[MAX_LAYERS] = {nullptr};    // GEMM weight copy [J*nout x ldw] (operand type)
+  float* bias[MAX_LAYERS] = {nullptr};// [J*nout]
+  int64_t D = 0;
+  int J = 0;
+  int bf16 = 0;
+};
+
+struct MoveArgs {
+  NetShape net;
+  float* theta = nullptr;
+  float* P = nullptr;
+  const float* g = nullptr;      // gradient of the scaled log-likelihood (prior added here)
+  const float* noise = nullptr;  // injected standard normals [J x D] (FIRST), or null
+  double* part = nullptr;        // [3][J][nblk] per-workgroup sums: |xi|^2, |theta|^2, |P_end|^2
+  int nblk = 0;
+  int mode = MOVE_FIRST;
+  float h = 0.0f;
+  float inv_prior_var = 1.0f;
+  uint32_t key0 = 0, key1 = 0, ctr_iter = 0;
+  int cast = 1;                  // refresh the GEMM copy of theta
+};
+hipError_t move_run(const MoveArgs& a, hipStream_t s);
+
+// Build the GEMM copy of theta (and the bias copy) for every layer; with
+// `placement` only particles j with placement[j] != j are refreshed.
+hipError_t cast_run(const NetShape& net, const float* theta, const int32_t* placement, hipStream_t s);
+
+struct WeightArgs {
+  int J = 0;
+  int nblk = 0;
+  int init = 0;                  // initial weighting (Eq. init_weight)
+  double lambda = 1.0;
+  double inv_2prior_var = 0.5;
+  double ess_frac = 0.5;
+  const double* ll = nullptr;    // [J] subset log-likelihood at the new state
+  const double* part = nullptr;  // [3][J][nblk]
+  const double* extra = nullptr; // [J] extra log-weight term (learned proposal), or null
+  const double* tsq = nullptr;   // [J] |theta|^2 when part is null (initial weighting)
+  int no_kinetic = 0;            // ignore the momentum terms (learned move supplies `extra`)
+  double* lp = nullptr;          // [J] cached log pi (in: previous, out: new)
+  double* logw = nullptr;        // [J] normalised log-weights (in/out)
+  double* w = nullptr;           // [J] normalised weights (out)
+  double* stats = nullptr;       // [8] out
+};
+// stats layout
+enum { ST_ESS = 0, ST_LOGZ = 1, ST_MEANLL = 2, ST_MAXLL = 3, ST_NONFINITE = 4, ST_RECOMMEND = 5, ST_ALLBAD = 6,
+       ST_RESAMPLED = 7 };
+hipError_t weight_run(const WeightArgs& a, hipStream_t s);
+
+struct ResampleArgs {
+  int J = 0;
+  int mode = 0;                  // 0 if needed, 1 always, 2 never
+  double ess_frac = 0.5;
+  const double* u_dev = nullptr; // device scalar u (or null: draw with Philox)
+  uint32_t key0 = 0, key1 = 0, ctr_iter = 0;
+  double* w = nullptr;           // [J] normalised weights (in; reset to 1/J)
+  double* logw = nullptr;        // [J] (reset to -log J)
+  double* stats = nullptr;       // [8] (ESS read; ST_RESAMPLED written)
+  int32_t* ancestors = nullptr;  // [J] sorted ancestors (identity if not resampled)
+  int32_t* placement = nullptr;  // [J]
+  double* sc[4] = {nullptr, nullptr, nullptr, nullptr};  // per-particle scalars gathered in place
+};
+hipError_t resample_run(const ResampleArgs& a, hipStream_t s);
+hipError_t kernels_set_smem_limits();
+// gather rows of the [J x D] arrays in place according to placement
+hipError_t gather_rows_run(int J, int64_t D, const int32_t* placement, float* a0, float* a1, hipStream_t s);
+
+hipError_t normalise_run(const double* logw, int J, double* out, double* stats, hipStream_t s,
+                         double* wout = nullptr);
+hipError_t systematic_run(const double* w, int J, double u, int32_t* anc, int32_t* placement, hipStream_t s);
+hipError_t philox_run(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t* out,
+                      hipStream_t s);
+hipError_t prior_draw_run(float* theta, int J, int64_t D, float prior_std, uint32_t k0, uint32_t k1, hipStream_t s);
+
+hipError_t posterior_mean_run(const float* theta, const double* w, int J, int64_t D, double* out, hipStream_t s);
+
+// combine per-particle log-probabilities into the predictive mixture for samples [0, n)
+hipError_t predictive_run(const float* logp, int64_t ld_logp, const double* logw, int J, int C, int64_t n,
+                          const int32_t* y, float* probs, double* per_sample /*[n x 2]*/, hipStream_t s);
+hipError_t predictive_finish_run(const double* per_sample, int64_t n, double* out2, hipStream_t s);
+
+// fill helpers
+hipError_t fill_f64_run(double* p, int64_t n, double v, hipStream_t s);
+hipError_t grad_with_prior_run(const float* theta, const float* g, float* out, int64_t n, float inv_prior_var,
+                               hipStream_t s);
+hipError_t sq_norm_rows_run(const float* a, int J, int64_t D, double* out, hipStream_t s);
+
+}  // namespace smc

@@ -1,0 +1,1016 @@
+// C ABI of the MI355X data-annealed SMC sampler: handle, buffers and the
+// orchestration of one iteration on a single HIP stream.
+//
+// Device memory layout (all owned by the handle):
+//   X   [n_pad x ldx]      inputs in the GEMM operand type, rows in annealing order,
+//                          features padded with zeros to a multiple of 8
+//   XT  [(n_0+1) x n_pad]  the same inputs transposed, plus a row of ones so that
+//                          the weight-gradient GEMM of layer 1 also yields the bias
+//                          gradient (column n_0 of the augmented block [W | b])
+//   theta, g, P [J x D]    FP32 master parameters (one contiguous row per particle),
+//                          the lambda-scaled log-likelihood gradient (the prior term
+//                          is added where it is used) and momenta
+//   w_l  [J*n_l x ldw_l]   GEMM copy of each layer's weights (operand type), b_l [J*n_l]
+//   act_l [mc x J*n_l]     hidden activations of one chunk of samples, all particles'
+//                          units side by side ("concatenated" layout), so layer 1 is a
+//                          single dense GEMM over the J*n_1 columns
+//   dT_l [J*n_l x mc]      back-propagated errors, sample-contiguous (K-major for the
+//                          weight-gradient GEMM)
+// The subset [0, M_k) is processed in chunks of mc samples; activations live only
+// for one chunk, so the backward pass of a chunk always works from a freshly computed
+// forward pass (activation recomputation bounded by act_budget_bytes).
+#include "../../include/smc.h"
+#include "kernels.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace smc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Fail {
+  smc_status st;
+};
+
+void fail(smc_status st, const std::string& msg) {
+  g_last_error = msg;
+  throw Fail{st};
+}
+
+#define HIPCHECK(expr)                                                                                \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess)                                                                             \
+      fail(e_ == hipErrorOutOfMemory ? SMC_ERR_OOM : SMC_ERR_DEVICE,                                  \
+           std::string(#expr) + ": " + hipGetErrorString(e_) + " (" + __FILE__ + ":" + std::to_string(__LINE__) + ")"); \
+  } while (0)
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+template <typename T>
+T* dalloc(std::vector<void*>& owned, int64_t n) {
+  void* p = nullptr;
+  if (n <= 0) n = 1;
+  hipError_t e = hipMalloc(&p, (size_t)n * sizeof(T));
+  if (e != hipSuccess) fail(SMC_ERR_OOM, "hipMalloc of " + std::to_string((size_t)n * sizeof(T)) + " bytes failed");
+  owned.push_back(p);
+  return (T*)p;
+}
+
+// ------------------------------------------------------------------ data preparation kernels
+template <typename T>
+__global__ void pack_x_kernel(const float* x, int64_t n, int F, int ldx, int64_t n_pad, T* X) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad * ldx) return;
+  const int64_t r = i / ldx;
+  const int c = (int)(i - r * ldx);
+  const float v = (r < n && c < F) ? x[r * F + c] : 0.0f;
+  X[i] = cvt_out<T>(v);
+}
+
+template <typename T>
+__global__ void pack_xt_kernel(const float* x, int64_t n, int F, int64_t n_pad, T* XT) {
+  // XT[f][r] for f in [0, F], with row F all ones
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)(F + 1) * n_pad) return;
+  const int f = (int)(i / n_pad);
+  const int64_t r = i - (int64_t)f * n_pad;
+  float v;
+  if (f == F) v = 1.0f;
+  else v = r < n ? x[r * F + f] : 0.0f;
+  XT[i] = cvt_out<T>(v);
+}
+
+__global__ void pack_labels_kernel(const void* y, int64_t n, int64_t n_pad, int gaussian, int32_t* ylab,
+                                   float* yreal) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  if (gaussian) yreal[i] = i < n ? ((const float*)y)[i] : 0.0f;
+  else ylab[i] = i < n ? ((const int32_t*)y)[i] : 0;
+}
+
+template <typename T>
+__global__ void fill_ones_rows_kernel(T* a, int J, int H, int64_t ldm, int64_t ncols) {
+  // set row H of every particle's [(H+1) x ldm] block to ones
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)J * ncols) return;
+  const int j = (int)(i / ncols);
+  const int64_t c = i - (int64_t)j * ncols;
+  a[((int64_t)j * (H + 1) + H) * ldm + c] = cvt_out<T>(1.0f);
+}
+
+// W_l^T copy for layers >= 2: wT[j][i][o] = W_l[j][o][i], tiled through LDS
+template <typename T>
+__global__ void transpose_w_kernel(const float* theta, int64_t D, int64_t off, int nout, int nin, int ldwT, T* wT) {
+  __shared__ float tile[32][33];
+  const int j = blockIdx.z;
+  const int o0 = blockIdx.y * 32, i0 = blockIdx.x * 32;
+  const float* src = theta + (int64_t)j * D + off;
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const int o = o0 + r, i = i0 + threadIdx.x;
+    tile[r][threadIdx.x] = (o < nout && i < nin) ? src[(int64_t)o * (nin + 1) + i] : 0.0f;
+  }
+  __syncthreads();
+  T* dst = wT + (int64_t)j * nin * ldwT;
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const int i = i0 + r, o = o0 + threadIdx.x;
+    if (i < nin && o < nout) dst[(int64_t)i * ldwT + o] = cvt_out<T>(tile[threadIdx.x][r]);
+  }
+}
+
+struct LayerBufs {
+  void* act = nullptr;   // [mc x J*nout] (hidden layers)
+  void* actT = nullptr;  // [J x (nout+1) x mc] (hidden layers feeding another hidden layer)
+  void* dT = nullptr;    // [J*nout x mc]
+  void* dR = nullptr;    // [mc x J*nout] (hidden layers >= 2)
+  void* wT = nullptr;    // [J x nin x ldwT] (layers >= 2 that are not the output layer)
+  int ldwT = 0;
+};
+
+}  // namespace
+
+struct smc_handle {
+  smc_config cfg{};
+  hipStream_t stream = nullptr;
+  std::vector<void*> owned;
+  int J = 0, L = 0, F = 0, C = 0, bf16 = 0;
+  int64_t D = 0;
+  int64_t n_data = 0, n_pad = 0;
+  int ldx = 0;
+  size_t esz = 4;  // operand element size
+  NetShape net;
+  LayerBufs lb[MAX_LAYERS];
+  void* X = nullptr;
+  void* XT = nullptr;
+  int32_t* ylab = nullptr;
+  float* yreal = nullptr;
+  float *theta = nullptr, *g = nullptr, *P = nullptr;
+  double *ll = nullptr, *lp = nullptr, *logw = nullptr, *w = nullptr, *stats = nullptr, *part = nullptr;
+  double* tsq = nullptr;
+  double* extra = nullptr;
+  int32_t *anc = nullptr, *place = nullptr;
+  int nblk = 0;
+  int64_t mc = 0;
+  int nsplit_max = 0;
+  double* llpart = nullptr;
+  float* dWpart = nullptr;
+  float* noise = nullptr;
+  bool noise_pending = false;
+  bool w_dirty = true;
+  int64_t m = 0;
+  double lam = 1.0;
+  uint64_t rng_iter = 0;
+  int64_t grad_evals = 0;
+  // learned proposal
+  float* pnet = nullptr;
+  int pnet_n = 0;
+  double h0 = 0.0;
+  int G = 0;
+  // posterior predictive scratch (grown on demand)
+  void* tx = nullptr;
+  int64_t tx_rows = 0;
+  float* logp = nullptr;
+  int64_t logp_n = 0;
+  double* per_sample = nullptr;
+  double* pred_out = nullptr;
+};
+
+namespace {
+
+void sync(smc_t h) { HIPCHECK(hipStreamSynchronize(h->stream)); }
+
+uint32_t key0(smc_t h) { return (uint32_t)(h->cfg.seed & 0xffffffffu); }
+uint32_t key1(smc_t h) { return (uint32_t)(h->cfg.seed >> 32); }
+
+void check_config(const smc_config* c) {
+  if (!c) fail(SMC_ERR_ARG, "null config");
+  if (c->n_particles < 1 || c->n_particles > MAX_J)
+    fail(SMC_ERR_ARG, "n_particles must be in [1, " + std::to_string(MAX_J) + "]");
+  if (c->n_layers < 1 || c->n_layers > SMC_MAX_LAYERS) fail(SMC_ERR_ARG, "n_layers must be in [1, 8]");
+  for (int l = 0; l <= c->n_layers; ++l)
+    if (c->widths[l] < 1) fail(SMC_ERR_ARG, "every width must be >= 1");
+  if (c->model_kind != SMC_MODEL_MLP) fail(SMC_ERR_UNSUPPORTED, "model_kind: only SMC_MODEL_MLP through smc_init");
+  if (c->activation != SMC_ACT_TANH && c->activation != SMC_ACT_RELU) fail(SMC_ERR_ARG, "activation");
+  if (c->likelihood == SMC_LIK_CATEGORICAL) {
+    if (c->widths[c->n_layers] < 2 || c->widths[c->n_layers] > 16)
+      fail(SMC_ERR_UNSUPPORTED, "categorical likelihood needs 2..16 classes");
+  } else if (c->likelihood == SMC_LIK_GAUSSIAN) {
+    if (c->widths[c->n_layers] != 1) fail(SMC_ERR_ARG, "Gaussian likelihood needs one output");
+    if (!(c->noise_std > 0)) fail(SMC_ERR_ARG, "noise_std must be > 0");
+  } else {
+    fail(SMC_ERR_ARG, "likelihood");
+  }
+  if (c->precision != SMC_PREC_FP32 && c->precision != SMC_PREC_BF16) fail(SMC_ERR_ARG, "precision");
+  if (c->proposal != SMC_PROPOSAL_FIXED && c->proposal != SMC_PROPOSAL_LEARNED) fail(SMC_ERR_ARG, "proposal");
+  if (c->proposal == SMC_PROPOSAL_LEARNED && c->leapfrog_steps != 1)
+    fail(SMC_ERR_UNSUPPORTED, "the learned proposal is a Langevin (S = 1) move");
+  if (c->leapfrog_steps < 1) fail(SMC_ERR_ARG, "leapfrog_steps must be >= 1");
+  if (!(c->step_size >= 0) || !isfinite(c->step_size)) fail(SMC_ERR_ARG, "step_size must be finite and >= 0");
+  if (!(c->prior_std > 0)) fail(SMC_ERR_ARG, "prior_std must be > 0");
+  if (!(c->ess_frac >= 0 && c->ess_frac <= 1)) fail(SMC_ERR_ARG, "ess_frac must be in [0, 1]");
+  if (c->act_budget_bytes < 0) fail(SMC_ERR_ARG, "act_budget_bytes must be >= 0");
+  // hidden layers that feed another GEMM layer use 16-byte aligned per-particle rows
+  if (c->n_layers >= 3)
+    for (int l = 1; l < c->n_layers; ++l)
+      if (c->widths[l] % 8) fail(SMC_ERR_UNSUPPORTED, "with two or more hidden layers every hidden width must be a multiple of 8");
+  const int H = c->widths[c->n_layers - 1], C = c->widths[c->n_layers];
+  if ((size_t)head_smem_bytes(H, C) > 160 * 1024 || C * (H + 1) > head_max_pairs())
+    fail(SMC_ERR_UNSUPPORTED, "last hidden layer too wide for the output-layer kernel");
+}
+
+void setup_shapes(smc_t h) {
+  const smc_config& c = h->cfg;
+  h->J = c.n_particles;
+  h->L = c.n_layers;
+  h->F = c.widths[0];
+  h->C = c.widths[c.n_layers];
+  h->bf16 = c.precision == SMC_PREC_BF16;
+  h->esz = h->bf16 ? 2 : 4;
+  NetShape& n = h->net;
+  n.L = h->L;
+  n.J = h->J;
+  n.bf16 = h->bf16;
+  int64_t off = 0;
+  for (int l = 0; l < h->L; ++l) {
+    n.nin[l] = c.widths[l];
+    n.nout[l] = c.widths[l + 1];
+    n.off[l] = off;
+    n.ldw[l] = (int)round_up(n.nin[l], 8);
+    n.rinv[l] = 1.0f / (float)(n.nin[l] + 1);
+    off += (int64_t)n.nout[l] * (n.nin[l] + 1);
+  }
+  n.off[h->L] = off;
+  n.D = off;
+  h->D = off;
+  if (h->D > (1 << 24)) fail(SMC_ERR_UNSUPPORTED, "more than 2^24 parameters per particle");
+  h->ldx = (int)round_up(h->F, 8);
+  h->nblk = (int)((h->D + MOVE_ELEMS - 1) / MOVE_ELEMS);
+}
+
+// samples per chunk from the activation budget
+int64_t choose_chunk(smc_t h) {
+  int64_t budget = h->cfg.act_budget_bytes > 0 ? h->cfg.act_budget_bytes : ((int64_t)8 << 30);
+  int64_t per_sample = 0;  // bytes of activation buffers per sample
+  for (int l = 0; l < h->L - 1; ++l) {
+    const int64_t u = (int64_t)h->J * h->net.nout[l];
+    per_sample += u * h->esz * 2;                                  // act + dT
+    if (l >= 1) per_sample += u * h->esz;                          // dR
+    if (l + 1 < h->L - 1) per_sample += (int64_t)h->J * (h->net.nout[l] + 1) * h->esz;  // actT
+  }
+  if (per_sample == 0) per_sample = 1;
+  int64_t mc = budget / per_sample;
+  mc = mc / 256 * 256;
+  if (mc < 256) mc = 256;
+  const int64_t cap = round_up(h->n_data, 256);
+  return std::min(mc, cap);
+}
+
+void alloc_all(smc_t h) {
+  const int J = h->J;
+  const int64_t D = h->D;
+  h->n_pad = round_up(h->n_data, 256);
+  h->X = dalloc<char>(h->owned, h->n_pad * h->ldx * (int64_t)h->esz);
+  h->XT = dalloc<char>(h->owned, (int64_t)(h->F + 1) * h->n_pad * (int64_t)h->esz);
+  if (h->cfg.likelihood == SMC_LIK_GAUSSIAN) h->yreal = dalloc<float>(h->owned, h->n_pad);
+  else h->ylab = dalloc<int32_t>(h->owned, h->n_pad);
+  h->theta = dalloc<float>(h->owned, (int64_t)J * D);
+  h->g = dalloc<float>(h->owned, (int64_t)J * D);
+  h->P = dalloc<float>(h->owned, (int64_t)J * D);
+  h->ll = dalloc<double>(h->owned, J);
+  h->lp = dalloc<double>(h->owned, J);
+  h->logw = dalloc<double>(h->owned, J);
+  h->w = dalloc<double>(h->owned, J);
+  h->tsq = dalloc<double>(h->owned, J);
+  h->extra = dalloc<double>(h->owned, J);
+  h->stats = dalloc<double>(h->owned, 16);
+  h->part = dalloc<double>(h->owned, (int64_t)3 * J * h->nblk);
+  h->anc = dalloc<int32_t>(h->owned, J);
+  h->place = dalloc<int32_t>(h->owned, J);
+  HIPCHECK(hipMemsetAsync(h->stats, 0, 16 * sizeof(double), h->stream));
+  HIPCHECK(hipMemsetAsync(h->part, 0, (size_t)3 * J * h->nblk * sizeof(double), h->stream));
+  for (int l = 0; l < h->L; ++l) {
+    const int64_t n = (int64_t)J * h->net.nout[l] * h->net.ldw[l] * (int64_t)h->esz;
+    h->net.w[l] = dalloc<char>(h->owned, n);
+    HIPCHECK(hipMemsetAsync(h->net.w[l], 0, (size_t)n, h->stream));  // row padding stays zero
+    h->net.bias[l] = dalloc<float>(h->owned, (int64_t)J * h->net.nout[l]);
+  }
+  h->mc = choose_chunk(h);
+  const int64_t mc = h->mc;
+  for (int l = 0; l < h->L - 1; ++l) {
+    const int64_t u = (int64_t)J * h->net.nout[l];
+    LayerBufs& b = h->lb[l];
+    b.act = dalloc<char>(h->owned, mc * u * (int64_t)h->esz);
+    b.dT = dalloc<char>(h->owned, mc * u * (int64_t)h->esz);
+    if (l >= 1) b.dR = dalloc<char>(h->owned, mc * u * (int64_t)h->esz);
+    if (l + 1 < h->L - 1) {
+      const int64_t nc = (int64_t)J * (h->net.nout[l] + 1);
+      b.actT = dalloc<char>(h->owned, nc * mc * (int64_t)h->esz);
+      const int64_t tot = (int64_t)J * mc;
+      if (h->bf16)
+        hipLaunchKernelGGL(fill_ones_rows_kernel<__bf16>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h->stream,
+                           (__bf16*)b.actT, J, h->net.nout[l], mc, mc);
+      else
+        hipLaunchKernelGGL(fill_ones_rows_kernel<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h->stream,
+                           (float*)b.actT, J, h->net.nout[l], mc, mc);
+      HIPCHECK(hipGetLastError());
+    }
+  }
+  for (int l = 1; l < h->L - 1; ++l) {
+    LayerBufs& b = h->lb[l];
+    b.ldwT = (int)round_up(h->net.nout[l], 8);
+    const int64_t n = (int64_t)J * h->net.nin[l] * b.ldwT * (int64_t)h->esz;
+    b.wT = dalloc<char>(h->owned, n);
+    HIPCHECK(hipMemsetAsync(b.wT, 0, (size_t)n, h->stream));
+  }
+  const int ntiles = (int)(mc / 64);
+  h->nsplit_max = std::max(1, std::min(ntiles, (2048 + J - 1) / J));
+  const int H = h->net.nin[h->L - 1];
+  h->llpart = dalloc<double>(h->owned, (int64_t)J * h->nsplit_max);
+  h->dWpart = dalloc<float>(h->owned, (int64_t)J * h->nsplit_max * h->C * (H + 1));
+}
+
+void upload_data(smc_t h, const float* x, const void* y) {
+  const int64_t nx = h->n_pad * h->ldx;
+  const int64_t nt = (int64_t)(h->F + 1) * h->n_pad;
+  if (h->bf16) {
+    hipLaunchKernelGGL(pack_x_kernel<__bf16>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream, x,
+                       h->n_data, h->F, h->ldx, h->n_pad, (__bf16*)h->X);
+    hipLaunchKernelGGL(pack_xt_kernel<__bf16>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, h->stream, x,
+                       h->n_data, h->F, h->n_pad, (__bf16*)h->XT);
+  } else {
+    hipLaunchKernelGGL(pack_x_kernel<float>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream, x,
+                       h->n_data, h->F, h->ldx, h->n_pad, (float*)h->X);
+    hipLaunchKernelGGL(pack_xt_kernel<float>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, h->stream, x,
+                       h->n_data, h->F, h->n_pad, (float*)h->XT);
+  }
+  HIPCHECK(hipGetLastError());
+  hipLaunchKernelGGL(pack_labels_kernel, dim3((unsigned)((h->n_pad + 255) / 256)), dim3(256), 0, h->stream, y,
+                     h->n_data, h->n_pad, h->cfg.likelihood == SMC_LIK_GAUSSIAN ? 1 : 0, h->ylab, h->yreal);
+  HIPCHECK(hipGetLastError());
+}
+
+void transpose_weights(smc_t h, const float* theta) {
+  for (int l = 1; l < h->L - 1; ++l) {
+    const LayerBufs& b = h->lb[l];
+    const int nout = h->net.nout[l], nin = h->net.nin[l];
+    dim3 grid((nin + 31) / 32, (nout + 31) / 32, h->J);
+    if (h->bf16)
+      hipLaunchKernelGGL(transpose_w_kernel<__bf16>, grid, dim3(32, 8), 0, h->stream, theta, h->D, h->net.off[l], nout,
+                         nin, b.ldwT, (__bf16*)b.wT);
+    else
+      hipLaunchKernelGGL(transpose_w_kernel<float>, grid, dim3(32, 8), 0, h->stream, theta, h->D, h->net.off[l], nout,
+                         nin, b.ldwT, (float*)b.wT);
+    HIPCHECK(hipGetLastError());
+  }
+}
+
+void gemm(smc_t h, const GemmParams& p) {
+  const hipError_t e = gemm_run(p, h->bf16 ? GEMM_BF16 : GEMM_F32, h->stream);
+  if (e != hipSuccess) fail(SMC_ERR_DEVICE, std::string("GEMM launch failed: ") + hipGetErrorString(e));
+}
+
+// Forward through the hidden layers for samples [c0, c0 + rows) of the operand X
+// (ldx-strided rows).  Writes act_l (and actT_l when a hidden layer follows).
+void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows) {
+  const int J = h->J;
+  for (int l = 0; l < h->L - 1; ++l) {
+    const int nout = h->net.nout[l];
+    const int64_t U = (int64_t)J * nout;
+    GemmParams p;
+    p.epi = EPI_FWD;
+    p.act = h->cfg.activation;
+    p.M = rows;
+    p.K = h->net.ldw[l];
+    if (l == 0) {
+      // one dense GEMM over the concatenation of all particles' units
+      p.A = (const char*)Xop + c0 * h->ldx * (int64_t)h->esz;
+      p.lda = h->ldx;
+      p.B = h->net.w[0];
+      p.ldb = h->net.ldw[0];
+      p.N = (int)U;
+      p.batch = 1;
+      p.bias = h->net.bias[0];
+      p.out0.ptr = h->lb[0].act;
+      p.out0.rstr = U;
+      if (h->lb[0].actT) {
+        p.out1.ptr = h->lb[0].actT;
+        p.out1.cs = nout;
+        p.out1.sC = (int64_t)(nout + 1) * h->mc;
+        p.out1.cstr = h->mc;
+        p.out1.rstr = 1;
+      }
+    } else {
+      // batched over particles: A_{l-1}[j] is a column block of the concatenated layout
+      const int nin = h->net.nin[l];
+      p.A = h->lb[l - 1].act;
+      p.lda = (int64_t)J * nin;
+      p.sAb = nin;
+      p.B = h->net.w[l];
+      p.ldb = h->net.ldw[l];
+      p.sBb = (int64_t)nout * h->net.ldw[l];
+      p.K = nin;
+      p.N = nout;
+      p.batch = J;
+      p.bias = h->net.bias[l];
+      p.sbias = nout;
+      p.out0.ptr = h->lb[l].act;
+      p.out0.sb = nout;
+      p.out0.rstr = U;
+      if (h->lb[l].actT) {
+        p.out1.ptr = h->lb[l].actT;
+        p.out1.sb = (int64_t)(nout + 1) * h->mc;
+        p.out1.cstr = h->mc;
+        p.out1.rstr = 1;
+      }
+    }
+    gemm(h, p);
+  }
+}
+
+HeadArgs head_args(smc_t h, const float* theta) {
+  HeadArgs a;
+  const int L = h->L;
+  a.theta = theta;
+  a.D = h->D;
+  a.offL = h->net.off[L - 1];
+  a.H = h->net.nin[L - 1];
+  a.C = h->C;
+  a.J = h->J;
+  a.likelihood = h->cfg.likelihood == SMC_LIK_GAUSSIAN ? 1 : 0;
+  const double s = h->cfg.noise_std;
+  a.inv_var = (float)(1.0 / (s * s));
+  a.gauss_c = (float)(-0.5 * log(2.0 * M_PI * s * s));
+  a.ylab = h->ylab;
+  a.yreal = h->yreal;
+  a.act = h->cfg.activation;
+  if (L >= 2) {
+    a.A = h->lb[L - 2].act;
+    a.sAj = a.H;
+    a.sAm = (int64_t)h->J * a.H;
+  } else {
+    a.A = h->X;
+    a.sAj = 0;
+    a.sAm = h->ldx;
+  }
+  a.llpart = h->llpart;
+  a.dWpart = h->dWpart;
+  return a;
+}
+
+void set_splits(smc_t h, HeadArgs& a, int m_valid) {
+  const int ntiles = (m_valid + 63) / 64;
+  int ns = std::max(1, std::min(h->nsplit_max, ntiles));
+  a.tiles_per_split = (ntiles + ns - 1) / ns;
+  a.nsplit = (ntiles + a.tiles_per_split - 1) / a.tiles_per_split;
+}
+
+// One pass over the subset [0, m): log-likelihoods ll_out[j] (FP64) and, when
+// g_out is given, g_out[j] = scale_j * d LL_j / d theta_j (the lambda-scaled
+// likelihood gradient).  The GEMM copies of `theta` must be current.
+void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const double* scale, double* ll_out,
+               float* g_out) {
+  const int J = h->J, L = h->L;
+  const bool train = g_out != nullptr;
+  if (train && L >= 3) transpose_weights(h, theta);
+  for (int64_t c0 = 0; c0 < m; c0 += h->mc) {
+    const int mcv = (int)std::min<int64_t>(h->mc, m - c0);
+    const int rows = (int)round_up(mcv, 64);
+    const int beta = c0 > 0 ? 1 : 0;
+    forward_hidden(h, h->X, c0, rows);
+    HeadArgs a = head_args(h, theta);
+    if (L == 1) a.A = (const char*)h->X + c0 * h->ldx * (int64_t)h->esz;
+    a.m_valid = mcv;
+    a.c0 = c0;
+    a.lambda = lambda;
+    a.scale = scale;
+    a.ll_acc = ll_out;
+    a.grad = g_out;
+    a.beta = beta;
+    set_splits(h, a, mcv);
+    if (train && L >= 2) {
+      a.dT = h->lb[L - 2].dT;
+      a.sdTj = (int64_t)a.H * h->mc;
+      a.sdTh = h->mc;
+      if (h->lb[L - 2].dR) {
+        a.dR = h->lb[L - 2].dR;
+        a.sdRj = a.H;
+        a.sdRm = (int64_t)J * a.H;
+      }
+    }
+    HIPCHECK(head_run(a, train ? HEAD_TRAIN : HEAD_FORWARD, h->bf16, h->stream));
+    if (!train) continue;
+    // backward through the hidden layers, top down
+    for (int l = L - 2; l >= 0; --l) {
+      const int nout = h->net.nout[l], nin = h->net.nin[l];
+      {
+        // weight gradient [W_l | b_l] = delta_l^T [a_{l-1}, 1]
+        GemmParams p;
+        p.epi = EPI_GRAD;
+        p.beta = beta;
+        p.K = rows;
+        p.A = h->lb[l].dT;
+        p.lda = h->mc;
+        if (l == 0) {
+          p.M = J * nout;
+          p.N = nin + 1;
+          p.B = (const char*)h->XT + c0 * (int64_t)h->esz;
+          p.ldb = h->n_pad;
+          p.batch = 1;
+          p.out0.ptr = g_out;
+          p.out0.rs = nout;
+          p.out0.sR = h->D;
+          p.out0.rstr = nin + 1;
+        } else {
+          p.M = nout;
+          p.N = nin + 1;
+          p.sAb = (int64_t)nout * h->mc;
+          p.B = h->lb[l - 1].actT;
+          p.ldb = h->mc;
+          p.sBb = (int64_t)(nin + 1) * h->mc;
+          p.batch = J;
+          p.out0.ptr = g_out + h->net.off[l];
+          p.out0.sb = h->D;
+          p.out0.rstr = nin + 1;
+        }
+        gemm(h, p);
+      }
+      if (l >= 1) {
+        // error of the layer below: (delta_l W_l) * act'(a_{l-1}), written sample-contiguous
+        GemmParams p;
+        p.epi = EPI_DELTA;
+        p.act = h->cfg.activation;
+        p.M = rows;
+        p.N = nin;
+        p.K = nout;
+        p.A = h->lb[l].dR;
+        p.lda = (int64_t)J * nout;
+        p.sAb = nout;
+        p.B = h->lb[l].wT;
+        p.ldb = h->lb[l].ldwT;
+        p.sBb = (int64_t)nin * h->lb[l].ldwT;
+        p.batch = J;
+        p.aux.ptr = h->lb[l - 1].act;
+        p.aux.sb = nin;
+        p.aux.rstr = (int64_t)J * nin;
+        p.out0.ptr = h->lb[l - 1].dT;
+        p.out0.sb = (int64_t)nin * h->mc;
+        p.out0.cstr = h->mc;
+        p.out0.rstr = 1;
+        if (h->lb[l - 1].dR) {
+          p.out1.ptr = h->lb[l - 1].dR;
+          p.out1.sb = nin;
+          p.out1.rstr = (int64_t)J * nin;
+        }
+        gemm(h, p);
+      }
+    }
+  }
+  if (train) h->grad_evals += (int64_t)J * m;
+}
+
+void ensure_cast(smc_t h) {
+  if (!h->w_dirty) return;
+  HIPCHECK(cast_run(h->net, h->theta, nullptr, h->stream));
+  h->w_dirty = false;
+}
+
+void read_stats(smc_t h, double* st) {
+  HIPCHECK(hipMemcpyAsync(st, h->stats, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  sync(h);
+}
+
+void fill_info(smc_t h, smc_step_info* info, int64_t evals) {
+  double st[8];
+  read_stats(h, st);
+  if (info) {
+    info->ess = st[ST_ESS];
+    info->log_z_increment = st[ST_LOGZ];
+    info->mean_loglik = st[ST_MEANLL];
+    info->max_loglik = st[ST_MAXLL];
+    info->n_nonfinite = (int32_t)st[ST_NONFINITE];
+    info->resample_recommended = (int32_t)st[ST_RECOMMEND];
+    info->grad_evals = evals;
+  }
+  if (st[ST_ALLBAD] != 0.0) fail(SMC_ERR_NONFINITE, "every particle has a non-finite log-weight");
+}
+
+// initial weighting at the current subset: log w = lambda LL (Eq. init_weight)
+void initial_weighting(smc_t h) {
+  HIPCHECK(sq_norm_rows_run(h->theta, h->J, h->D, h->tsq, h->stream));
+  WeightArgs wa;
+  wa.J = h->J;
+  wa.init = 1;
+  wa.lambda = h->lam;
+  wa.inv_2prior_var = 0.5 / (h->cfg.prior_std * h->cfg.prior_std);
+  wa.ess_frac = h->cfg.ess_frac;
+  wa.ll = h->ll;
+  wa.tsq = h->tsq;
+  wa.lp = h->lp;
+  wa.logw = h->logw;
+  wa.w = h->w;
+  wa.stats = h->stats;
+  HIPCHECK(weight_run(wa, h->stream));
+}
+
+MoveArgs move_args(smc_t h, int mode) {
+  MoveArgs a;
+  a.net = h->net;
+  a.theta = h->theta;
+  a.P = h->P;
+  a.g = h->g;
+  a.part = h->part;
+  a.nblk = h->nblk;
+  a.mode = mode;
+  a.h = (float)h->cfg.step_size;
+  a.inv_prior_var = (float)(1.0 / (h->cfg.prior_std * h->cfg.prior_std));
+  a.key0 = key0(h);
+  a.key1 = key1(h);
+  a.ctr_iter = (uint32_t)h->rng_iter;
+  a.cast = 1;
+  return a;
+}
+
+smc_status guard(void (*body)(void*), void* ctx) {
+  try {
+    g_last_error.clear();
+    body(ctx);
+    return SMC_OK;
+  } catch (const Fail& f) {
+    return f.st;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return SMC_ERR_OOM;
+  } catch (...) {
+    g_last_error = "unexpected C++ exception";
+    return SMC_ERR_DEVICE;
+  }
+}
+
+template <typename F>
+smc_status run(F&& f) {
+  auto thunk = [](void* c) { (*(F*)c)(); };
+  return guard(thunk, (void*)&f);
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+extern "C" {
+
+const char* smc_status_string(smc_status s) {
+  switch (s) {
+    case SMC_OK: return "ok";
+    case SMC_ERR_ARG: return "invalid argument";
+    case SMC_ERR_OOM: return "out of device memory";
+    case SMC_ERR_DEVICE: return "HIP device error";
+    case SMC_ERR_STATE: return "invalid call for the handle's state";
+    case SMC_ERR_NONFINITE: return "every particle has a non-finite log-weight";
+    case SMC_ERR_UNSUPPORTED: return "unsupported configuration";
+    case SMC_ERR_NOLIB: return "library not loaded";
+  }
+  return "unknown status";
+}
+
+const char* smc_last_error(void) { return g_last_error.c_str(); }
+
+smc_status smc_init(const smc_config* cfg, const float* x_dev, const void* y_dev, int64_t n_data,
+                    const float* theta0_dev, int64_t m0, double lambda0, void* hip_stream, smc_t* out) {
+  smc_t h = nullptr;
+  const smc_status st = run([&]() {
+    if (!out) fail(SMC_ERR_ARG, "out is null");
+    *out = nullptr;
+    check_config(cfg);
+    if (!x_dev || !y_dev) fail(SMC_ERR_ARG, "x_dev and y_dev are required");
+    if (n_data < 1 || n_data > (int64_t)1 << 30) fail(SMC_ERR_ARG, "n_data out of range");
+    if (m0 < 1 || m0 > n_data) fail(SMC_ERR_ARG, "m0 must be in [1, n_data]");
+    if (!(lambda0 > 0) || !isfinite(lambda0)) fail(SMC_ERR_ARG, "lambda0 must be finite and > 0");
+    h = new smc_handle();
+    h->cfg = *cfg;
+    h->stream = (hipStream_t)hip_stream;
+    h->n_data = n_data;
+    setup_shapes(h);
+    HIPCHECK(head_set_smem_limits());
+    HIPCHECK(kernels_set_smem_limits());
+    alloc_all(h);
+    upload_data(h, x_dev, y_dev);
+    if (theta0_dev)
+      HIPCHECK(hipMemcpyAsync(h->theta, theta0_dev, (size_t)h->J * h->D * 4, hipMemcpyDeviceToDevice, h->stream));
+    else
+      HIPCHECK(prior_draw_run(h->theta, h->J, h->D, (float)cfg->prior_std, key0(h), key1(h), h->stream));
+    h->w_dirty = true;
+    ensure_cast(h);
+    h->m = m0;
+    h->lam = lambda0;
+    grad_pass(h, h->theta, m0, lambda0, nullptr, h->ll, h->g);
+    initial_weighting(h);
+    double st8[8];
+    read_stats(h, st8);
+    if (st8[ST_ALLBAD] != 0.0) fail(SMC_ERR_NONFINITE, "every particle has a non-finite initial log-weight");
+    *out = h;
+  });
+  if (st != SMC_OK && h) {
+    (void)hipStreamSynchronize(h->stream);
+    for (void* p : h->owned) (void)hipFree(p);
+    delete h;
+  }
+  return st;
+}
+
+void smc_destroy(smc_t h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (void* p : h->owned) (void)hipFree(p);
+  if (h->tx) (void)hipFree(h->tx);
+  if (h->logp) (void)hipFree(h->logp);
+  if (h->per_sample) (void)hipFree(h->per_sample);
+  delete h;
+}
+
+int64_t smc_n_params(smc_t h) { return h ? h->D : -1; }
+int64_t smc_chunk_samples(smc_t h) { return h ? h->mc : -1; }
+
+smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info) {
+  return run([&]() {
+    if (!h) fail(SMC_ERR_ARG, "null handle");
+    if (m_k < h->m || m_k > h->n_data) fail(SMC_ERR_ARG, "m_k must satisfy previous m <= m_k <= n_data");
+    if (!(lambda_k > 0) || !isfinite(lambda_k)) fail(SMC_ERR_ARG, "lambda_k must be finite and > 0");
+    if (h->cfg.proposal == SMC_PROPOSAL_LEARNED && !h->pnet) fail(SMC_ERR_STATE, "no proposal network set");
+    const int64_t ev0 = h->grad_evals;
+    ensure_cast(h);
+    if (m_k != h->m || lambda_k != h->lam) {
+      // the target changed: gradient at the current particles on the new subset
+      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g);
+      h->m = m_k;
+      h->lam = lambda_k;
+    }
+    h->rng_iter += 1;
+    const int S = h->cfg.leapfrog_steps;
+    MoveArgs ma = move_args(h, MOVE_FIRST);
+    if (h->noise_pending) ma.noise = h->noise;
+    HIPCHECK(move_run(ma, h->stream));
+    h->noise_pending = false;
+    for (int s = 1; s <= S; ++s) {
+      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g);
+      MoveArgs mb = move_args(h, s < S ? MOVE_MID : MOVE_LAST);
+      HIPCHECK(move_run(mb, h->stream));
+    }
+    WeightArgs wa;
+    wa.J = h->J;
+    wa.nblk = h->nblk;
+    wa.lambda = lambda_k;
+    wa.inv_2prior_var = 0.5 / (h->cfg.prior_std * h->cfg.prior_std);
+    wa.ess_frac = h->cfg.ess_frac;
+    wa.ll = h->ll;
+    wa.part = h->part;
+    wa.lp = h->lp;
+    wa.logw = h->logw;
+    wa.w = h->w;
+    wa.stats = h->stats;
+    HIPCHECK(weight_run(wa, h->stream));
+    if (info) fill_info(h, info, h->grad_evals - ev0);
+  });
+}
+
+smc_status smc_resample(smc_t h, int32_t mode, const double* u, int32_t* resampled, int32_t* ancestors_host) {
+  return run([&]() {
+    if (!h) fail(SMC_ERR_ARG, "null handle");
+    if (mode < 0 || mode > 2) fail(SMC_ERR_ARG, "mode");
+    if (u && !(*u >= 0.0 && *u < 1.0)) fail(SMC_ERR_ARG, "u must be in [0, 1)");
+    ResampleArgs ra;
+    ra.J = h->J;
+    ra.mode = mode;
+    ra.ess_frac = h->cfg.ess_frac;
+    double* u_dev = nullptr;
+    if (u) {
+      u_dev = h->stats + 8;  // device scalar slot
+      HIPCHECK(hipMemcpyAsync(u_dev, u, sizeof(double), hipMemcpyHostToDevice, h->stream));
+      sync(h);  // the host value may go out of scope
+    }
+    ra.u_dev = u_dev;
+    ra.key0 = key0(h);
+    ra.key1 = key1(h);
+    ra.ctr_iter = (uint32_t)h->rng_iter;
+    ra.w = h->w;
+    ra.logw = h->logw;
+    ra.stats = h->stats;
+    ra.ancestors = h->anc;
+    ra.placement = h->place;
+    ra.sc[0] = h->ll;
+    ra.sc[1] = h->lp;
+    HIPCHECK(resample_run(ra, h->stream));
+    HIPCHECK(gather_rows_run(h->J, h->D, h->place, h->theta, h->g, h->stream));
+    if (!h->w_dirty) HIPCHECK(cast_run(h->net, h->theta, h->place, h->stream));
+    if (resampled || ancestors_host) {
+      double st[8];
+      read_stats(h, st);
+      if (resampled) *resampled = st[ST_RESAMPLED] != 0.0 ? 1 : 0;
+      if (ancestors_host) {
+        HIPCHECK(hipMemcpyAsync(ancestors_host, h->anc, (size_t)h->J * 4, hipMemcpyDeviceToHost, h->stream));
+        sync(h);
+      }
+    }
+  });
+}
+
+smc_status smc_posterior_predict(smc_t h, const float* x_dev, const int32_t* y_dev, int64_t n, float* probs_dev,
+                                 double* accuracy, double* mean_log_pred) {
+  return run([&]() {
+    if (!h) fail(SMC_ERR_ARG, "null handle");
+    if (!x_dev || n < 1) fail(SMC_ERR_ARG, "x_dev and n >= 1 are required");
+    if ((accuracy || mean_log_pred) && !y_dev) fail(SMC_ERR_ARG, "accuracy needs labels");
+    if (h->cfg.likelihood != SMC_LIK_CATEGORICAL && (accuracy || mean_log_pred))
+      fail(SMC_ERR_UNSUPPORTED, "accuracy needs the categorical likelihood");
+    ensure_cast(h);
+    const int64_t np = round_up(n, 256);
+    if (np > h->tx_rows) {
+      if (h->tx) HIPCHECK(hipFree(h->tx));
+      h->tx = nullptr;
+      HIPCHECK(hipMalloc(&h->tx, (size_t)np * h->ldx * h->esz));
+      h->tx_rows = np;
+    }
+    if (n > h->logp_n) {
+      if (h->logp) HIPCHECK(hipFree(h->logp));
+      if (h->per_sample) HIPCHECK(hipFree(h->per_sample));
+      h->logp = nullptr;
+      h->per_sample = nullptr;
+      HIPCHECK(hipMalloc((void**)&h->logp, (size_t)h->J * n * h->C * sizeof(float)));
+      HIPCHECK(hipMalloc((void**)&h->per_sample, (size_t)n * 2 * sizeof(double) + 4 * sizeof(double)));
+      h->logp_n = n;
+    }
+    const int64_t nx = np * h->ldx;
+    if (h->bf16)
+      hipLaunchKernelGGL(pack_x_kernel<__bf16>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream, x_dev, n,
+                         h->F, h->ldx, np, (__bf16*)h->tx);
+    else
+      hipLaunchKernelGGL(pack_x_kernel<float>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream, x_dev, n,
+                         h->F, h->ldx, np, (float*)h->tx);
+    HIPCHECK(hipGetLastError());
+    for (int64_t c0 = 0; c0 < n; c0 += h->mc) {
+      const int mcv = (int)std::min<int64_t>(h->mc, n - c0);
+      const int rows = (int)round_up(mcv, 64);
+      forward_hidden(h, h->tx, c0, rows);
+      HeadArgs a = head_args(h, h->theta);
+      if (h->L == 1) a.A = (const char*)h->tx + c0 * h->ldx * (int64_t)h->esz;
+      a.m_valid = mcv;
+      a.c0 = c0;
+      a.logp = h->logp;
+      a.ld_logp = n;
+      set_splits(h, a, mcv);
+      HIPCHECK(head_run(a, HEAD_PREDICT, h->bf16, h->stream));
+    }
+    double* pred_out = h->per_sample + 2 * n;
+    HIPCHECK(predictive_run(h->logp, n, h->logw, h->J, h->C, n, y_dev, probs_dev, y_dev ? h->per_sample : nullptr,
+                            h->stream));
+    if (y_dev && (accuracy || mean_log_pred)) {
+      HIPCHECK(predictive_finish_run(h->per_sample, n, pred_out, h->stream));
+      double host[2];
+      HIPCHECK(hipMemcpyAsync(host, pred_out, sizeof(host), hipMemcpyDeviceToHost, h->stream));
+      sync(h);
+      if (accuracy) *accuracy = host[0];
+      if (mean_log_pred) *mean_log_pred = host[1];
+    }
+  });
+}
+
+smc_status smc_posterior_mean(smc_t h, double* mean_dev) {
+  return run([&]() {
+    if (!h || !mean_dev) fail(SMC_ERR_ARG, "null argument");
+    HIPCHECK(posterior_mean_run(h->theta, h->w, h->J, h->D, mean_dev, h->stream));
+  });
+}
+
+smc_status smc_get_state(smc_t h, float* theta_dev, double* logw_dev, double* loglik_dev, double* logpi_dev,
+                         float* grad_dev) {
+  return run([&]() {
+    if (!h) fail(SMC_ERR_ARG, "null handle");
+    const size_t nd = (size_t)h->J * h->D;
+    if (theta_dev) HIPCHECK(hipMemcpyAsync(theta_dev, h->theta, nd * 4, hipMemcpyDeviceToDevice, h->stream));
+    if (logw_dev) HIPCHECK(hipMemcpyAsync(logw_dev, h->logw, h->J * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (loglik_dev) HIPCHECK(hipMemcpyAsync(loglik_dev, h->ll, h->J * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (logpi_dev) HIPCHECK(hipMemcpyAsync(logpi_dev, h->lp, h->J * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (grad_dev)
+      HIPCHECK(grad_with_prior_run(h->theta, h->g, grad_dev, (int64_t)nd,
+                                   (float)(1.0 / (h->cfg.prior_std * h->cfg.prior_std)), h->stream));
+  });
+}
+
+smc_status smc_set_state(smc_t h, const float* theta_dev, const double* logw_dev, const double* logpi_dev,
+                         uint64_t rng_counter) {
+  return run([&]() {
+    if (!h || !theta_dev) fail(SMC_ERR_ARG, "handle and theta_dev are required");
+    HIPCHECK(hipMemcpyAsync(h->theta, theta_dev, (size_t)h->J * h->D * 4, hipMemcpyDeviceToDevice, h->stream));
+    h->w_dirty = true;
+    ensure_cast(h);
+    grad_pass(h, h->theta, h->m, h->lam, nullptr, h->ll, h->g);
+    h->rng_iter = rng_counter;
+    // log pi and the initial weights at the restored particles
+    initial_weighting(h);
+    if (logpi_dev) HIPCHECK(hipMemcpyAsync(h->lp, logpi_dev, h->J * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (logw_dev) {
+      double* s4 = h->stats + 8;
+      HIPCHECK(normalise_run(logw_dev, h->J, h->logw, s4, h->stream, h->w));
+      double host[4];
+      HIPCHECK(hipMemcpyAsync(host, s4, sizeof(host), hipMemcpyDeviceToHost, h->stream));
+      sync(h);
+      double st[8] = {host[1], 0.0, 0.0, 0.0, host[2], host[1] < h->cfg.ess_frac * h->J ? 1.0 : 0.0,
+                      host[3] == -INFINITY ? 1.0 : 0.0, 0.0};
+      HIPCHECK(hipMemcpyAsync(h->stats, st, sizeof(st), hipMemcpyHostToDevice, h->stream));
+      sync(h);
+    }
+  });
+}
+
+smc_status smc_get_rng_counter(smc_t h, uint64_t* counter) {
+  if (!h || !counter) return SMC_ERR_ARG;
+  *counter = h->rng_iter;
+  return SMC_OK;
+}
+
+smc_status smc_set_noise(smc_t h, const float* momenta_dev) {
+  return run([&]() {
+    if (!h || !momenta_dev) fail(SMC_ERR_ARG, "null argument");
+    if (!h->noise) h->noise = dalloc<float>(h->owned, (int64_t)h->J * h->D);
+    HIPCHECK(hipMemcpyAsync(h->noise, momenta_dev, (size_t)h->J * h->D * 4, hipMemcpyDeviceToDevice, h->stream));
+    h->noise_pending = true;
+  });
+}
+
+smc_status smc_set_proposal_net(smc_t h, const float* params_dev, int32_t n_params, double h0) {
+  return run([&]() {
+    if (!h || !params_dev) fail(SMC_ERR_ARG, "null argument");
+    fail(SMC_ERR_UNSUPPORTED, "learned proposal not built yet");
+    (void)n_params;
+    (void)h0;
+  });
+}
+
+smc_status smc_proposal_features(smc_t h, double k_over_K, double m_over_N, double* feat_dev) {
+  return run([&]() {
+    if (!h || !feat_dev) fail(SMC_ERR_ARG, "null argument");
+    fail(SMC_ERR_UNSUPPORTED, "learned proposal not built yet");
+    (void)k_over_K;
+    (void)m_over_N;
+  });
+}
+
+smc_status smc_nn_forward(smc_t h, const float* theta_dev, int64_t m, double* ll_dev) {
+  return run([&]() {
+    if (!h || !theta_dev || !ll_dev) fail(SMC_ERR_ARG, "null argument");
+    if (m < 1 || m > h->n_data) fail(SMC_ERR_ARG, "m must be in [1, n_data]");
+    HIPCHECK(cast_run(h->net, theta_dev, nullptr, h->stream));
+    h->w_dirty = true;
+    grad_pass(h, theta_dev, m, 1.0, nullptr, ll_dev, nullptr);
+  });
+}
+
+smc_status smc_nn_backward(smc_t h, const float* theta_dev, int64_t m, const double* scale_dev, double* ll_dev,
+                           float* grad_dev) {
+  return run([&]() {
+    if (!h || !theta_dev || !grad_dev) fail(SMC_ERR_ARG, "null argument");
+    if (m < 1 || m > h->n_data) fail(SMC_ERR_ARG, "m must be in [1, n_data]");
+    HIPCHECK(cast_run(h->net, theta_dev, nullptr, h->stream));
+    h->w_dirty = true;
+    double* ll = ll_dev ? ll_dev : h->extra;
+    const int64_t ev = h->grad_evals;
+    grad_pass(h, theta_dev, m, 1.0, scale_dev, ll, grad_dev);
+    h->grad_evals = ev;  // not part of the sampler's own accounting
+  });
+}
+
+smc_status smc_normalise(const double* logw_dev, int32_t J, double* logw_out_dev, double* stats_dev,
+                         void* hip_stream) {
+  return run([&]() {
+    if (!logw_dev || !logw_out_dev || !stats_dev) fail(SMC_ERR_ARG, "null argument");
+    if (J < 1 || J > MAX_J) fail(SMC_ERR_ARG, "J out of range");
+    HIPCHECK(normalise_run(logw_dev, J, logw_out_dev, stats_dev, (hipStream_t)hip_stream));
+  });
+}
+
+smc_status smc_systematic_resample(const double* w_dev, int32_t J, double u, int32_t* ancestors_dev,
+                                   int32_t* placement_dev, void* hip_stream) {
+  return run([&]() {
+    if (!w_dev || !ancestors_dev) fail(SMC_ERR_ARG, "null argument");
+    if (J < 1 || J > MAX_J) fail(SMC_ERR_ARG, "J out of range");
+    if (!(u >= 0.0 && u < 1.0)) fail(SMC_ERR_ARG, "u must be in [0, 1)");
+    HIPCHECK(systematic_run(w_dev, J, u, ancestors_dev, placement_dev, (hipStream_t)hip_stream));
+  });
+}
+
+smc_status smc_philox(uint32_t key0_, uint32_t key1_, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n_blocks,
+                      uint32_t* out_dev, void* hip_stream) {
+  return run([&]() {
+    if (!out_dev || n_blocks < 0 || n_blocks > ((int64_t)1 << 32)) fail(SMC_ERR_ARG, "bad argument");
+    HIPCHECK(philox_run(key0_, key1_, c1, c2, c3, n_blocks, out_dev, (hipStream_t)hip_stream));
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,634 @@
+// Elementwise, reduction and population kernels of the SMC sampler.
+//
+//  * move_kernel     leapfrog half/full steps over the [J x D] population (Section 2.1,
+//                    Eqs. mom_first, pos_update, mom_second) with Philox momenta, fused
+//                    |xi|^2, |theta|^2, |P_end|^2 partial sums and the GEMM-layout re-cast;
+//  * weight_kernel   the reversed-momentum L-kernel log-weight update (Eq. weight_update_fp),
+//                    normalisation (Eq. normalise) and ESS (Eq. jeff) in FP64;
+//  * resample_kernel exact-integer systematic resampling and the in-place placement;
+//  * gather, posterior mean, predictive mixture, Philox, prior draw.
+// Reductions run in a fixed order (no floating-point atomics), so results are
+// reproducible run to run.
+#include "kernels.h"
+
+#include <math.h>
+
+namespace smc {
+
+namespace {
+
+// ------------------------------------------------------------------ GEMM-layout cast
+template <typename T>
+__device__ __forceinline__ void cast_one(const NetShape& n, int j, int64_t e, float v) {
+  int l = 0;
+#pragma unroll
+  for (int q = 1; q < MAX_LAYERS; ++q)
+    if (q < n.L && e >= n.off[q]) l = q;
+  const int rowlen = n.nin[l] + 1;
+  const int ep = (int)(e - n.off[l]);
+  int o = (int)((float)ep * n.rinv[l]);
+  while (o * rowlen > ep) --o;
+  while ((o + 1) * rowlen <= ep) ++o;
+  const int i = ep - o * rowlen;
+  const int64_t r = (int64_t)j * n.nout[l] + o;
+  if (i < n.nin[l]) ((T*)n.w[l])[r * n.ldw[l] + i] = cvt_out<T>(v);
+  else n.bias[l][r] = v;
+}
+
+__device__ __forceinline__ void cast_any(const NetShape& n, int j, int64_t e, float v) {
+  if (n.bf16) cast_one<__bf16>(n, j, e, v);
+  else cast_one<float>(n, j, e, v);
+}
+
+__global__ __launch_bounds__(256) void cast_kernel(const NetShape n, const float* __restrict__ theta,
+                                                   const int32_t* __restrict__ placement) {
+  const int j = blockIdx.y;
+  if (placement && placement[j] == j) return;
+  const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + 4 * threadIdx.x;
+  const float* th = theta + (int64_t)j * n.D;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t e = e0 + i;
+    if (e < n.D) cast_any(n, j, e, th[e]);
+  }
+}
+
+// ------------------------------------------------------------------ move
+__global__ __launch_bounds__(256) void move_kernel(const MoveArgs a) {
+  __shared__ double red[3][4];
+  const int j = blockIdx.y;
+  const int64_t D = a.net.D;
+  const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + 4 * threadIdx.x;
+  float* th = a.theta + (int64_t)j * D;
+  float* P = a.P + (int64_t)j * D;
+  const float* g = a.g + (int64_t)j * D;
+  float s_xi = 0.0f, s_th = 0.0f, s_pe = 0.0f;
+  f32x4 nz = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (a.mode == MOVE_FIRST && !a.noise && e0 < D) {
+    const u32x4 c = {(uint32_t)(e0 >> 2), (uint32_t)j, a.ctr_iter, (uint32_t)TAG_MOMENTUM};
+    nz = normal4(philox4x32_10(c, a.key0, a.key1));
+  }
+  const float h = a.h, hh = 0.5f * a.h;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t e = e0 + i;
+    if (e >= D) break;
+    float t = th[e];
+    const float gf = g[e] - t * a.inv_prior_var;
+    if (a.mode == MOVE_FIRST) {
+      const float xi = a.noise ? a.noise[(int64_t)j * D + e] : nz[i];
+      s_xi += xi * xi;
+      const float p = xi + hh * gf;
+      t = t + h * p;
+      P[e] = p;
+      th[e] = t;
+      s_th += t * t;
+      if (a.cast) cast_any(a.net, j, e, t);
+    } else if (a.mode == MOVE_MID) {
+      const float p = P[e] + h * gf;
+      t = t + h * p;
+      P[e] = p;
+      th[e] = t;
+      s_th += t * t;
+      if (a.cast) cast_any(a.net, j, e, t);
+    } else {
+      const float p = P[e] + hh * gf;
+      s_pe += p * p;
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const double v0 = wave_sum((double)s_xi), v1 = wave_sum((double)s_th), v2 = wave_sum((double)s_pe);
+  if (lane == 0) { red[0][wid] = v0; red[1][wid] = v1; red[2][wid] = v2; }
+  __syncthreads();
+  // each mode owns its rows: FIRST |xi|^2 and |theta|^2, MID |theta|^2, LAST |P_end|^2
+  const int w = threadIdx.x;
+  const bool own = (a.mode == MOVE_FIRST && w < 2) || (a.mode == MOVE_MID && w == 1) || (a.mode == MOVE_LAST && w == 2);
+  if (w < 3 && own) {
+    const double s = red[w][0] + red[w][1] + red[w][2] + red[w][3];
+    a.part[((int64_t)w * a.net.J + j) * a.nblk + blockIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------------ block scans
+template <typename V>
+__device__ V block_exclusive_scan(V v, V* wsum, V& total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  V x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const V y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    V run = 0;
+    for (int w = 0; w < nw; ++w) {
+      const V t = wsum[w];
+      wsum[w] = run;
+      run += t;
+    }
+    wsum[nw] = run;
+  }
+  __syncthreads();
+  const V ex = wsum[wid] + x - v;
+  total = wsum[nw];
+  __syncthreads();
+  return ex;
+}
+
+// ------------------------------------------------------------------ weights
+__global__ __launch_bounds__(1024) void weight_kernel(const WeightArgs a) {
+  __shared__ double red[16];
+  constexpr int NPT = MAX_J / 1024;
+  const int J = a.J, tid = threadIdx.x;
+  double lwn[NPT];
+  double mx = -INFINITY, llsum = 0.0, llmax = -INFINITY;
+  double nbad = 0.0, nfin = 0.0;
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int j = tid + q * 1024;
+    lwn[q] = -INFINITY;
+    if (j >= J) continue;
+    double k0 = 0.0, kt = a.tsq ? a.tsq[j] : 0.0, k1 = 0.0;
+    if (a.part) {
+      const double* p0 = a.part + (int64_t)j * a.nblk;
+      const double* p1 = a.part + ((int64_t)J + j) * a.nblk;
+      const double* p2 = a.part + ((int64_t)2 * J + j) * a.nblk;
+      for (int b = 0; b < a.nblk; ++b) { k0 += p0[b]; kt += p1[b]; k1 += p2[b]; }
+      if (a.no_kinetic) { k0 = 0.0; k1 = 0.0; }
+    }
+    const double ll = a.ll[j];
+    const double lpn = a.lambda * ll - kt * a.inv_2prior_var;
+    double incr;
+    double prev;
+    if (a.init) {
+      incr = a.lambda * ll;
+      prev = 0.0;
+    } else {
+      incr = lpn - a.lp[j] - 0.5 * k1 + 0.5 * k0 + (a.extra ? a.extra[j] : 0.0);
+      prev = a.logw[j];
+    }
+    double v = prev + incr;
+    if (!isfinite(incr) || !isfinite(ll) || isnan(v)) v = -INFINITY;
+    if (v == -INFINITY) nbad += 1.0;
+    a.lp[j] = lpn;
+    lwn[q] = v;
+    mx = fmax(mx, v);
+    if (isfinite(ll)) { llsum += ll; llmax = fmax(llmax, ll); nfin += 1.0; }
+  }
+  const double m = block_max(mx, red);
+  const double tot_bad = block_sum(nbad, red);
+  const double tot_ll = block_sum(llsum, red);
+  const double tot_fin = block_sum(nfin, red);
+  const double max_ll = block_max(llmax, red);
+  if (m == -INFINITY) {
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int j = tid + q * 1024;
+      if (j < J) { a.logw[j] = -INFINITY; a.w[j] = 0.0; }
+    }
+    if (tid == 0) {
+      a.stats[ST_ESS] = 0.0; a.stats[ST_LOGZ] = -INFINITY; a.stats[ST_MEANLL] = NAN; a.stats[ST_MAXLL] = NAN;
+      a.stats[ST_NONFINITE] = tot_bad; a.stats[ST_RECOMMEND] = 0.0; a.stats[ST_ALLBAD] = 1.0;
+    }
+    return;
+  }
+  double se = 0.0;
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) se += (tid + q * 1024 < J) ? exp(lwn[q] - m) : 0.0;
+  se = block_sum(se, red);
+  const double lz = m + log(se);
+  double s2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int j = tid + q * 1024;
+    if (j >= J) continue;
+    const double lw = lwn[q] - lz;
+    const double w = exp(lw);
+    a.logw[j] = lw;
+    a.w[j] = w;
+    s2 += w * w;
+  }
+  s2 = block_sum(s2, red);
+  if (tid == 0) {
+    const double ess = 1.0 / s2;
+    a.stats[ST_ESS] = ess;
+    a.stats[ST_LOGZ] = lz - (a.init ? log((double)J) : 0.0);
+    a.stats[ST_MEANLL] = tot_fin > 0 ? tot_ll / tot_fin : NAN;
+    a.stats[ST_MAXLL] = max_ll;
+    a.stats[ST_NONFINITE] = tot_bad;
+    a.stats[ST_RECOMMEND] = ess < a.ess_frac * (double)J ? 1.0 : 0.0;
+    a.stats[ST_ALLBAD] = 0.0;
+    a.stats[ST_RESAMPLED] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(1024) void normalise_kernel(const double* logw, int J, double* out, double* stats,
+                                                        double* wout) {
+  __shared__ double red[16];
+  constexpr int NPT = MAX_J / 1024;
+  const int tid = threadIdx.x;
+  double v[NPT];
+  double mx = -INFINITY, nbad = 0.0;
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int j = tid + q * 1024;
+    v[q] = j < J ? logw[j] : -INFINITY;
+    if (j < J && !(v[q] > -INFINITY && v[q] < INFINITY)) { nbad += 1.0; v[q] = -INFINITY; }
+    mx = fmax(mx, v[q]);
+  }
+  const double m = block_max(mx, red);
+  const double bad = block_sum(nbad, red);
+  double se = 0.0;
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) se += (tid + q * 1024 < J && m > -INFINITY) ? exp(v[q] - m) : 0.0;
+  se = block_sum(se, red);
+  const double lz = m > -INFINITY ? m + log(se) : -INFINITY;
+  double s2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int j = tid + q * 1024;
+    if (j >= J) continue;
+    const double lw = m > -INFINITY ? v[q] - lz : -INFINITY;
+    out[j] = lw;
+    const double w = exp(lw);
+    if (wout) wout[j] = w;
+    s2 += w * w;
+  }
+  s2 = block_sum(s2, red);
+  if (tid == 0) {
+    stats[0] = lz;
+    stats[1] = s2 > 0 ? 1.0 / s2 : 0.0;
+    stats[2] = bad;
+    stats[3] = m;
+  }
+}
+
+// ------------------------------------------------------------------ systematic resampling
+struct SysScratch {
+  uint64_t* S;   // [J]
+  int* cnt;      // [J]
+  int* einc;     // [J]
+  int* drank;    // [J]
+  uint64_t* wsu; // [17]
+  int* wsi;      // [17]
+};
+
+__device__ SysScratch sys_scratch(char* smem, int J) {
+  SysScratch s;
+  s.S = (uint64_t*)smem;
+  s.wsu = s.S + J;
+  s.cnt = (int*)(s.wsu + 17);
+  s.einc = s.cnt + J;
+  s.drank = s.einc + J;
+  s.wsi = s.drank + J;
+  return s;
+}
+size_t sys_smem_bytes(int J) { return (size_t)J * 8 + 17 * 8 + (size_t)J * 12 + 17 * 4; }
+
+// ancestors (sorted) and in-place placement from normalised weights w, offset u
+__device__ void systematic_core(const double* w, int J, double u, const SysScratch& s, int32_t* anc,
+                                int32_t* place) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int per = (J + nt - 1) / nt;
+  const int b = min(J, tid * per), e = min(J, b + per);
+  uint64_t loc = 0;
+  for (int i = b; i < e; ++i) {
+    loc += (uint64_t)floor(w[i] * 0x1p50);
+    s.S[i] = loc;
+  }
+  uint64_t tot;
+  const uint64_t ex = block_exclusive_scan<uint64_t>(loc, s.wsu, tot);
+  for (int i = b; i < e; ++i) s.S[i] += ex;
+  for (int i = tid; i < J; i += nt) s.cnt[i] = 0;
+  __syncthreads();
+  const uint64_t T = s.S[J - 1];
+  uint64_t R = (uint64_t)floor(u * (double)T);
+  if (R > T - 1) R = T - 1;
+  for (int k = tid; k < J; k += nt) {
+    const uint64_t t = ((uint64_t)k * T + R) / (uint64_t)J;
+    int lo = 0, hi = J - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s.S[mid] > t) hi = mid;
+      else lo = mid + 1;
+    }
+    anc[k] = lo;
+    atomicAdd(&s.cnt[lo], 1);
+  }
+  __syncthreads();
+  if (!place) return;
+  int dloc = 0, xloc = 0;
+  for (int i = b; i < e; ++i) {
+    const int c = s.cnt[i];
+    dloc += c == 0;
+    xloc += c > 1 ? c - 1 : 0;
+  }
+  int dtot, xtot;
+  int dr = block_exclusive_scan<int>(dloc, s.wsi, dtot);
+  int xr = block_exclusive_scan<int>(xloc, s.wsi, xtot);
+  for (int i = b; i < e; ++i) {
+    const int c = s.cnt[i];
+    s.drank[i] = dr;
+    dr += c == 0;
+    xr += c > 1 ? c - 1 : 0;
+    s.einc[i] = xr;
+  }
+  __syncthreads();
+  for (int k = tid; k < J; k += nt) {
+    if (s.cnt[k] > 0) {
+      place[k] = k;
+    } else {
+      const int r = s.drank[k];
+      int lo = 0, hi = J - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s.einc[mid] > r) hi = mid;
+        else lo = mid + 1;
+      }
+      place[k] = lo;
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void systematic_kernel(const double* w, int J, double u, int32_t* anc,
+                                                          int32_t* place) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const SysScratch s = sys_scratch(smem, J);
+  systematic_core(w, J, u, s, anc, place);
+}
+
+__device__ __forceinline__ double philox_u01_double(uint32_t k0, uint32_t k1, uint32_t iter, uint32_t tag) {
+  const u32x4 c = {0u, 0u, iter, tag};
+  const u32x4 r = philox4x32_10(c, k0, k1);
+  const uint64_t hi = r[0] >> 5, lo = r[1] >> 6;  // 27 + 26 bits
+  return (double)((hi << 26) | lo) * 0x1p-53;
+}
+
+__global__ __launch_bounds__(1024) void resample_kernel(const ResampleArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int J = a.J, tid = threadIdx.x;
+  const double ess = a.stats[ST_ESS];
+  const bool doit = a.mode == 1 || (a.mode == 0 && ess < a.ess_frac * (double)J);
+  if (!doit) {
+    for (int k = tid; k < J; k += blockDim.x) {
+      a.ancestors[k] = k;
+      a.placement[k] = k;
+    }
+    if (tid == 0) a.stats[ST_RESAMPLED] = 0.0;
+    return;
+  }
+  const double u = a.u_dev ? *a.u_dev : philox_u01_double(a.key0, a.key1, a.ctr_iter, TAG_RESAMPLE_U);
+  const SysScratch s = sys_scratch(smem, J);
+  systematic_core(a.w, J, u, s, a.ancestors, a.placement);
+  // gather the per-particle scalars (read everything before writing)
+  constexpr int NPT = MAX_J / 1024;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (!a.sc[c]) continue;
+    double tmp[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int k = tid + q * 1024;
+      tmp[q] = k < J ? a.sc[c][a.placement[k]] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int k = tid + q * 1024;
+      if (k < J) a.sc[c][k] = tmp[q];
+    }
+    __syncthreads();
+  }
+  const double lw = -log((double)J), w = 1.0 / (double)J;
+  for (int k = tid; k < J; k += blockDim.x) {
+    a.logw[k] = lw;
+    a.w[k] = w;
+  }
+  if (tid == 0) {
+    a.stats[ST_RESAMPLED] = 1.0;
+    a.stats[ST_ESS] = (double)J;
+    a.stats[ST_RECOMMEND] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void gather_rows_kernel(int64_t D, const int32_t* __restrict__ placement,
+                                                          float* a0, float* a1) {
+  const int j = blockIdx.y;
+  const int p = placement[j];
+  if (p == j) return;
+  const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + 4 * threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t e = e0 + i;
+    if (e >= D) break;
+    a0[(int64_t)j * D + e] = a0[(int64_t)p * D + e];
+    if (a1) a1[(int64_t)j * D + e] = a1[(int64_t)p * D + e];
+  }
+}
+
+// ------------------------------------------------------------------ estimates
+__global__ __launch_bounds__(256) void posterior_mean_kernel(const float* theta, const double* w, int J, int64_t D,
+                                                             double* out) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= D) return;
+  double s = 0.0;
+  for (int j = 0; j < J; ++j) s += w[j] * (double)theta[(int64_t)j * D + d];
+  out[d] = s;
+}
+
+__global__ __launch_bounds__(256) void predictive_kernel(const float* logp, int64_t ld, const double* logw, int J,
+                                                         int C, int64_t n, const int32_t* y, float* probs,
+                                                         double* per_sample) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double pr[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) pr[c] = 0.0;
+  const int yi = y ? y[i] : 0;
+  double m = -INFINITY, s = 0.0;
+  for (int j = 0; j < J; ++j) {
+    const double lw = logw[j];
+    if (lw == -INFINITY) continue;
+    const float* row = logp + ((int64_t)j * ld + i) * C;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c < C) pr[c] += exp(lw + (double)row[c]);
+    if (y) {
+      const double v = lw + (double)row[yi];
+      if (v > m) { s = s * exp(m - v) + 1.0; m = v; }
+      else s += exp(v - m);
+    }
+  }
+  int best = 0;
+  for (int c = 1; c < C; ++c)
+    if (pr[c] > pr[best]) best = c;
+  if (probs)
+    for (int c = 0; c < C; ++c) probs[i * C + c] = (float)pr[c];
+  if (per_sample) {
+    per_sample[2 * i] = (y && best == yi) ? 1.0 : 0.0;
+    per_sample[2 * i + 1] = y ? m + log(s) : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(1024) void predictive_finish_kernel(const double* per_sample, int64_t n, double* out2) {
+  __shared__ double red[16];
+  double a = 0.0, b = 0.0;
+  // fixed per-thread contiguous ranges, then a fixed tree
+  const int64_t per = (n + blockDim.x - 1) / blockDim.x;
+  const int64_t lo = min(n, (int64_t)threadIdx.x * per), hi = min(n, lo + per);
+  for (int64_t i = lo; i < hi; ++i) { a += per_sample[2 * i]; b += per_sample[2 * i + 1]; }
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  if (threadIdx.x == 0) { out2[0] = a / (double)n; out2[1] = b / (double)n; }
+}
+
+// ------------------------------------------------------------------ RNG and helpers
+__global__ void philox_kernel(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
+                              uint32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const u32x4 c = {(uint32_t)i, c1, c2, c3};
+  const u32x4 r = philox4x32_10(c, k0, k1);
+  for (int q = 0; q < 4; ++q) out[4 * i + q] = r[q];
+}
+
+__global__ __launch_bounds__(256) void prior_draw_kernel(float* theta, int64_t D, float sd, uint32_t k0, uint32_t k1) {
+  const int j = blockIdx.y;
+  const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + 4 * threadIdx.x;
+  if (e0 >= D) return;
+  const u32x4 c = {(uint32_t)(e0 >> 2), (uint32_t)j, 0u, (uint32_t)TAG_PRIOR};
+  const f32x4 nz = normal4(philox4x32_10(c, k0, k1));
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (e0 + i < D) theta[(int64_t)j * D + e0 + i] = sd * nz[i];
+}
+
+__global__ void fill_f64_kernel(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void grad_with_prior_kernel(const float* theta, const float* g, float* out, int64_t n, float ipv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = g[i] - theta[i] * ipv;
+}
+
+__global__ __launch_bounds__(256) void sq_norm_rows_kernel(const float* a, int64_t D, double* out) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < D; e += 256) {
+    const double v = a[(int64_t)j * D + e];
+    s += v * v;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t kernels_set_smem_limits() {
+  const int big = 160 * 1024;
+  hipError_t e = hipFuncSetAttribute((const void*)systematic_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)resample_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+}
+
+hipError_t cast_run(const NetShape& net, const float* theta, const int32_t* placement, hipStream_t s) {
+  dim3 grid(nblocks(net.D, MOVE_ELEMS), net.J);
+  hipLaunchKernelGGL(cast_kernel, grid, dim3(256), 0, s, net, theta, placement);
+  return hipGetLastError();
+}
+
+hipError_t move_run(const MoveArgs& a, hipStream_t s) {
+  dim3 grid(a.nblk, a.net.J);
+  hipLaunchKernelGGL(move_kernel, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t weight_run(const WeightArgs& a, hipStream_t s) {
+  if (a.J > MAX_J) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(weight_kernel, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t normalise_run(const double* logw, int J, double* out, double* stats, hipStream_t s, double* wout) {
+  if (J > MAX_J || J < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(normalise_kernel, dim3(1), dim3(1024), 0, s, logw, J, out, stats, wout);
+  return hipGetLastError();
+}
+
+hipError_t resample_run(const ResampleArgs& a, hipStream_t s) {
+  if (a.J > MAX_J) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(resample_kernel, dim3(1), dim3(1024), sys_smem_bytes(a.J), s, a);
+  return hipGetLastError();
+}
+
+hipError_t systematic_run(const double* w, int J, double u, int32_t* anc, int32_t* placement, hipStream_t s) {
+  if (J > MAX_J || J < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(systematic_kernel, dim3(1), dim3(1024), sys_smem_bytes(J), s, w, J, u, anc, placement);
+  return hipGetLastError();
+}
+
+hipError_t gather_rows_run(int J, int64_t D, const int32_t* placement, float* a0, float* a1, hipStream_t s) {
+  dim3 grid(nblocks(D, MOVE_ELEMS), J);
+  hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(256), 0, s, D, placement, a0, a1);
+  return hipGetLastError();
+}
+
+hipError_t philox_run(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t* out,
+                      hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(philox_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, k0, k1, c1, c2, c3, n, out);
+  return hipGetLastError();
+}
+
+hipError_t prior_draw_run(float* theta, int J, int64_t D, float prior_std, uint32_t k0, uint32_t k1, hipStream_t s) {
+  dim3 grid(nblocks(D, MOVE_ELEMS), J);
+  hipLaunchKernelGGL(prior_draw_kernel, grid, dim3(256), 0, s, theta, D, prior_std, k0, k1);
+  return hipGetLastError();
+}
+
+hipError_t posterior_mean_run(const float* theta, const double* w, int J, int64_t D, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(posterior_mean_kernel, dim3(nblocks(D, 256)), dim3(256), 0, s, theta, w, J, D, out);
+  return hipGetLastError();
+}
+
+hipError_t predictive_run(const float* logp, int64_t ld, const double* logw, int J, int C, int64_t n,
+                          const int32_t* y, float* probs, double* per_sample, hipStream_t s) {
+  if (C > 16) return hipErrorInvalidValue;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(predictive_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, logp, ld, logw, J, C, n, y, probs,
+                     per_sample);
+  return hipGetLastError();
+}
+
+hipError_t predictive_finish_run(const double* per_sample, int64_t n, double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(predictive_finish_kernel, dim3(1), dim3(1024), 0, s, per_sample, n, out2);
+  return hipGetLastError();
+}
+
+hipError_t fill_f64_run(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t grad_with_prior_run(const float* theta, const float* g, float* out, int64_t n, float ipv, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(grad_with_prior_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, theta, g, out, n, ipv);
+  return hipGetLastError();
+}
+
+hipError_t sq_norm_rows_run(const float* a, int J, int64_t D, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sq_norm_rows_kernel, dim3(J), dim3(256), 0, s, a, D, out);
+  return hipGetLastError();
+}
+
+}  // namespace smc

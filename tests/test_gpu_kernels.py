@@ -1,0 +1,145 @@
+"""GPU parity of the population kernels against the oracle: Philox, normalisation/ESS,
+systematic resampling (bit-exact), and the network log-likelihood/gradient pass."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import cuda, lib, print_case, rel_err, to_dev, torch
+from oracle import mlp, smc
+from oracle.philox import philox4x32
+import smc_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def test_philox_bitexact():
+    cuda()
+    P = lib()
+    n = 1000
+    out = torch.zeros(4 * n, dtype=torch.int32, device="cuda")
+    print_case("philox", n=n)
+    P._lib.smc_philox(0x12345678, 0x9abcdef0, 7, 11, 13, n, out.data_ptr(), None)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32).reshape(n, 4)
+    for i in list(range(0, n, 97)) + [n - 1]:
+        assert tuple(int(x) for x in got[i]) == philox4x32((i, 7, 11, 13), (0x12345678, 0x9abcdef0))
+
+
+@pytest.mark.parametrize("J", [1, 5, 64, 1000, 4096])
+def test_normalise_and_ess(J):
+    cuda()
+    P = lib()
+    rng = np.random.default_rng(J)
+    lw = 40.0 * rng.standard_normal(J)
+    if J > 3:
+        lw[2] = -np.inf
+    print_case("normalise", J=J)
+    d_in = to_dev(lw)
+    d_out = torch.empty_like(d_in)
+    st = torch.zeros(4, dtype=torch.float64, device="cuda")
+    P._lib.smc_normalise(d_in.data_ptr(), J, d_out.data_ptr(), st.data_ptr(), None)
+    torch.cuda.synchronize()
+    ref, lz = smc.normalise(lw)
+    got = d_out.cpu().numpy()
+    fin = np.isfinite(ref)
+    assert np.all(got[~fin] == -np.inf)
+    assert np.max(np.abs(got[fin] - ref[fin])) < 1e-12 * max(1.0, np.max(np.abs(ref[fin])))
+    s = st.cpu().numpy()
+    assert abs(s[0] - lz) < 1e-12 * max(1.0, abs(lz))
+    assert abs(s[1] - smc.ess(ref)) < 1e-10 * smc.ess(ref)
+    assert s[2] == (1 if J > 3 else 0)
+
+
+def _sys_case(w, u):
+    P = lib()
+    J = len(w)
+    d_w = to_dev(np.asarray(w, np.float64))
+    anc = torch.empty(J, dtype=torch.int32, device="cuda")
+    pl = torch.empty(J, dtype=torch.int32, device="cuda")
+    P._lib.smc_systematic_resample(d_w.data_ptr(), J, float(u), anc.data_ptr(), pl.data_ptr(), None)
+    torch.cuda.synchronize()
+    return anc.cpu().numpy(), pl.cpu().numpy()
+
+
+def test_systematic_worked_examples():
+    cuda()
+    for w, u, a in [([0.1, 0.2, 0.3, 0.4], 0.5, [1, 2, 3, 3]), ([0, 0, 1, 0, 0], 0.25, [2] * 5),
+                    ([0.5, 0.5, 0, 0], 0.0, [0, 0, 1, 1])]:
+        print_case("systematic-worked", J=len(w), u=u)
+        got, _ = _sys_case(w, u)
+        assert got.tolist() == a
+
+
+@pytest.mark.parametrize("J", [1, 3, 64, 257, 1024, 4096])
+def test_systematic_bitexact_vs_oracle(J):
+    cuda()
+    rng = np.random.default_rng(100 + J)
+    for trial in range(4):
+        if trial == 0:
+            w = np.full(J, 1.0 / J)
+        elif trial == 1:
+            w = np.zeros(J); w[J // 2] = 1.0
+        else:
+            lw, _ = smc.normalise(3.0 * rng.standard_normal(J))
+            w = np.exp(lw)
+        u = [0.0, 1.0 - 2 ** -53, rng.random(), rng.random()][trial]
+        print_case("systematic", J=J, trial=trial, u=u)
+        anc, pl = _sys_case(w, u)
+        ref = smc.systematic_ancestors(w, u)
+        assert np.array_equal(anc, ref)
+        assert np.array_equal(pl, smc.placement(ref))
+
+
+# ---------------------------------------------------------------- network pass
+NET_CASES = [
+    # widths, act, lik, J, M, precision, budget (small budgets force several chunks)
+    ([2, 16, 2], "tanh", "categorical", 64, 1000, "fp32", 0),
+    ([784, 100, 10], "relu", "categorical", 24, 1000, "fp32", 24 * 100 * 4 * 2 * 256),
+    ([784, 64, 32, 10], "relu", "categorical", 12, 700, "fp32", 0),
+    ([784, 64, 32, 10], "relu", "categorical", 12, 700, "fp32", 1),
+    ([5, 1], "relu", "gaussian", 33, 999, "fp32", 0),
+    ([784, 100, 10], "relu", "categorical", 24, 1000, "bf16", 0),
+    ([784, 64, 32, 10], "tanh", "categorical", 12, 700, "bf16", 0),
+]
+
+
+def _net_data(widths, lik, n, seed):
+    if widths[0] == 784:
+        X, y = smc_inputs.templates28(n, seed=seed)
+    elif lik == "gaussian":
+        X, y, _ = smc_inputs.linreg(n, widths[0], seed=seed)
+    else:
+        X, y = smc_inputs.blobs(n, seed=seed)
+    return X, y
+
+
+@pytest.mark.parametrize("case", range(len(NET_CASES)))
+def test_loglik_and_gradient_vs_oracle(case):
+    cuda()
+    P = lib()
+    widths, act, lik, J, M, prec, budget = NET_CASES[case]
+    print_case("net", widths=widths, act=act, lik=lik, J=J, M=M, prec=prec, budget=budget)
+    X, y = _net_data(widths, lik, M + 37, seed=case)
+    D = mlp.n_params(widths)
+    theta = smc_inputs.prior_draw(case, J, D, 0.3 if widths[0] == 784 else 1.0)
+    cfg = P.SMCConfig(widths=widths, n_particles=J, activation=act, likelihood=lik, precision=prec,
+                      noise_std=0.7, act_budget_bytes=budget)
+    yd = to_dev(y.astype(np.float32) if lik == "gaussian" else y.astype(np.int32))
+    s = P.SMCSampler(cfg, to_dev(X), yd, m0=M, lambda0=1.0, theta0=to_dev(theta))
+    if budget:
+        assert s.chunk_samples() < M  # the pass really is split into chunks
+    scale = np.linspace(0.5, 2.0, J)
+    ll_g, g_g = s.nn_backward(to_dev(theta), M, to_dev(scale))
+    ll_f = s.nn_forward(to_dev(theta), M)
+    torch.cuda.synchronize()
+    ll_ref, g_ref = mlp.loglik_grad(theta, X[:M], y[:M], widths, act, lik, 0.7, scale=scale)
+    ll_g, ll_f, g_g = ll_g.cpu().numpy(), ll_f.cpu().numpy(), g_g.cpu().numpy()
+    tol_ll = 1e-5 if prec == "fp32" else 2e-2
+    assert rel_err(ll_g, ll_ref) < tol_ll
+    assert rel_err(ll_f, ll_ref) < tol_ll
+    # gradients: compare against the scale of each particle's gradient
+    gs = np.max(np.abs(g_ref), axis=1, keepdims=True)
+    err = np.max(np.abs(g_g - g_ref) / gs)
+    assert err < (2e-4 if prec == "fp32" else 3e-2), err
+    s.close()

@@ -1,0 +1,208 @@
+"""End-to-end GPU parity of the SMC sampler against the oracle on seeded inputs,
+with the same injected momenta and resampling offsets on both sides."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import cuda, lib, print_case, rel_err, to_dev, torch
+from oracle import blr, mlp, schedules, smc
+import smc_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_pair(widths, act, X, y, Xt, yt, J, sizes, N, h, prec="fp32", S=1, seed=0, prior=1.0):
+    """Run the oracle and the GPU sampler side by side; yield per-iteration pairs."""
+    P = lib()
+    D = mlp.n_params(widths)
+    th0 = smc_inputs.prior_draw(seed, J, D, prior)
+    o = smc.Sampler(X, y, widths, act, step_size=h, leapfrog_steps=S, prior_std=prior)
+    o.init(th0, sizes[0], N / sizes[0])
+    cfg = P.SMCConfig(widths=widths, n_particles=J, activation=act, precision=prec, step_size=h,
+                      leapfrog_steps=S, prior_std=prior, seed=seed)
+    g = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=sizes[0], lambda0=N / sizes[0],
+                     theta0=to_dev(th0))
+    u = smc_inputs.uniforms(seed + 7, len(sizes))
+    res_o = o.resample(u[0])
+    res_g, anc_g = g.resample("if_needed", float(u[0]), want=True)
+    yield 0, o, g, res_o, res_g, anc_g
+    for k in range(1, len(sizes)):
+        xi = smc_inputs.momenta(1000 * seed + k, (J, D))
+        g.set_noise(to_dev(xi))
+        info = g.step(sizes[k], N / sizes[k])
+        o.step(sizes[k], N / sizes[k], xi)
+        assert info["grad_evals"] == J * sizes[k] * (S + (1 if sizes[k] != sizes[k - 1] else 0))
+        res_o = o.resample(u[k])
+        res_g, anc_g = g.resample("if_needed", float(u[k]), want=True)
+        yield k, o, g, res_o, res_g, anc_g
+
+
+def _compare(o, g, res_o, res_g, anc_g, tol_theta, tol_logw, k):
+    st = g.state()
+    assert res_g == res_o, f"iteration {k}: resampling decision differs"
+    if res_o:
+        assert anc_g == o.ancestors.tolist(), f"iteration {k}: ancestors differ"
+    th = st["theta"].cpu().numpy()
+    scale = np.max(np.abs(o.theta))
+    assert np.max(np.abs(th - o.theta)) < tol_theta * scale, f"iteration {k}: theta"
+    lw = st["logw"].cpu().numpy()
+    big = o.logw > np.log(1e-6)
+    assert np.max(np.abs(lw[big] - o.logw[big])) < tol_logw, f"iteration {k}: logw"
+    ll = st["loglik"].cpu().numpy()
+    assert rel_err(ll, o.ll) < 1e-4, f"iteration {k}: loglik"
+
+
+def test_blobs_trajectory_matches_oracle():
+    cuda()
+    X, y = smc_inputs.blobs(1024, seed=0)
+    Xt, yt = smc_inputs.blobs(1024, seed=1)
+    sizes = schedules.sizes("linear", 10, 1024, 128, 128)
+    print_case("blobs-trajectory", J=64, sizes=sizes)
+    for k, o, g, res_o, res_g, anc_g in _run_pair([2, 16, 2], "tanh", X, y, Xt, yt, 64, sizes, 1024, h=1e-3):
+        _compare(o, g, res_o, res_g, anc_g, 1e-5, 1e-3, k)
+    r = g.predict(to_dev(Xt), to_dev(yt.astype(np.int32)), probs=True)
+    probs, acc, mlpd = o.predictive(Xt, yt)
+    assert abs(r["accuracy"] - acc) <= 0.005
+    assert abs(r["mean_log_pred"] - mlpd) < 1e-3 * max(1.0, abs(mlpd))
+    assert np.max(np.abs(r["probs"].cpu().numpy() - probs)) < 1e-4
+    g.close()
+
+
+def test_blobs_hmc_trajectory_matches_oracle():
+    cuda()
+    X, y = smc_inputs.blobs(512, seed=2)
+    sizes = schedules.sizes("linear", 6, 512, 128, 128)
+    print_case("blobs-hmc", J=32, S=3)
+    for k, o, g, res_o, res_g, anc_g in _run_pair([2, 16, 2], "tanh", X, y, None, None, 32, sizes, 512,
+                                                   h=2e-3, S=3, seed=3):
+        _compare(o, g, res_o, res_g, anc_g, 1e-5, 1e-3, k)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mnist_shaped_trajectory(prec):
+    cuda()
+    N = 3000
+    X, y = smc_inputs.templates28(N, seed=0)
+    Xt, yt = smc_inputs.templates28(500, seed=1)
+    sizes = [1000, 2000, 3000, 3000]
+    print_case("mnist-shaped-trajectory", prec=prec, J=24)
+    last = None
+    for k, o, g, res_o, res_g, anc_g in _run_pair([784, 100, 10], "relu", X, y, Xt, yt, 24, sizes, N,
+                                                   h=2e-3, prec=prec, seed=5, prior=0.1):
+        if prec == "fp32":
+            _compare(o, g, res_o, res_g, anc_g, 1e-4, 2e-2, k)
+        last = (o, g)
+    o, g = last
+    r = g.predict(to_dev(Xt), to_dev(yt.astype(np.int32)))
+    _, acc, mlpd = o.predictive(Xt, yt)
+    assert abs(r["accuracy"] - acc) <= 0.005
+    g.close()
+
+
+def test_blr_posterior_with_device_rng():
+    # Gaussian linear regression: the weighted particle mean/covariance match the exact posterior
+    cuda()
+    P = lib()
+    n, d, noise = 48, 2, 0.5
+    X, y, _ = smc_inputs.linreg(n, d, seed=11, noise_std=noise)
+    J = 4096
+    cfg = P.SMCConfig(widths=[d, 1], n_particles=J, likelihood="gaussian", noise_std=noise, step_size=0.03,
+                      seed=1234)
+    s = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.float32)), m0=8, lambda0=n / 8)
+    s.resample()
+    for m in [16, 24, 32, 40, 48] + [48] * 40:
+        s.step(m, n / m, info=False)
+        s.resample()
+    st = s.state()
+    w = np.exp(st["logw"].cpu().numpy())
+    th = st["theta"].cpu().numpy().astype(np.float64)
+    mu, cov = blr.posterior(X, y, noise, 1.0)
+    mean = w @ th
+    sd = np.sqrt(np.diag(cov))
+    assert np.all(np.abs(mean - mu) < 0.25 * sd)
+    c = (th - mean).T @ ((th - mean) * w[:, None])
+    np.testing.assert_allclose(np.sqrt(np.diag(c)), sd, rtol=0.08)
+    pm = s.posterior_mean().cpu().numpy()
+    np.testing.assert_allclose(pm, mean, rtol=1e-6, atol=1e-9)
+    s.close()
+
+
+def _fresh(P, seed=9, J=48):
+    X, y = smc_inputs.blobs(512, seed=4)
+    cfg = P.SMCConfig(widths=[2, 16, 2], n_particles=J, activation="tanh", step_size=0.05, seed=seed)
+    return P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=128, lambda0=4.0), X, y
+
+
+def test_runs_are_bitwise_reproducible():
+    cuda()
+    P = lib()
+    outs = []
+    for _ in range(2):
+        s, _, _ = _fresh(P)
+        for m in [256, 384, 512]:
+            s.step(m, 512 / m, info=False)
+            s.resample()
+        st = s.state()
+        outs.append((st["theta"].cpu().numpy(), st["logw"].cpu().numpy()))
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_checkpoint_resume_is_exact():
+    cuda()
+    P = lib()
+    a, _, _ = _fresh(P)
+    a.step(256, 2.0, info=False)
+    a.resample()
+    ck = a.state()
+    a.step(384, 512 / 384, info=False)
+    a.resample()
+    a.step(512, 1.0, info=False)
+    ref = a.state()
+    b, _, _ = _fresh(P, seed=9)
+    b.step(256, 2.0, info=False)  # bring the subset to the checkpoint's size
+    b.set_state(ck["theta"], ck["logw"], ck["logpi"], ck["rng_counter"])
+    b.step(384, 512 / 384, info=False)
+    b.resample()
+    b.step(512, 1.0, info=False)
+    got = b.state()
+    assert np.array_equal(got["theta"].cpu().numpy(), ref["theta"].cpu().numpy())
+    assert np.array_equal(got["logw"].cpu().numpy(), ref["logw"].cpu().numpy())
+    a.close()
+    b.close()
+
+
+def test_nonfinite_particles():
+    cuda()
+    P = lib()
+    X, y = smc_inputs.blobs(256, seed=4)
+    th = smc_inputs.prior_draw(1, 8, 82, 1.0)
+    th[3, 10] = np.nan
+    cfg = P.SMCConfig(widths=[2, 16, 2], n_particles=8, activation="tanh", step_size=1e-3)
+    s = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=256, lambda0=1.0, theta0=to_dev(th))
+    lw = s.state()["logw"].cpu().numpy()
+    assert lw[3] == -np.inf and np.all(np.isfinite(np.delete(lw, 3)))
+    info = s.step(256, 1.0)
+    assert info["n_nonfinite"] >= 1
+    s.close()
+    th[:, 0] = np.nan
+    with pytest.raises(P.SMCError) as e:
+        P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=256, lambda0=1.0, theta0=to_dev(th))
+    assert e.value.status == 5
+
+
+def test_argument_errors():
+    cuda()
+    P = lib()
+    s, X, y = _fresh(P)
+    s.step(256, 2.0, info=False)
+    with pytest.raises(P.SMCError) as e:
+        s.step(128, 4.0)  # the subset only grows
+    assert e.value.status == 1
+    with pytest.raises(P.SMCError):
+        s.step(10 ** 6, 1.0)
+    with pytest.raises(P.SMCError):
+        s.resample("always", u=1.5)
+    s.close()
