@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Throughput and time-to-accuracy of the data-annealed SMC sampler on one MI355X.
+
+Workload (synthetic stand-in for the paper's MNIST experiments, which need a data
+set that is not available here): 28x28 grey class-template images, 60,000 train /
+10,000 test, MLP 784-100-10 ReLU, N(0, 1) prior, J = 256 particles, Linear
+annealing schedule C = kappa = 1000 over K = 60 iterations (M_k = 1000 k + 1000,
+full batch from k = 54), Langevin moves with h = 0.002, systematic resampling
+when ESS < J/2.
+
+One "step" is one SMC iteration: the gradient pass on the grown subset, the
+move with its gradient pass, the FP64 reweighting/normalisation/ESS and the
+(device-decided) resampling.  `value` is particle-sample gradient evaluations
+per second (sum over gradient passes of J * M_k, divided by the wall time of
+the timed steps) of the BF16 sampler; the FP32 sampler, time-to-accuracy, the
+dominant kernel's roofline fraction and the CPU oracle are reported beside it.
+
+    python bench.py [--gpus 1] [--steps 60] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WIDTHS = [784, 100, 10]
+J = 256
+N_TRAIN, N_TEST = 60000, 10000
+K_FULL = 60
+C0 = KAPPA = 1000
+STEP = 0.002
+PEAK = {"bf16": 2500.0, "fp32": 157.3}  # dense MFMA TFLOP/s (MI355X datasheet)
+HBM_PEAK = 8000.0  # GB/s
+ALU_PEAK = 157.3   # fp32 vector TFLOP/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=K_FULL)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
+    return ap.parse_args()
+
+
+def make_data():
+    import smc_inputs
+    X, y = smc_inputs.templates28(N_TRAIN, seed=0)
+    Xt, yt = smc_inputs.templates28(N_TEST, seed=1)
+    perm = smc_inputs.annealing_permutation(N_TRAIN, seed=2)
+    return X[perm], y[perm].astype(np.int32), Xt, yt.astype(np.int32)
+
+
+def passes(sizes, k):
+    """gradient passes of iteration k: one for the grown subset (if it grew) + one per leapfrog step"""
+    return 1 + (1 if sizes[k] != sizes[k - 1] else 0)
+
+
+def run_timed(P, dev, prec, sizes, steps, warmup, seed):
+    import torch
+    X, y = dev["X"], dev["y"]
+    cfg = P.SMCConfig(widths=WIDTHS, n_particles=J, activation="relu", precision=prec, step_size=STEP,
+                      prior_std=1.0, seed=seed)
+    if warmup > 0:
+        w = P.SMCSampler(cfg, X, y, m0=sizes[0], lambda0=N_TRAIN / sizes[0])
+        for k in range(1, min(warmup, len(sizes) - 1) + 1):
+            w.step(sizes[k], N_TRAIN / sizes[k], info=False)
+            w.resample()
+        torch.cuda.synchronize()
+        w.close()
+    s = P.SMCSampler(cfg, X, y, m0=sizes[0], lambda0=N_TRAIN / sizes[0])
+    s.resample()
+    s.profile(True)
+    s.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        s.step(sizes[k], N_TRAIN / sizes[k], info=False)
+        s.resample()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_read()
+    s.close()
+    evals = sum(J * passes(sizes, k) * sizes[k] for k in range(1, steps + 1))
+    return {"seconds": t1 - t0, "evals": evals, "rate": evals / (t1 - t0), "prof": prof}
+
+
+def run_tta(P, dev, prec, sizes, steps, seed):
+    """Cumulative wall time (init + steps, evaluation excluded) and test accuracy per iteration."""
+    import torch
+    cfg = P.SMCConfig(widths=WIDTHS, n_particles=J, activation="relu", precision=prec, step_size=STEP,
+                      prior_std=1.0, seed=seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = P.SMCSampler(cfg, dev["X"], dev["y"], m0=sizes[0], lambda0=N_TRAIN / sizes[0])
+    s.resample()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    trace = []
+    for k in range(1, steps + 1):
+        t = time.perf_counter()
+        s.step(sizes[k], N_TRAIN / sizes[k], info=False)
+        s.resample()
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t
+        r = s.predict(dev["Xt"], dev["yt"])
+        trace.append((k, elapsed, r["accuracy"], r["mean_log_pred"]))
+    s.close()
+    return trace
+
+
+def kernel_table(prof, prec):
+    out = {}
+    for name, (ms, n, fl, by) in prof.items():
+        if n == 0:
+            continue
+        e = {"total_ms": round(ms, 4), "launches": n, "avg_us": round(1e3 * ms / n, 3)}
+        if fl > 0:
+            e["tflops"] = round(fl / (ms * 1e-3) / 1e12, 2)
+        if by > 0:
+            e["gbps"] = round(by / (ms * 1e-3) / 1e9, 1)
+        out[name] = e
+    return out
+
+
+def roofline(prof, prec):
+    # dominant kernel class by total time
+    name, (ms, n, fl, by) = max(prof.items(), key=lambda kv: kv[1][0])
+    if fl > 0 and name.startswith("gemm"):
+        ach = fl / (ms * 1e-3) / 1e12
+        peak = PEAK[prec]
+        return {"kernel": name, "bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": None,
+                "avg_launch_us": round(1e3 * ms / n, 3), "flops_per_launch": fl / n}
+    if by > 0:
+        ach = by / (ms * 1e-3) / 1e9
+        return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK, 4), "traffic": None, "avg_launch_us": round(1e3 * ms / n, 3)}
+    ach = fl / (ms * 1e-3) / 1e12
+    return {"kernel": name, "bound": "alu", "achieved": round(ach, 2), "peak": ALU_PEAK, "unit": "TFLOP/s",
+            "frac": round(ach / ALU_PEAK, 4), "traffic": None, "avg_launch_us": round(1e3 * ms / n, 3)}
+
+
+def cpu_baseline(X, y, sizes, budget_s=12.0, J_s=8):
+    """The FP64 oracle on the host cores: iterations k = 1, 2, ... of the same schedule
+    with J_s particles until about budget_s seconds of work; rate in grad evals/s."""
+    from oracle import smc as osmc
+    import smc_inputs
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    D = sum(WIDTHS[i + 1] * (WIDTHS[i] + 1) for i in range(len(WIDTHS) - 1))
+    th0 = smc_inputs.prior_draw(5, J_s, D, 1.0)
+    o = osmc.Sampler(X[: sizes[-1]], y[: sizes[-1]], WIDTHS, "relu", step_size=STEP)
+    o.init(th0, sizes[0], N_TRAIN / sizes[0])
+    evals, t_used, k = 0, 0.0, 0
+    while t_used < budget_s and k + 1 < len(sizes):
+        k += 1
+        xi = smc_inputs.momenta(100 + k, (J_s, D))
+        t = time.perf_counter()
+        o.step(sizes[k], N_TRAIN / sizes[k], xi)
+        o.resample(0.5)
+        t_used += time.perf_counter() - t
+        evals += J_s * passes(sizes, k) * sizes[k]
+    return {"value": evals / t_used, "unit": "grad-evals/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"FP64 NumPy oracle, J={J_s} particles, SMC iterations k=1..{k} of the same schedule "
+                      f"(M_k up to {sizes[k]}), {t_used:.1f} s of host time"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
+              "(particles would shard across GPUs, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2601_21983_amd as P
+    from paper_2601_21983_amd import schedules
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    steps = max(1, min(args.steps, K_FULL))
+    sizes = schedules.sizes("linear", K_FULL, N_TRAIN, C0, KAPPA)
+    t = time.perf_counter()
+    X, y, Xt, yt = make_data()
+    log(f"data generated in {time.perf_counter() - t:.1f} s")
+    cuda = torch.device("cuda")
+    dev = {"X": torch.from_numpy(X).to(cuda), "y": torch.from_numpy(y).to(cuda),
+           "Xt": torch.from_numpy(Xt).to(cuda), "yt": torch.from_numpy(yt).to(cuda)}
+
+    res = {}
+    for prec in ("bf16", "fp32"):
+        r = run_timed(P, dev, prec, sizes, steps, args.warmup, args.seed)
+        res[prec] = r
+        log(f"{prec}: {steps} steps in {r['seconds']:.3f} s, {r['rate']:.4g} grad-evals/s")
+        log(json.dumps(kernel_table(r["prof"], prec)))
+
+    tta = None
+    if not args.no_tta:
+        traces = {p: run_tta(P, dev, p, sizes, steps, args.seed) for p in ("fp32", "bf16")}
+        target = traces["fp32"][-1][2] - 0.005
+        tta = {"target_accuracy": round(target, 4)}
+        for p, tr in traces.items():
+            hit = next((e for e in tr if e[2] >= target), None)
+            tta[p] = {"seconds": round(hit[1], 4) if hit else None, "iteration": hit[0] if hit else None,
+                      "final_accuracy": round(tr[-1][2], 4), "final_mean_log_pred": round(tr[-1][3], 5)}
+        log("time-to-accuracy: " + json.dumps(tta))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(X, y, sizes)
+        log(f"cpu baseline: {cpu}")
+
+    b = res["bf16"]
+    line = {
+        "metric": "particle-sample gradient evaluations per second",
+        "value": round(b["rate"], 1),
+        "unit": "grad-evals/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * b["seconds"] / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "MNIST-shaped synthetic templates 60000/10000, MLP 784-100-10 ReLU, J=256, "
+                               "Linear schedule C=kappa=1000 K=60, Langevin h=0.002, systematic resampling",
+                   "particles": J, "iterations": steps, "proposal": "fixed", "precision": "bf16"},
+        "roofline": roofline(b["prof"], "bf16"),
+        "cpu_baseline": cpu,
+        "fp32_plain": {"value": round(res["fp32"]["rate"], 1), "unit": "grad-evals/s",
+                       "ms_per_step": round(1e3 * res["fp32"]["seconds"] / steps, 4),
+                       "roofline": roofline(res["fp32"]["prof"], "fp32")},
+        "time_to_accuracy": tta,
+        "kernels": {"bf16": kernel_table(b["prof"], "bf16"), "fp32": kernel_table(res["fp32"]["prof"], "fp32")},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

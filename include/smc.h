@@ -223,6 +223,38 @@ SMC_API int64_t smc_n_params(smc_t h);
 /* Samples per activation chunk chosen from act_budget_bytes (for tests). */
 SMC_API int64_t smc_chunk_samples(smc_t h);
 
+/* ---------------------------------------------------------------- kernel timing */
+/*
+ * Kernel classes timed by the profiling hook.  FLOP and byte counts are the
+ * algorithmic work of each launch (unpadded sizes): GEMMs 2*M*N*K, the output
+ * layer 6*C*H per particle-sample, moves the parameter bytes they must touch.
+ */
+enum {
+  SMC_K_GEMM_FWD1 = 0,   /* layer-1 forward GEMM over all particles' units */
+  SMC_K_GEMM_DW1 = 1,    /* layer-1 weight-gradient GEMM */
+  SMC_K_GEMM_OTHER = 2,  /* GEMMs of layers >= 2 */
+  SMC_K_HEAD = 3,        /* output layer, likelihood and its reduction */
+  SMC_K_MOVE = 4,        /* leapfrog / Langevin parameter updates */
+  SMC_K_WEIGHT = 5,      /* log-weight update, normalisation, ESS */
+  SMC_K_RESAMPLE = 6,    /* systematic resampling + row gather + re-cast */
+  SMC_K_OTHER = 7,
+  SMC_K_COUNT = 8
+};
+
+/*
+ * enable != 0: from now on every kernel launch of the handle is bracketed by a
+ * pair of HIP events recorded on the handle's stream.  enable == 0 stops
+ * recording.  Records accumulate until smc_profile_read.
+ */
+SMC_API smc_status smc_profile(smc_t h, int32_t enable);
+
+/*
+ * Synchronise, then for each class k < SMC_K_COUNT write total_ms[k] (summed
+ * event time), launches[k], flops[k] and bytes[k] (algorithmic totals).  Any
+ * pointer may be NULL.  Clears the records.
+ */
+SMC_API smc_status smc_profile_read(smc_t h, double* total_ms, int64_t* launches, double* flops, double* bytes);
+
 /* ---------------------------------------------------------------- stateless kernels */
 
 /*

@@ -94,7 +94,12 @@ _SIGS = {
     "smc_normalise": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "smc_systematic_resample": (_i32, [_vp, _i32, _d, _vp, _vp, _vp]),
     "smc_philox": (_i32, [_u32, _u32, _u32, _u32, _u32, _i64, _vp, _vp]),
+    "smc_profile": (_i32, [_handle, _i32]),
+    "smc_profile_read": (_i32, [_handle, C.POINTER(_d), C.POINTER(_i64), C.POINTER(_d), C.POINTER(_d)]),
 }
+
+SMC_K_NAMES = ("gemm_fwd1", "gemm_dw1", "gemm_other", "head", "move", "weight", "resample", "other")
+SMC_K_COUNT = len(SMC_K_NAMES)
 
 EXPORTED = tuple(_SIGS)
 
@@ -215,3 +220,17 @@ def smc_systematic_resample(w_dev, J: int, u: float, ancestors_dev, placement_de
 
 def smc_philox(key0: int, key1: int, c1: int, c2: int, c3: int, n_blocks: int, out_dev, stream) -> None:
     _check(lib.smc_philox(key0, key1, c1, c2, c3, n_blocks, _opt(out_dev), _opt(stream)), "smc_philox")
+
+
+def smc_profile(h, enable: bool) -> None:
+    _check(lib.smc_profile(h, 1 if enable else 0), "smc_profile")
+
+
+def smc_profile_read(h) -> dict:
+    """{class name: (total_ms, launches, algorithmic flops, algorithmic bytes)}"""
+    t = (C.c_double * SMC_K_COUNT)()
+    n = (C.c_int64 * SMC_K_COUNT)()
+    f = (C.c_double * SMC_K_COUNT)()
+    b = (C.c_double * SMC_K_COUNT)()
+    _check(lib.smc_profile_read(h, t, n, f, b), "smc_profile_read")
+    return {SMC_K_NAMES[k]: (t[k], n[k], f[k], b[k]) for k in range(SMC_K_COUNT)}

@@ -127,6 +127,12 @@ __global__ void transpose_w_kernel(const float* theta, int64_t D, int64_t off, i
   }
 }
 
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
 struct LayerBufs {
   void* act = nullptr;   // [mc x J*nout] (hidden layers)
   void* actT = nullptr;  // [J x (nout+1) x mc] (hidden layers feeding another hidden layer)
@@ -182,11 +188,40 @@ struct smc_handle {
   int64_t logp_n = 0;
   double* per_sample = nullptr;
   double* pred_out = nullptr;
+  // kernel timing (smc_profile)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_pool;
+  std::vector<ProfRec> prof_recs;
 };
 
 namespace {
 
 void sync(smc_t h) { HIPCHECK(hipStreamSynchronize(h->stream)); }
+
+hipEvent_t prof_event(smc_t h) {
+  if (!h->prof_pool.empty()) {
+    hipEvent_t e = h->prof_pool.back();
+    h->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHECK(hipEventCreate(&e));
+  return e;
+}
+
+// Run `launch` bracketed by events on the handle's stream when profiling is on.
+template <typename F>
+void timed(smc_t h, int cls, double flops, double bytes, F&& launch) {
+  if (!h->prof_on) {
+    launch();
+    return;
+  }
+  ProfRec r{cls, prof_event(h), prof_event(h), flops, bytes};
+  HIPCHECK(hipEventRecord(r.a, h->stream));
+  launch();
+  HIPCHECK(hipEventRecord(r.b, h->stream));
+  h->prof_recs.push_back(r);
+}
 
 uint32_t key0(smc_t h) { return (uint32_t)(h->cfg.seed & 0xffffffffu); }
 uint32_t key1(smc_t h) { return (uint32_t)(h->cfg.seed >> 32); }
@@ -373,14 +408,16 @@ void transpose_weights(smc_t h, const float* theta) {
   }
 }
 
-void gemm(smc_t h, const GemmParams& p) {
-  const hipError_t e = gemm_run(p, h->bf16 ? GEMM_BF16 : GEMM_F32, h->stream);
-  if (e != hipSuccess) fail(SMC_ERR_DEVICE, std::string("GEMM launch failed: ") + hipGetErrorString(e));
+void gemm(smc_t h, const GemmParams& p, int cls, double flops) {
+  timed(h, cls, flops, 0.0, [&]() {
+    const hipError_t e = gemm_run(p, h->bf16 ? GEMM_BF16 : GEMM_F32, h->stream);
+    if (e != hipSuccess) fail(SMC_ERR_DEVICE, std::string("GEMM launch failed: ") + hipGetErrorString(e));
+  });
 }
 
 // Forward through the hidden layers for samples [c0, c0 + rows) of the operand X
 // (ldx-strided rows).  Writes act_l (and actT_l when a hidden layer follows).
-void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows) {
+void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows, int m_valid) {
   const int J = h->J;
   for (int l = 0; l < h->L - 1; ++l) {
     const int nout = h->net.nout[l];
@@ -432,7 +469,8 @@ void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows) {
         p.out1.rstr = 1;
       }
     }
-    gemm(h, p);
+    const double fl = 2.0 * m_valid * (double)U * (l == 0 ? h->F : h->net.nin[l]);
+    gemm(h, p, l == 0 ? SMC_K_GEMM_FWD1 : SMC_K_GEMM_OTHER, fl);
   }
 }
 
@@ -485,7 +523,7 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
     const int mcv = (int)std::min<int64_t>(h->mc, m - c0);
     const int rows = (int)round_up(mcv, 64);
     const int beta = c0 > 0 ? 1 : 0;
-    forward_hidden(h, h->X, c0, rows);
+    forward_hidden(h, h->X, c0, rows, mcv);
     HeadArgs a = head_args(h, theta);
     if (L == 1) a.A = (const char*)h->X + c0 * h->ldx * (int64_t)h->esz;
     a.m_valid = mcv;
@@ -506,7 +544,8 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
         a.sdRm = (int64_t)J * a.H;
       }
     }
-    HIPCHECK(head_run(a, train ? HEAD_TRAIN : HEAD_FORWARD, h->bf16, h->stream));
+    timed(h, SMC_K_HEAD, (train ? 6.0 : 2.0) * a.C * (double)a.H * J * mcv, 0.0,
+          [&]() { HIPCHECK(head_run(a, train ? HEAD_TRAIN : HEAD_FORWARD, h->bf16, h->stream)); });
     if (!train) continue;
     // backward through the hidden layers, top down
     for (int l = L - 2; l >= 0; --l) {
@@ -541,7 +580,7 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
           p.out0.sb = h->D;
           p.out0.rstr = nin + 1;
         }
-        gemm(h, p);
+        gemm(h, p, l == 0 ? SMC_K_GEMM_DW1 : SMC_K_GEMM_OTHER, 2.0 * J * nout * (double)(nin + 1) * mcv);
       }
       if (l >= 1) {
         // error of the layer below: (delta_l W_l) * act'(a_{l-1}), written sample-contiguous
@@ -570,7 +609,7 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
           p.out1.sb = nin;
           p.out1.rstr = (int64_t)J * nin;
         }
-        gemm(h, p);
+        gemm(h, p, SMC_K_GEMM_OTHER, 2.0 * J * nout * (double)nin * mcv);
       }
     }
   }
@@ -579,7 +618,8 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
 
 void ensure_cast(smc_t h) {
   if (!h->w_dirty) return;
-  HIPCHECK(cast_run(h->net, h->theta, nullptr, h->stream));
+  timed(h, SMC_K_OTHER, 0.0, (double)h->J * h->D * (4.0 + h->esz),
+        [&]() { HIPCHECK(cast_run(h->net, h->theta, nullptr, h->stream)); });
   h->w_dirty = false;
 }
 
@@ -732,6 +772,8 @@ void smc_destroy(smc_t h) {
   if (h->tx) (void)hipFree(h->tx);
   if (h->logp) (void)hipFree(h->logp);
   if (h->per_sample) (void)hipFree(h->per_sample);
+  for (auto& r : h->prof_recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  for (auto e : h->prof_pool) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -756,12 +798,16 @@ smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info) 
     const int S = h->cfg.leapfrog_steps;
     MoveArgs ma = move_args(h, MOVE_FIRST);
     if (h->noise_pending) ma.noise = h->noise;
-    HIPCHECK(move_run(ma, h->stream));
+    const double nd = (double)h->J * h->D;
+    // FIRST: read theta, g (+noise); write P, theta and the GEMM copy
+    timed(h, SMC_K_MOVE, 0.0, nd * (16.0 + h->esz + (ma.noise ? 4.0 : 0.0)),
+          [&]() { HIPCHECK(move_run(ma, h->stream)); });
     h->noise_pending = false;
     for (int s = 1; s <= S; ++s) {
       grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g);
       MoveArgs mb = move_args(h, s < S ? MOVE_MID : MOVE_LAST);
-      HIPCHECK(move_run(mb, h->stream));
+      // MID: read theta, g, P; write P, theta, copy.  LAST: read P, g, theta
+      timed(h, SMC_K_MOVE, 0.0, nd * (s < S ? 20.0 + h->esz : 12.0), [&]() { HIPCHECK(move_run(mb, h->stream)); });
     }
     WeightArgs wa;
     wa.J = h->J;
@@ -775,7 +821,7 @@ smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info) 
     wa.logw = h->logw;
     wa.w = h->w;
     wa.stats = h->stats;
-    HIPCHECK(weight_run(wa, h->stream));
+    timed(h, SMC_K_WEIGHT, 0.0, 0.0, [&]() { HIPCHECK(weight_run(wa, h->stream)); });
     if (info) fill_info(h, info, h->grad_evals - ev0);
   });
 }
@@ -806,9 +852,11 @@ smc_status smc_resample(smc_t h, int32_t mode, const double* u, int32_t* resampl
     ra.placement = h->place;
     ra.sc[0] = h->ll;
     ra.sc[1] = h->lp;
-    HIPCHECK(resample_run(ra, h->stream));
-    HIPCHECK(gather_rows_run(h->J, h->D, h->place, h->theta, h->g, h->stream));
-    if (!h->w_dirty) HIPCHECK(cast_run(h->net, h->theta, h->place, h->stream));
+    timed(h, SMC_K_RESAMPLE, 0.0, 0.0, [&]() {
+      HIPCHECK(resample_run(ra, h->stream));
+      HIPCHECK(gather_rows_run(h->J, h->D, h->place, h->theta, h->g, h->stream));
+      if (!h->w_dirty) HIPCHECK(cast_run(h->net, h->theta, h->place, h->stream));
+    });
     if (resampled || ancestors_host) {
       double st[8];
       read_stats(h, st);
@@ -857,7 +905,7 @@ smc_status smc_posterior_predict(smc_t h, const float* x_dev, const int32_t* y_d
     for (int64_t c0 = 0; c0 < n; c0 += h->mc) {
       const int mcv = (int)std::min<int64_t>(h->mc, n - c0);
       const int rows = (int)round_up(mcv, 64);
-      forward_hidden(h, h->tx, c0, rows);
+      forward_hidden(h, h->tx, c0, rows, mcv);
       HeadArgs a = head_args(h, h->theta);
       if (h->L == 1) a.A = (const char*)h->tx + c0 * h->ldx * (int64_t)h->esz;
       a.m_valid = mcv;
@@ -983,6 +1031,38 @@ smc_status smc_nn_backward(smc_t h, const float* theta_dev, int64_t m, const dou
     const int64_t ev = h->grad_evals;
     grad_pass(h, theta_dev, m, 1.0, scale_dev, ll, grad_dev);
     h->grad_evals = ev;  // not part of the sampler's own accounting
+  });
+}
+
+smc_status smc_profile(smc_t h, int32_t enable) {
+  if (!h) return SMC_ERR_ARG;
+  h->prof_on = enable != 0;
+  return SMC_OK;
+}
+
+smc_status smc_profile_read(smc_t h, double* total_ms, int64_t* launches, double* flops, double* bytes) {
+  return run([&]() {
+    if (!h) fail(SMC_ERR_ARG, "null handle");
+    sync(h);
+    double t[SMC_K_COUNT] = {0}, f[SMC_K_COUNT] = {0}, b[SMC_K_COUNT] = {0};
+    int64_t n[SMC_K_COUNT] = {0};
+    for (const ProfRec& r : h->prof_recs) {
+      float ms = 0.0f;
+      HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
+      t[r.cls] += ms;
+      n[r.cls] += 1;
+      f[r.cls] += r.flops;
+      b[r.cls] += r.bytes;
+      h->prof_pool.push_back(r.a);
+      h->prof_pool.push_back(r.b);
+    }
+    h->prof_recs.clear();
+    for (int k = 0; k < SMC_K_COUNT; ++k) {
+      if (total_ms) total_ms[k] = t[k];
+      if (launches) launches[k] = n[k];
+      if (flops) flops[k] = f[k];
+      if (bytes) bytes[k] = b[k];
+    }
   });
 }
 

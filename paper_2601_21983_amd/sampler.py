@@ -167,6 +167,14 @@ class SMCSampler:
     def chunk_samples(self) -> int:
         return L.smc_chunk_samples(self.handle)
 
+    def profile(self, enable: bool = True) -> None:
+        """Bracket every kernel launch with HIP events on the sampler's stream."""
+        L.smc_profile(self.handle, enable)
+
+    def profile_read(self) -> dict:
+        """{kernel class: (total_ms, launches, algorithmic flops, algorithmic bytes)}; clears the records."""
+        return L.smc_profile_read(self.handle)
+
     # ---------------------------------------------------------------- network passes
     def nn_forward(self, theta: torch.Tensor, m: int) -> torch.Tensor:
         ll = torch.empty(self.J, dtype=torch.float64, device=theta.device)
