@@ -67,7 +67,20 @@ __device__ __forceinline__ int64_t split_at(const OutDesc& d, const SplitIdx& s,
   return s.colpart + (int64_t)rq * d.sR + (int64_t)rr * d.rstr;
 }
 
-template <typename T, int BM, int BN, int WM, int WN, int EPI>
+template <int ACT>
+__device__ __forceinline__ float act_apply(float v) {
+  if constexpr (ACT == ACT_RELU) return fmaxf(v, 0.0f);
+  else if constexpr (ACT == ACT_TANH) return tanhf(v);
+  else return v;
+}
+template <int ACT>
+__device__ __forceinline__ float act_deriv(float a) {
+  if constexpr (ACT == ACT_RELU) return a > 0.0f ? 1.0f : 0.0f;
+  else return 1.0f - a * a;
+}
+
+// ACT: activation of the FWD epilogue / derivative of the DELTA epilogue (-1: none)
+template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT>
 __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
   constexpr int VEC = Mf<T>::VEC;
   constexpr int BKE = ROW_BYTES / (int)sizeof(T);
@@ -81,8 +94,27 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
 
   __shared__ __attribute__((aligned(16))) char smem[2 * STAGE];
 
-  const int b = blockIdx.z;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int b = blockIdx.y;
+  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+  // renumber them so that each XCD receives a contiguous range of tiles, and walk
+  // that range in groups of GROUP_M row-tiles per column-tile (the group's A panels
+  // stay in the XCD's L2 while the B panel streams once per group).
+  int tm, tn;
+  {
+    const int nM = (p.M + BM - 1) / BM, nN = (p.N + BN - 1) / BN;
+    const int ntiles = nM * nN;
+    const int pid = blockIdx.x;
+    int t = pid;
+    if (ntiles % 8 == 0) t = (pid % 8) * (ntiles / 8) + pid / 8;
+    constexpr int GROUP_M = 8;
+    const int group = t / (GROUP_M * nN);
+    const int first_m = group * GROUP_M;
+    const int gm = min(nM - first_m, GROUP_M);
+    const int r = t - group * GROUP_M * nN;
+    tm = first_m + r % gm;
+    tn = r / gm;
+  }
+  const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / NWN, wn = wave % NWN;
   const T* __restrict__ A = (const T*)p.A + (int64_t)b * p.sAb;
@@ -182,6 +214,9 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
     static_assert(SLAB_BYTES + NWM * 32 * 8 <= 2 * STAGE, "slab does not fit in LDS");
     static_assert(THREADS % BN == 0, "copy loop assumes BN divides the workgroup");
     int64_t* rowaddr = (int64_t*)(smem + SLAB_BYTES);
+    constexpr int VOA = 16 / (int)sizeof(O);
+    const bool vec_ok = ((uintptr_t)p.out0.ptr % 16 == 0) && p.out0.rstr % VOA == 0 && p.out0.sR % VOA == 0 &&
+                        p.out0.sb % VOA == 0 && n0 % VOA == 0;
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
       // each wave drops its 32-row block i into the slab
@@ -195,10 +230,7 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
         for (int q = 0; q < 16; ++q) {
           const int lr = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
           float v = acc[i][j][q];
-          if (EPI == EPI_FWD) {
-            v += bias;
-            if (p.act >= 0) v = act_fwd(v, p.act);
-          }
+          if (EPI == EPI_FWD) v = act_apply<ACT>(v + bias);
           slab[lr * SROW + lc] = cvt_out<O>(v);
         }
       }
@@ -209,18 +241,46 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
       }
       __syncthreads();
       // the whole workgroup copies the slab rows out, consecutive lanes on consecutive columns
-      const int lc = tid % BN;
-      const int col = n0 + lc;
-      if (col < N) {
-        for (int lr = tid / BN; lr < NWM * 32; lr += THREADS / BN) {
+      constexpr int VO = 16 / (int)sizeof(O);   // elements per 16-byte vector
+      constexpr int VPR = BN / VO;              // vectors per slab row
+      if (vec_ok) {
+        for (int e = tid; e < NWM * 32 * VPR; e += THREADS) {
+          const int lr = e / VPR, lc = (e - lr * VPR) * VO;
           const int64_t ra = rowaddr[lr];
-          if (ra < 0) continue;
+          const int col = n0 + lc;
+          if (ra < 0 || col >= N) continue;
           O* dst = (O*)p.out0.ptr + ra + col;
-          if (EPI == EPI_GRAD) {
-            const float v = cvt_in<O>(slab[lr * SROW + lc]);
-            *dst = p.beta ? *dst + v : v;
+          const O* src = slab + lr * SROW + lc;
+          if (col + VO <= N) {
+            u32x4 v = *(const u32x4*)src;
+            if (EPI == EPI_GRAD && p.beta) {
+              f32x4 a = __builtin_bit_cast(f32x4, v), o = *(const f32x4*)dst;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) a[q] += o[q];
+              v = __builtin_bit_cast(u32x4, a);
+            }
+            *(u32x4*)dst = v;
           } else {
-            *dst = slab[lr * SROW + lc];
+            for (int q = 0; q < N - col; ++q) {
+              if (EPI == EPI_GRAD) dst[q] = p.beta ? dst[q] + src[q] : src[q];
+              else dst[q] = src[q];
+            }
+          }
+        }
+      } else {
+        const int lc = tid % BN;
+        const int col = n0 + lc;
+        if (col < N) {
+          for (int lr = tid / BN; lr < NWM * 32; lr += THREADS / BN) {
+            const int64_t ra = rowaddr[lr];
+            if (ra < 0) continue;
+            O* dst = (O*)p.out0.ptr + ra + col;
+            if (EPI == EPI_GRAD) {
+              const float v = cvt_in<O>(slab[lr * SROW + lc]);
+              *dst = p.beta ? *dst + v : v;
+            } else {
+              *dst = slab[lr * SROW + lc];
+            }
           }
         }
       }
@@ -251,11 +311,10 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
           *g = p.beta ? *g + v : v;
         } else {
           if (EPI == EPI_FWD) {
-            v += bias;
-            if (p.act >= 0) v = act_fwd(v, p.act);
+            v = act_apply<ACT>(v + bias);
           } else {
             const float a = cvt_in<T>(*((const T*)p.aux.ptr + split_at(p.aux, sa, dr)));
-            v *= act_grad_from_out(a, p.act);
+            v *= act_deriv<ACT>(a);
           }
           *((T*)p.out0.ptr + split_at(p.out0, s0, dr)) = cvt_out<T>(v);
           if (p.out1.ptr) *((T*)p.out1.ptr + split_at(p.out1, s1, dr)) = cvt_out<T>(v);
@@ -265,16 +324,29 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
   }
 }
 
+template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT>
+hipError_t launch_one(const GemmParams& p, dim3 grid, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI, ACT>), grid, dim3(THREADS), 0, s, p);
+  return hipGetLastError();
+}
+
 template <typename T, int BM, int BN, int WM, int WN>
 hipError_t launch_cfg(const GemmParams& p, hipStream_t s) {
-  dim3 grid((p.N + BN - 1) / BN, (p.M + BM - 1) / BM, p.batch);
+  const int64_t ntiles = (int64_t)((p.N + BN - 1) / BN) * ((p.M + BM - 1) / BM);
+  if (ntiles > 0x7fffffff || p.batch > 65535) return hipErrorInvalidValue;
+  dim3 grid((unsigned)ntiles, p.batch);
   switch (p.epi) {
-    case EPI_FWD: hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI_FWD>), grid, dim3(THREADS), 0, s, p); break;
-    case EPI_GRAD: hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI_GRAD>), grid, dim3(THREADS), 0, s, p); break;
-    case EPI_DELTA: hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI_DELTA>), grid, dim3(THREADS), 0, s, p); break;
+    case EPI_FWD:
+      if (p.act == ACT_RELU) return launch_one<T, BM, BN, WM, WN, EPI_FWD, ACT_RELU>(p, grid, s);
+      if (p.act == ACT_TANH) return launch_one<T, BM, BN, WM, WN, EPI_FWD, ACT_TANH>(p, grid, s);
+      return launch_one<T, BM, BN, WM, WN, EPI_FWD, -1>(p, grid, s);
+    case EPI_GRAD: return launch_one<T, BM, BN, WM, WN, EPI_GRAD, -1>(p, grid, s);
+    case EPI_DELTA:
+      if (p.act == ACT_RELU) return launch_one<T, BM, BN, WM, WN, EPI_DELTA, ACT_RELU>(p, grid, s);
+      if (p.act == ACT_TANH) return launch_one<T, BM, BN, WM, WN, EPI_DELTA, ACT_TANH>(p, grid, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace
@@ -285,7 +357,10 @@ hipError_t gemm_run(const GemmParams& p, int type, hipStream_t stream) {
   const int vec = type == GEMM_BF16 ? 8 : 4;
   if (p.K % vec || p.lda % vec || p.ldb % vec) return hipErrorInvalidValue;
   if (((uintptr_t)p.A | (uintptr_t)p.B) & 15) return hipErrorInvalidValue;
-  const bool big = (int64_t)p.M * p.N >= (int64_t)256 * 128 * 512;
+  // the 256x128 tile keeps its 128 accumulators in registers only with the lean
+  // epilogues (identity/ReLU forward, gradient); tanh and delta epilogues use 128x128
+  const bool lean = p.epi == EPI_GRAD || (p.epi == EPI_FWD && p.act != ACT_TANH);
+  const bool big = lean && (int64_t)p.M * p.N >= (int64_t)256 * 128 * 512;
   if (type == GEMM_BF16) {
     return big ? launch_cfg<__bf16, 256, 128, 128, 64>(p, stream) : launch_cfg<__bf16, 128, 128, 64, 64>(p, stream);
   }

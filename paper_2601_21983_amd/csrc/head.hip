@@ -1,40 +1,163 @@
-// Output layer of every particle's network: logits, log-likelihood, the
-// output-layer gradient and the error sent to the last hidden layer.
+// Output layer of every particle's network on the matrix cores: logits,
+// log-likelihood, the output-layer gradient and the error sent to the last
+// hidden layer.
 //
-// For particle j and a tile of 64 samples the kernel
-//   * stages the last hidden activations a_{L-1} (any layout, via strides) in LDS,
-//   * forms z = W_L a + b_L (W_L read from the FP32 master parameters),
-//   * categorical: log p = z_y - logsumexp(z), delta = lambda_j (onehot - softmax(z));
-//     Gaussian:    log p = -1/2 log(2 pi s^2) - (y - z)^2 / (2 s^2), delta = lambda_j (y - z) / s^2
-//     (the subset log-likelihood sum and its scaled gradient, Section 3, Eq. approx-grad),
-//   * accumulates dW_L (and db_L) = sum_i delta_i [a_i, 1] in registers,
-//   * writes delta_{L-1} = (W_L^T delta) * act'(a) transposed ([unit][sample]) for the
-//     weight-gradient GEMM of the layer below, and optionally row-major.
-// Log-likelihoods are accumulated in FP64 per thread in sample order and reduced
-// in a fixed order, so results do not depend on scheduling.
+// For particle j and a tile of 64 samples (one 16-sample block per wave):
+//   1. logits^T [16 classes x 16 samples] = Wc [16 x Hp] . A^T, where Wc holds
+//      [W_L | b_L] zero-padded to 16 classes and Hp = roundup(H + 1, 16) columns,
+//      and the staged activation tile A carries a column of ones at index H, so
+//      the bias rides along in the contraction;
+//   2. categorical: log p = z_y - logsumexp(z), delta = lambda (onehot - softmax(z));
+//      Gaussian: log p = -1/2 log(2 pi s^2) - (y - z)^2 / (2 s^2), delta = lambda (y - z) / s^2
+//      (the subset log-likelihood and its scaled gradient, Section 3, Eq. approx-grad).
+//      In the 16x16 accumulator layout a lane holds classes 4g..4g+3 (g = lane/16)
+//      of sample lane%16, so the softmax is a reduction over 4 registers and the
+//      lanes g = 0..3;
+//   3. delta_{L-1}^T [Hp x 16] = Wt [Hp x 16 classes] . delta^T: the accumulator of
+//      step 2 is already the B operand of this product; the result times act'(a) is
+//      staged in LDS and written sample-contiguous ([unit][sample]) for the
+//      weight-gradient GEMM of the layer below;
+//   4. dW_L [16 x Hp] += delta^T . [A | 1] over the tile's samples (bias column
+//      included), kept in registers across tiles; each wave owns every fourth
+//      16-column block.
+// MFMA forms: bf16 v_mfma_f32_16x16x16_bf16 (a lane supplies 4 consecutive K
+// values), fp32 v_mfma_f32_16x16x4_f32 issued four times over a 4-wide K slice
+// (instruction t takes component t; lane groups cover K offsets 4g + t), so both
+// precisions read 4 consecutive K values per lane.  Accumulator layout: lane l
+// holds rows 4(l/16) + i, column l % 16.
+// Log-likelihoods are summed in FP64 in a fixed order.
 #include "kernels.h"
 
 namespace smc {
 
 namespace {
 
-constexpr int HT = 64;        // samples per tile
+constexpr int HT = 64;  // samples per tile (16 per wave)
 constexpr int HTHREADS = 256;
-constexpr int MAXP = 40;      // register accumulators per thread for dW_L: C*(H+1) <= 40*256
+constexpr int MAXHB = 8;  // h-blocks per wave in the dW_L accumulator: Hp <= 4 * 16 * MAXHB = 512
+
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short s16x4;
+
+template <typename T> struct V4;
+template <> struct V4<__bf16> {
+  typedef s16x4 type;
+};
+template <> struct V4<float> {
+  typedef f32x4 type;
+};
+
+__device__ __forceinline__ f32x4 mma16(const s16x4& a, const s16x4& b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma16(const f32x4& a, const f32x4& b, f32x4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], c, 0, 0, 0);
+  return c;
+}
+
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type ld4(const T* p) {
+  return *(const typename V4<T>::type*)p;
+}
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type gather4(const T* p, int stride) {
+  typename V4<T>::type v;
+  if constexpr (sizeof(T) == 2) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = __builtin_bit_cast(short, p[t * stride]);
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = p[t * stride];
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type pack4(const float* x) {
+  typename V4<T>::type v;
+  if constexpr (sizeof(T) == 2) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = __builtin_bit_cast(short, to_bf16(x[t]));
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = x[t];
+  }
+  return v;
+}
+
+struct HeadLayout {
+  int Hp, AS, WT, DS, SS;  // padded widths / LDS row strides (elements)
+  int offWt, offAs, offDt, offSt, offRed, total;  // byte offsets
+  bool stage;
+};
+
+__host__ __device__ inline int rup(int x, int m) { return (x + m - 1) / m * m; }
+
+template <typename T>
+__host__ __device__ inline HeadLayout head_layout(int H, bool stage) {
+  HeadLayout L;
+  const int e = (int)sizeof(T);
+  L.Hp = rup(H + 1, 16);
+  L.AS = L.Hp + 16 / e * 2;  // pad: keeps 16 consecutive rows on distinct banks
+  L.WT = 16 + 8 / e * 2;
+  L.DS = HT + 16 / e;
+  L.SS = HT + 16 / e;
+  int off = 16 * L.AS * e;  // Wc [16][AS]
+  L.offWt = off;
+  off += L.Hp * L.WT * e;
+  off = rup(off, 16);
+  L.offAs = off;
+  off += HT * L.AS * e;
+  off = rup(off, 16);
+  L.offDt = off;
+  off += 16 * L.DS * e;
+  off = rup(off, 16);
+  L.offSt = off;
+  L.stage = stage;
+  if (stage) off += L.Hp * L.SS * e;
+  off = rup(off, 16);
+  L.offRed = off;
+  off += 16 * 4 * (int)sizeof(double) + 64 * (int)sizeof(float);
+  L.total = off;
+  return L;
+}
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a) {
-  extern __shared__ __attribute__((aligned(16))) float hs[];
-  const int H = a.H, C = a.C, HP = H + 1;  // HP: padded LDS row (odd stride for H even)
-  const int HS = (H | 1);
-  float* Ws = hs;                        // [C][HP]  (weights, bias in column H)
-  float* As = Ws + C * HP;               // [HT][HS]
-  float* Zs = As + HT * HS;              // [HT][C]  logits, then deltas
-  const int j = blockIdx.y;
-  const int split = blockIdx.x;
-  const int tid = threadIdx.x;
+__global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const HeadLayout Lo) {
+  extern __shared__ __attribute__((aligned(16))) char hsm[];
+  T* Wc = (T*)hsm;
+  T* Wt = (T*)(hsm + Lo.offWt);
+  T* As = (T*)(hsm + Lo.offAs);
+  T* Dt = (T*)(hsm + Lo.offDt);
+  T* St = (T*)(hsm + Lo.offSt);
+  double* red = (double*)(hsm + Lo.offRed);
+  float* bred = (float*)(red + 64);
+  const int H = a.H, C = a.C, Hp = Lo.Hp, AS = Lo.AS, WT = Lo.WT, DS = Lo.DS, SS = Lo.SS;
+  const int NHB = Hp / 16;
+  const int j = blockIdx.y, split = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, cl = lane & 15;
+
+  // weights of the output layer: Wc[c][h] = [W | b], Wt[h][c] = W^T (zero padded)
   const float* wsrc = a.theta + (int64_t)j * a.D + a.offL;
-  for (int e = tid; e < C * HP; e += HTHREADS) Ws[e] = wsrc[e];
+  for (int e = tid; e < 16 * AS; e += HTHREADS) {
+    const int c = e / AS, h = e - c * AS;
+    const float v = (c < C && h <= H) ? wsrc[c * (H + 1) + h] : 0.0f;
+    Wc[e] = cvt_out<T>(v);
+  }
+  if (MODE == HEAD_TRAIN) {
+    for (int e = tid; e < Hp * WT; e += HTHREADS) {
+      const int h = e / WT, c = e - h * WT;
+      const float v = (c < C && h < H) ? wsrc[c * (H + 1) + h] : 0.0f;
+      Wt[e] = cvt_out<T>(v);
+    }
+  }
+  // activation tile: columns >= H are constant (1 at H, 0 beyond) for the whole kernel
+  for (int e = tid; e < HT * (AS - H); e += HTHREADS) {
+    const int s = e / (AS - H), h = H + (e - s * (AS - H));
+    As[s * AS + h] = cvt_out<T>(h == H ? 1.0f : 0.0f);
+  }
 
   const float lam = a.scale ? (float)a.scale[j] : (float)a.lambda;
   const T* Aj = (const T*)a.A + (int64_t)j * a.sAj;
@@ -44,120 +167,144 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a) {
   const float rinvH = 1.0f / (float)H;
 
   double llacc = 0.0;
-  float dacc[MAXP];
+  f32x4 dacc[MAXHB];
 #pragma unroll
-  for (int q = 0; q < MAXP; ++q) dacc[q] = 0.0f;
-  const int npair = C * HP;
-  __syncthreads();
+  for (int q = 0; q < MAXHB; ++q) dacc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
   for (int t = t0; t < t1; ++t) {
     const int s0 = t * HT;
-    // 1. stage the activation tile
+    __syncthreads();  // previous tile's LDS reads are done
     for (int e = tid; e < HT * H; e += HTHREADS) {
       int s = (int)(((float)e + 0.5f) * rinvH);
       int h = e - s * H;
       if (h < 0) { --s; h += H; } else if (h >= H) { ++s; h -= H; }
-      As[s * HS + h] = cvt_in<T>(Aj[(int64_t)(s0 + s) * a.sAm + h]);
+      As[s * AS + h] = Aj[(int64_t)(s0 + s) * a.sAm + h];
     }
     __syncthreads();
-    // 2. logits
-    {
-      const int s = tid & 63;
-      for (int c = tid >> 6; c < C; c += 4) {
-        const float* w = Ws + c * HP;
-        const float* x = As + s * HS;
-        float z = w[H];
-        for (int h = 0; h < H; ++h) z = fmaf(w[h], x[h], z);
-        Zs[s * C + c] = z;
+
+    // ---- 1. logits^T for this wave's 16 samples
+    const T* arow = As + (w * 16 + cl) * AS + 4 * g;
+    const T* wrow = Wc + cl * AS + 4 * g;
+    f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kb = 0; kb < NHB; ++kb) z = mma16(ld4(wrow + kb * 16), ld4(arow + kb * 16), z);
+
+    // ---- 2. likelihood and output error (sample cl, classes 4g + i)
+    const int sl = w * 16 + cl;           // sample within the tile
+    const int sg = s0 + sl;               // sample within the chunk
+    const bool valid = sg < a.m_valid;
+    float d[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (a.likelihood == 0) {
+      float zz[4];
+      float mx = -INFINITY;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        zz[i] = (4 * g + i < C) ? z[i] : -INFINITY;
+        mx = fmaxf(mx, zz[i]);
+      }
+      mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      float se = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) se += (4 * g + i < C) ? expf(zz[i] - mx) : 0.0f;
+      se += __shfl_xor(se, 16, 64);
+      se += __shfl_xor(se, 32, 64);
+      const float lse = mx + logf(se);
+      if (MODE == HEAD_PREDICT) {
+        if (valid) {
+          float* lp = a.logp + ((int64_t)j * a.ld_logp + a.c0 + sg) * C;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (4 * g + i < C) lp[4 * g + i] = zz[i] - lse;
+        }
+      } else {
+        const int y = valid ? a.ylab[a.c0 + sg] : -1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = 4 * g + i;
+          if (c == y) llacc += (double)(zz[i] - lse);
+          if (MODE == HEAD_TRAIN && valid && c < C) d[i] = lam * ((c == y ? 1.0f : 0.0f) - expf(zz[i] - lse));
+        }
+      }
+    } else {
+      // one output: the value sits in lane group 0, register 0
+      const float yv = valid ? a.yreal[a.c0 + sg] : 0.0f;
+      const float r = yv - z[0];
+      if (MODE == HEAD_PREDICT) {
+        if (valid && g == 0) a.logp[(int64_t)j * a.ld_logp + a.c0 + sg] = z[0];
+      } else if (g == 0 && valid) {
+        llacc += (double)(a.gauss_c - 0.5f * r * r * a.inv_var);
+        if (MODE == HEAD_TRAIN) d[0] = lam * r * a.inv_var;
       }
     }
-    __syncthreads();
-    // 3. per-sample likelihood and output error
-    if (tid < HT) {
-      const int s = tid;
-      const bool valid = s0 + s < a.m_valid;
-      float* z = Zs + s * C;
-      if (a.likelihood == 0) {
-        float mx = z[0];
-        for (int c = 1; c < C; ++c) mx = fmaxf(mx, z[c]);
-        float se = 0.0f;
-        for (int c = 0; c < C; ++c) se += expf(z[c] - mx);
-        const float lse = mx + logf(se);
-        if (MODE == HEAD_PREDICT) {
-          if (valid) {
-            float* lp = a.logp + ((int64_t)j * a.ld_logp + a.c0 + s0 + s) * C;
-            for (int c = 0; c < C; ++c) lp[c] = z[c] - lse;
-          }
-        } else {
-          const int y = valid ? a.ylab[a.c0 + s0 + s] : 0;
-          if (valid) llacc += (double)(z[y] - lse);
-          if (MODE == HEAD_TRAIN) {
-            for (int c = 0; c < C; ++c) {
-              const float p = expf(z[c] - lse);
-              z[c] = valid ? lam * ((c == y ? 1.0f : 0.0f) - p) : 0.0f;
+
+    if (MODE == HEAD_TRAIN) {
+      // ---- 3. delta_{L-1}^T = W^T delta^T (times act'), staged for sample-contiguous stores
+      if (a.dT) {
+        const typename V4<T>::type bd = pack4<T>(d);
+        for (int hb = 0; hb < NHB; ++hb) {
+          f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+          v = mma16(ld4(Wt + (hb * 16 + cl) * WT + 4 * g), bd, v);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int h = hb * 16 + 4 * g + i;
+            if (h < H) {
+              const float av = cvt_in<T>(As[sl * AS + h]);
+              const float dv = v[i] * act_grad_from_out(av, a.act);
+              if (Lo.stage) St[h * SS + sl] = cvt_out<T>(dv);
+              else ((T*)a.dT)[(int64_t)j * a.sdTj + (int64_t)h * a.sdTh + sg] = cvt_out<T>(dv);
+              if (a.dR) ((T*)a.dR)[(int64_t)j * a.sdRj + (int64_t)sg * a.sdRm + h] = cvt_out<T>(dv);
             }
           }
         }
-      } else {
-        const float y = valid ? a.yreal[a.c0 + s0 + s] : 0.0f;
-        const float r = y - z[0];
-        if (MODE == HEAD_PREDICT) {
-          if (valid) a.logp[(int64_t)j * a.ld_logp + a.c0 + s0 + s] = z[0];
-        } else {
-          if (valid) llacc += (double)(a.gauss_c - 0.5f * r * r * a.inv_var);
-          if (MODE == HEAD_TRAIN) z[0] = valid ? lam * r * a.inv_var : 0.0f;
-        }
       }
-    }
-    __syncthreads();
-    if (MODE == HEAD_TRAIN) {
-      // 4. error of the last hidden layer, written [unit][sample]
-      if (a.dT) {
-        const int s = tid & 63;
-        T* dT = (T*)a.dT + (int64_t)j * a.sdTj + s0 + s;
-        T* dR = a.dR ? (T*)a.dR + (int64_t)j * a.sdRj + (int64_t)(s0 + s) * a.sdRm : nullptr;
-        const float* dz = Zs + s * C;
-        const float* x = As + s * HS;
-        for (int h = tid >> 6; h < H; h += 4) {
-          float v = 0.0f;
-          for (int c = 0; c < C; ++c) v = fmaf(dz[c], Ws[c * HP + h], v);
-          v *= act_grad_from_out(x[h], a.act);
-          dT[(int64_t)h * a.sdTh] = cvt_out<T>(v);
-          if (dR) dR[h] = cvt_out<T>(v);
-        }
-      }
-      // 5. output-layer gradient partial sums
+      // delta^T to LDS for the dW_L product
 #pragma unroll
-      for (int q = 0; q < MAXP; ++q) {
-        const int pidx = tid + q * HTHREADS;
-        if (pidx < npair) {
-          const int c = pidx / HP, h = pidx - c * HP;
-          float acc = 0.0f;
-          if (h < H) {
-            for (int s = 0; s < HT; ++s) acc = fmaf(Zs[s * C + c], As[s * HS + h], acc);
-          } else {
-            for (int s = 0; s < HT; ++s) acc += Zs[s * C + c];
-          }
-          dacc[q] += acc;
+      for (int i = 0; i < 4; ++i) Dt[(4 * g + i) * DS + sl] = cvt_out<T>(d[i]);
+      __syncthreads();
+      if (a.dT && Lo.stage) {
+        // rows h < H of 64 samples each, 16-byte vectors
+        constexpr int VPR = HT * (int)sizeof(T) / 16;  // vectors per row
+        for (int e = tid; e < H * VPR; e += HTHREADS) {
+          const int h = e / VPR, v = e - h * VPR;
+          const u32x4 val = *(const u32x4*)(St + h * SS + v * (16 / (int)sizeof(T)));
+          *(u32x4*)((T*)a.dT + (int64_t)j * a.sdTj + (int64_t)h * a.sdTh + s0 + v * (16 / (int)sizeof(T))) = val;
+        }
+      }
+      // ---- 4. dW_L += delta^T [A | 1]: this wave owns h-blocks w, w+4, ...
+#pragma unroll
+      for (int q = 0; q < MAXHB; ++q) {
+        const int hb = w + 4 * q;
+        if (hb >= NHB) break;
+#pragma unroll
+        for (int kb = 0; kb < HT / 16; ++kb) {
+          const typename V4<T>::type av = ld4(Dt + cl * DS + kb * 16 + 4 * g);
+          const typename V4<T>::type bv = gather4(As + (kb * 16 + 4 * g) * AS + hb * 16 + cl, AS);
+          dacc[q] = mma16(av, bv, dacc[q]);
         }
       }
     }
-    __syncthreads();
   }
 
   if (MODE != HEAD_PREDICT) {
-    // fixed-order reduction of the per-sample log-likelihood sums (threads 0..63 hold them)
-    if (tid < 64) {
-      const double v = wave_sum(llacc);
-      if (tid == 0) a.llpart[(int64_t)j * a.nsplit + split] = v;
-    }
+    const double v = wave_sum(llacc);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (tid == 0) a.llpart[(int64_t)j * a.nsplit + split] = red[0] + red[1] + red[2] + red[3];
   }
   if (MODE == HEAD_TRAIN) {
+    const int npair = C * (H + 1);
     float* dst = a.dWpart + ((int64_t)j * a.nsplit + split) * npair;
 #pragma unroll
-    for (int q = 0; q < MAXP; ++q) {
-      const int pidx = tid + q * HTHREADS;
-      if (pidx < npair) dst[pidx] = dacc[q];
+    for (int q = 0; q < MAXHB; ++q) {
+      const int hb = w + 4 * q;
+      if (hb >= NHB) break;
+      const int h = hb * 16 + cl;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 4 * g + i;
+        if (c < C && h <= H) dst[c * (H + 1) + h] = dacc[q][i];
+      }
     }
   }
 }
@@ -174,28 +321,41 @@ __global__ void head_reduce_kernel(const HeadArgs a, int beta, int with_grad) {
   }
   if (!with_grad) return;
   const float* src = a.dWpart + (int64_t)j * a.nsplit * npair;
-  float* g = a.grad + (int64_t)j * a.D + a.offL;
+  float* gr = a.grad + (int64_t)j * a.D + a.offL;
   for (int e = threadIdx.x; e < npair; e += blockDim.x) {
     double s = 0.0;
     for (int k = 0; k < a.nsplit; ++k) s += (double)src[(int64_t)k * npair + e];
-    g[e] = beta ? g[e] + (float)s : (float)s;
+    gr[e] = beta ? gr[e] + (float)s : (float)s;
   }
+}
+
+constexpr int LDS_LIMIT = 160 * 1024;
+
+template <typename T>
+HeadLayout pick_layout(int H) {
+  HeadLayout L = head_layout<T>(H, true);
+  if (L.total > LDS_LIMIT) L = head_layout<T>(H, false);
+  return L;
 }
 
 }  // namespace
 
-size_t head_smem_bytes(int H, int C) {
-  return sizeof(float) * ((size_t)C * (H + 1) + (size_t)HT * (H | 1) + (size_t)HT * C);
+bool head_supported(int H, int C, int bf16) {
+  if (C < 1 || C > 16 || H < 1) return false;
+  const HeadLayout L = bf16 ? pick_layout<__bf16>(H) : pick_layout<float>(H);
+  return L.Hp <= 4 * 16 * MAXHB && L.total <= LDS_LIMIT;
 }
-int head_max_pairs() { return MAXP * HTHREADS; }
 
 hipError_t head_run(const HeadArgs& a, int mode, int bf16, hipStream_t s) {
   const int ntiles = (a.m_valid + HT - 1) / HT;
   if (ntiles <= 0) return hipSuccess;
+  if (!head_supported(a.H, a.C, bf16)) return hipErrorInvalidValue;
   dim3 grid(a.nsplit, a.J);
-  const size_t smem = head_smem_bytes(a.H, a.C);
-  if (a.C * (a.H + 1) > head_max_pairs()) return hipErrorInvalidValue;
-#define HEAD_LAUNCH(T, MODE) hipLaunchKernelGGL((head_kernel<T, MODE>), grid, dim3(HTHREADS), smem, s, a)
+#define HEAD_LAUNCH(T, MODE)                                                                             \
+  do {                                                                                                   \
+    const HeadLayout L = pick_layout<T>(a.H);                                                            \
+    hipLaunchKernelGGL((head_kernel<T, MODE>), grid, dim3(HTHREADS), (size_t)L.total, s, a, L);           \
+  } while (0)
   if (bf16) {
     if (mode == HEAD_TRAIN) HEAD_LAUNCH(__bf16, HEAD_TRAIN);
     else if (mode == HEAD_FORWARD) HEAD_LAUNCH(__bf16, HEAD_FORWARD);
@@ -213,9 +373,8 @@ hipError_t head_run(const HeadArgs& a, int mode, int bf16, hipStream_t s) {
 }
 
 hipError_t head_set_smem_limits() {
-  const int big = 160 * 1024;
 #define HEAD_ATTR(T, MODE) \
-  hipFuncSetAttribute((const void*)head_kernel<T, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, big)
+  hipFuncSetAttribute((const void*)head_kernel<T, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_LIMIT)
   hipError_t e = hipSuccess;
   e = HEAD_ATTR(float, HEAD_TRAIN); if (e != hipSuccess) return e;
   e = HEAD_ATTR(float, HEAD_FORWARD); if (e != hipSuccess) return e;

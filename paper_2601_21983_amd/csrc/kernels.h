@@ -43,8 +43,7 @@ struct HeadArgs {
   int64_t ld_logp = 0;
 };
 
-size_t head_smem_bytes(int H, int C);
-int head_max_pairs();
+bool head_supported(int H, int C, int bf16);
 hipError_t head_run(const HeadArgs& a, int mode, int bf16, hipStream_t s);
 hipError_t head_set_smem_limits();
 

@@ -258,8 +258,8 @@ void check_config(const smc_config* c) {
     for (int l = 1; l < c->n_layers; ++l)
       if (c->widths[l] % 8) fail(SMC_ERR_UNSUPPORTED, "with two or more hidden layers every hidden width must be a multiple of 8");
   const int H = c->widths[c->n_layers - 1], C = c->widths[c->n_layers];
-  if ((size_t)head_smem_bytes(H, C) > 160 * 1024 || C * (H + 1) > head_max_pairs())
-    fail(SMC_ERR_UNSUPPORTED, "last hidden layer too wide for the output-layer kernel");
+  if (!head_supported(H, C, c->precision == SMC_PREC_BF16))
+    fail(SMC_ERR_UNSUPPORTED, "last hidden layer too wide for the output-layer kernel (at most 495 units)");
 }
 
 void setup_shapes(smc_t h) {
