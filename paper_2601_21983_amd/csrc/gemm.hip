@@ -203,20 +203,29 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
   }
 
   // ------------------------------------------------------------------ epilogue
-  // Staged path: outputs without column split or second output go through LDS so
-  // that each output row segment is written by consecutive lanes (coalesced).
-  if (p.out0.cs == (1 << 30) && p.out0.cstr == 1 && (EPI == EPI_GRAD || (EPI == EPI_FWD && !p.out1.ptr))) {
+  // Staged path: one output whose columns are contiguous inside each column-split
+  // segment goes through LDS, so each output row piece is written by consecutive
+  // lanes with the widest aligned vector stores (16, 8 or 4/2 bytes).
+  if (p.out0.cstr == 1 && (EPI == EPI_GRAD || (EPI == EPI_FWD && !p.out1.ptr))) {
     typedef typename std::conditional<EPI == EPI_GRAD, float, T>::type O;
-    constexpr int SROW = BN + 16 / (int)sizeof(O);  // padded LDS row, in elements
-    O* slab = (O*)smem;                              // [NWM*32][SROW]
+    constexpr int OS = (int)sizeof(O);
+    constexpr int SROW = BN + 16 / OS;  // padded LDS row, in elements
+    O* slab = (O*)smem;                 // [NWM*32][SROW]
     constexpr int NWM = BM / WM;
-    constexpr int SLAB_BYTES = NWM * 32 * SROW * (int)sizeof(O);
-    static_assert(SLAB_BYTES + NWM * 32 * 8 <= 2 * STAGE, "slab does not fit in LDS");
-    static_assert(THREADS % BN == 0, "copy loop assumes BN divides the workgroup");
+    constexpr int SLAB_BYTES = NWM * 32 * SROW * OS;
+    static_assert(SLAB_BYTES + (NWM * 32 + BN) * 8 <= 2 * STAGE, "slab does not fit in LDS");
     int64_t* rowaddr = (int64_t*)(smem + SLAB_BYTES);
-    constexpr int VOA = 16 / (int)sizeof(O);
-    const bool vec_ok = ((uintptr_t)p.out0.ptr % 16 == 0) && p.out0.rstr % VOA == 0 && p.out0.sR % VOA == 0 &&
-                        p.out0.sb % VOA == 0 && n0 % VOA == 0;
+    int64_t* colpart = rowaddr + NWM * 32;
+    const OutDesc& d = p.out0;
+    auto aligned = [&](int ve) {
+      return ((uintptr_t)d.ptr % (uintptr_t)(ve * OS)) == 0 && d.rstr % ve == 0 && d.sR % ve == 0 &&
+             d.sb % ve == 0 && d.sC % ve == 0 && d.cs % ve == 0;
+    };
+    const int vw = aligned(16 / OS) ? 16 / OS : (aligned(8 / OS) ? 8 / OS : 1);
+    for (int lc = tid; lc < BN; lc += THREADS) {
+      const int col = n0 + lc;
+      colpart[lc] = col < N ? (int64_t)(col / d.cs) * d.sC + (col % d.cs) : -1;
+    }
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
       // each wave drops its 32-row block i into the slab
@@ -236,51 +245,43 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
       }
       if (tid < NWM * 32) {
         const int row = m0 + (tid >> 5) * WM + i * 32 + (tid & 31);
-        const int rq = row / p.out0.rs, rr = row - rq * p.out0.rs;
-        rowaddr[tid] = row < M ? (int64_t)b * p.out0.sb + (int64_t)rq * p.out0.sR + (int64_t)rr * p.out0.rstr : -1;
+        const int rq = row / d.rs, rr = row - rq * d.rs;
+        rowaddr[tid] = row < M ? (int64_t)b * d.sb + (int64_t)rq * d.sR + (int64_t)rr * d.rstr : -1;
       }
       __syncthreads();
-      // the whole workgroup copies the slab rows out, consecutive lanes on consecutive columns
-      constexpr int VO = 16 / (int)sizeof(O);   // elements per 16-byte vector
-      constexpr int VPR = BN / VO;              // vectors per slab row
-      if (vec_ok) {
-        for (int e = tid; e < NWM * 32 * VPR; e += THREADS) {
-          const int lr = e / VPR, lc = (e - lr * VPR) * VO;
-          const int64_t ra = rowaddr[lr];
-          const int col = n0 + lc;
-          if (ra < 0 || col >= N) continue;
-          O* dst = (O*)p.out0.ptr + ra + col;
-          const O* src = slab + lr * SROW + lc;
-          if (col + VO <= N) {
-            u32x4 v = *(const u32x4*)src;
-            if (EPI == EPI_GRAD && p.beta) {
-              f32x4 a = __builtin_bit_cast(f32x4, v), o = *(const f32x4*)dst;
-#pragma unroll
-              for (int q = 0; q < 4; ++q) a[q] += o[q];
-              v = __builtin_bit_cast(u32x4, a);
-            }
-            *(u32x4*)dst = v;
-          } else {
-            for (int q = 0; q < N - col; ++q) {
-              if (EPI == EPI_GRAD) dst[q] = p.beta ? dst[q] + src[q] : src[q];
-              else dst[q] = src[q];
-            }
-          }
-        }
-      } else {
-        const int lc = tid % BN;
+      const int vpr = BN / vw;  // vectors per slab row
+      for (int e = tid; e < NWM * 32 * vpr; e += THREADS) {
+        const int lr = e / vpr, lc = (e - lr * vpr) * vw;
+        const int64_t ra = rowaddr[lr];
         const int col = n0 + lc;
-        if (col < N) {
-          for (int lr = tid / BN; lr < NWM * 32; lr += THREADS / BN) {
-            const int64_t ra = rowaddr[lr];
-            if (ra < 0) continue;
-            O* dst = (O*)p.out0.ptr + ra + col;
-            if (EPI == EPI_GRAD) {
-              const float v = cvt_in<O>(slab[lr * SROW + lc]);
-              *dst = p.beta ? *dst + v : v;
-            } else {
-              *dst = slab[lr * SROW + lc];
-            }
+        if (ra < 0 || col >= N) continue;
+        O* dst = (O*)d.ptr + ra + colpart[lc];
+        const O* src = slab + lr * SROW + lc;
+        if (col + vw <= N && vw * OS == 16) {
+          u32x4 v = *(const u32x4*)src;
+          if (EPI == EPI_GRAD && p.beta) {
+            f32x4 a = __builtin_bit_cast(f32x4, v), o = *(const f32x4*)dst;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] += o[q];
+            v = __builtin_bit_cast(u32x4, a);
+          }
+          *(u32x4*)dst = v;
+        } else if (col + vw <= N && vw * OS == 8) {
+          typedef __attribute__((__vector_size__(2 * sizeof(uint32_t)))) uint32_t u32x2;
+          typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2;
+          u32x2 v = *(const u32x2*)src;
+          if (EPI == EPI_GRAD && p.beta) {
+            f32x2 a = __builtin_bit_cast(f32x2, v), o = *(const f32x2*)dst;
+            a[0] += o[0];
+            a[1] += o[1];
+            v = __builtin_bit_cast(u32x2, a);
+          }
+          *(u32x2*)dst = v;
+        } else {
+          const int n = min(vw, N - col);
+          for (int q = 0; q < n; ++q) {
+            if (EPI == EPI_GRAD) dst[q] = p.beta ? dst[q] + src[q] : src[q];
+            else dst[q] = src[q];
           }
         }
       }

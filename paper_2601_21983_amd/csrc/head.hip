@@ -35,6 +35,7 @@ namespace {
 constexpr int HT = 64;  // samples per tile (16 per wave)
 constexpr int HTHREADS = 256;
 constexpr int MAXHB = 8;  // h-blocks per wave in the dW_L accumulator: Hp <= 4 * 16 * MAXHB = 512
+constexpr int PF = 8;     // 8-byte chunks of the next activation tile prefetched per thread
 
 typedef __attribute__((__vector_size__(4 * sizeof(short)))) short s16x4;
 
@@ -123,7 +124,9 @@ __host__ __device__ inline HeadLayout head_layout(int H, bool stage) {
   return L;
 }
 
-template <typename T, int MODE>
+typedef __attribute__((__vector_size__(2 * sizeof(uint32_t)))) uint32_t u32x2;
+
+template <typename T, int MODE, int NQ>
 __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const HeadLayout Lo) {
   extern __shared__ __attribute__((aligned(16))) char hsm[];
   T* Wc = (T*)hsm;
@@ -164,23 +167,68 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
   const int ntiles = (a.m_valid + HT - 1) / HT;
   const int t0 = split * a.tiles_per_split;
   const int t1 = min(ntiles, t0 + a.tiles_per_split);
-  const float rinvH = 1.0f / (float)H;
+
+  // activation tile loader: 8-byte chunks when rows allow it, else single elements
+  constexpr int CE = 8 / (int)sizeof(T);  // elements per chunk
+  const bool vec = (H % CE) == 0 && (a.sAm % CE) == 0 && (a.sAj % CE) == 0 && ((uintptr_t)a.A % 8) == 0;
+  const int cpr = vec ? H / CE : H;       // chunks per row
+  const int nch = HT * cpr;
+  const float rcpr = 1.0f / (float)cpr;
+  u32x2 pre[PF];
+  auto chunk_rc = [&](int e, int& s, int& c) {
+    s = (int)(((float)e + 0.5f) * rcpr);
+    c = e - s * cpr;
+    if (c < 0) { --s; c += cpr; } else if (c >= cpr) { ++s; c -= cpr; }
+  };
+  auto prefetch = [&](int tile) {
+    if (!vec) return;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * HTHREADS;
+      if (e < nch) {
+        int s, c;
+        chunk_rc(e, s, c);
+        pre[q] = *(const u32x2*)(Aj + (int64_t)(tile * HT + s) * a.sAm + c * CE);
+      }
+    }
+  };
+  auto stage = [&](int tile) {
+    if (vec) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int e = tid + q * HTHREADS;
+        if (e < nch) {
+          int s, c;
+          chunk_rc(e, s, c);
+          *(u32x2*)(As + s * AS + c * CE) = pre[q];
+        }
+      }
+      for (int e = tid + PF * HTHREADS; e < nch; e += HTHREADS) {
+        int s, c;
+        chunk_rc(e, s, c);
+        *(u32x2*)(As + s * AS + c * CE) = *(const u32x2*)(Aj + (int64_t)(tile * HT + s) * a.sAm + c * CE);
+      }
+    } else {
+      for (int e = tid; e < nch; e += HTHREADS) {
+        int s, c;
+        chunk_rc(e, s, c);
+        As[s * AS + c] = Aj[(int64_t)(tile * HT + s) * a.sAm + c];
+      }
+    }
+  };
 
   double llacc = 0.0;
-  f32x4 dacc[MAXHB];
+  f32x4 dacc[NQ];
 #pragma unroll
-  for (int q = 0; q < MAXHB; ++q) dacc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int q = 0; q < NQ; ++q) dacc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
+  if (t0 < t1) prefetch(t0);
   for (int t = t0; t < t1; ++t) {
     const int s0 = t * HT;
     __syncthreads();  // previous tile's LDS reads are done
-    for (int e = tid; e < HT * H; e += HTHREADS) {
-      int s = (int)(((float)e + 0.5f) * rinvH);
-      int h = e - s * H;
-      if (h < 0) { --s; h += H; } else if (h >= H) { ++s; h -= H; }
-      As[s * AS + h] = Aj[(int64_t)(s0 + s) * a.sAm + h];
-    }
+    stage(t);
     __syncthreads();
+    if (t + 1 < t1) prefetch(t + 1);
 
     // ---- 1. logits^T for this wave's 16 samples
     const T* arow = As + (w * 16 + cl) * AS + 4 * g;
@@ -272,7 +320,7 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
       }
       // ---- 4. dW_L += delta^T [A | 1]: this wave owns h-blocks w, w+4, ...
 #pragma unroll
-      for (int q = 0; q < MAXHB; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         const int hb = w + 4 * q;
         if (hb >= NHB) break;
 #pragma unroll
@@ -296,7 +344,7 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
     const int npair = C * (H + 1);
     float* dst = a.dWpart + ((int64_t)j * a.nsplit + split) * npair;
 #pragma unroll
-    for (int q = 0; q < MAXHB; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int hb = w + 4 * q;
       if (hb >= NHB) break;
       const int h = hb * 16 + cl;
@@ -354,7 +402,13 @@ hipError_t head_run(const HeadArgs& a, int mode, int bf16, hipStream_t s) {
 #define HEAD_LAUNCH(T, MODE)                                                                             \
   do {                                                                                                   \
     const HeadLayout L = pick_layout<T>(a.H);                                                            \
-    hipLaunchKernelGGL((head_kernel<T, MODE>), grid, dim3(HTHREADS), (size_t)L.total, s, a, L);           \
+    const int nq = (L.Hp / 16 + 3) / 4;                                                                  \
+    if (nq <= 2)                                                                                         \
+      hipLaunchKernelGGL((head_kernel<T, MODE, 2>), grid, dim3(HTHREADS), (size_t)L.total, s, a, L);      \
+    else if (nq <= 4)                                                                                    \
+      hipLaunchKernelGGL((head_kernel<T, MODE, 4>), grid, dim3(HTHREADS), (size_t)L.total, s, a, L);      \
+    else                                                                                                 \
+      hipLaunchKernelGGL((head_kernel<T, MODE, 8>), grid, dim3(HTHREADS), (size_t)L.total, s, a, L);      \
   } while (0)
   if (bf16) {
     if (mode == HEAD_TRAIN) HEAD_LAUNCH(__bf16, HEAD_TRAIN);
@@ -373,15 +427,19 @@ hipError_t head_run(const HeadArgs& a, int mode, int bf16, hipStream_t s) {
 }
 
 hipError_t head_set_smem_limits() {
-#define HEAD_ATTR(T, MODE) \
-  hipFuncSetAttribute((const void*)head_kernel<T, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_LIMIT)
+#define HEAD_ATTR(T, MODE, NQ) \
+  hipFuncSetAttribute((const void*)head_kernel<T, MODE, NQ>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_LIMIT)
+#define HEAD_ATTR3(T, MODE) \
+  if ((e = HEAD_ATTR(T, MODE, 2)) != hipSuccess || (e = HEAD_ATTR(T, MODE, 4)) != hipSuccess || \
+      (e = HEAD_ATTR(T, MODE, 8)) != hipSuccess) return e
   hipError_t e = hipSuccess;
-  e = HEAD_ATTR(float, HEAD_TRAIN); if (e != hipSuccess) return e;
-  e = HEAD_ATTR(float, HEAD_FORWARD); if (e != hipSuccess) return e;
-  e = HEAD_ATTR(float, HEAD_PREDICT); if (e != hipSuccess) return e;
-  e = HEAD_ATTR(__bf16, HEAD_TRAIN); if (e != hipSuccess) return e;
-  e = HEAD_ATTR(__bf16, HEAD_FORWARD); if (e != hipSuccess) return e;
-  e = HEAD_ATTR(__bf16, HEAD_PREDICT);
+  HEAD_ATTR3(float, HEAD_TRAIN);
+  HEAD_ATTR3(float, HEAD_FORWARD);
+  HEAD_ATTR3(float, HEAD_PREDICT);
+  HEAD_ATTR3(__bf16, HEAD_TRAIN);
+  HEAD_ATTR3(__bf16, HEAD_FORWARD);
+  HEAD_ATTR3(__bf16, HEAD_PREDICT);
+#undef HEAD_ATTR3
 #undef HEAD_ATTR
   return e;
 }

@@ -11,9 +11,10 @@
 //                          the lambda-scaled log-likelihood gradient (the prior term
 //                          is added where it is used) and momenta
 //   w_l  [J*n_l x ldw_l]   GEMM copy of each layer's weights (operand type), b_l [J*n_l]
-//   act_l [mc x J*n_l]     hidden activations of one chunk of samples, all particles'
-//                          units side by side ("concatenated" layout), so layer 1 is a
-//                          single dense GEMM over the J*n_1 columns
+//   act_l [J x mc x n_l]   hidden activations of one chunk of samples, particle-major
+//                          (one contiguous [samples x units] block per particle); layer 1
+//                          is still a single dense GEMM over the J*n_1 concatenated units,
+//                          whose epilogue scatters each particle's columns to its block
 //   dT_l [J*n_l x mc]      back-propagated errors, sample-contiguous (K-major for the
 //                          weight-gradient GEMM)
 // The subset [0, M_k) is processed in chunks of mc samples; activations live only
@@ -134,10 +135,10 @@ struct ProfRec {
 };
 
 struct LayerBufs {
-  void* act = nullptr;   // [mc x J*nout] (hidden layers)
+  void* act = nullptr;   // [J x mc x nout] (hidden layers)
   void* actT = nullptr;  // [J x (nout+1) x mc] (hidden layers feeding another hidden layer)
   void* dT = nullptr;    // [J*nout x mc]
-  void* dR = nullptr;    // [mc x J*nout] (hidden layers >= 2)
+  void* dR = nullptr;    // [J x mc x nout] (hidden layers >= 2)
   void* wT = nullptr;    // [J x nin x ldwT] (layers >= 2 that are not the output layer)
   int ldwT = 0;
 };
@@ -437,7 +438,9 @@ void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows, int m_valid)
       p.batch = 1;
       p.bias = h->net.bias[0];
       p.out0.ptr = h->lb[0].act;
-      p.out0.rstr = U;
+      p.out0.rstr = nout;
+      p.out0.cs = nout;
+      p.out0.sC = h->mc * nout;
       if (h->lb[0].actT) {
         p.out1.ptr = h->lb[0].actT;
         p.out1.cs = nout;
@@ -446,11 +449,11 @@ void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows, int m_valid)
         p.out1.rstr = 1;
       }
     } else {
-      // batched over particles: A_{l-1}[j] is a column block of the concatenated layout
+      // batched over particles: A_{l-1}[j] is particle j's [samples x units] block
       const int nin = h->net.nin[l];
       p.A = h->lb[l - 1].act;
-      p.lda = (int64_t)J * nin;
-      p.sAb = nin;
+      p.lda = nin;
+      p.sAb = h->mc * nin;
       p.B = h->net.w[l];
       p.ldb = h->net.ldw[l];
       p.sBb = (int64_t)nout * h->net.ldw[l];
@@ -460,8 +463,8 @@ void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows, int m_valid)
       p.bias = h->net.bias[l];
       p.sbias = nout;
       p.out0.ptr = h->lb[l].act;
-      p.out0.sb = nout;
-      p.out0.rstr = U;
+      p.out0.sb = h->mc * nout;
+      p.out0.rstr = nout;
       if (h->lb[l].actT) {
         p.out1.ptr = h->lb[l].actT;
         p.out1.sb = (int64_t)(nout + 1) * h->mc;
@@ -492,8 +495,8 @@ HeadArgs head_args(smc_t h, const float* theta) {
   a.act = h->cfg.activation;
   if (L >= 2) {
     a.A = h->lb[L - 2].act;
-    a.sAj = a.H;
-    a.sAm = (int64_t)h->J * a.H;
+    a.sAj = h->mc * a.H;
+    a.sAm = a.H;
   } else {
     a.A = h->X;
     a.sAj = 0;
@@ -540,8 +543,8 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
       a.sdTh = h->mc;
       if (h->lb[L - 2].dR) {
         a.dR = h->lb[L - 2].dR;
-        a.sdRj = a.H;
-        a.sdRm = (int64_t)J * a.H;
+        a.sdRj = h->mc * a.H;
+        a.sdRm = a.H;
       }
     }
     timed(h, SMC_K_HEAD, (train ? 6.0 : 2.0) * a.C * (double)a.H * J * mcv, 0.0,
@@ -591,23 +594,23 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
         p.N = nin;
         p.K = nout;
         p.A = h->lb[l].dR;
-        p.lda = (int64_t)J * nout;
-        p.sAb = nout;
+        p.lda = nout;
+        p.sAb = h->mc * nout;
         p.B = h->lb[l].wT;
         p.ldb = h->lb[l].ldwT;
         p.sBb = (int64_t)nin * h->lb[l].ldwT;
         p.batch = J;
         p.aux.ptr = h->lb[l - 1].act;
-        p.aux.sb = nin;
-        p.aux.rstr = (int64_t)J * nin;
+        p.aux.sb = h->mc * nin;
+        p.aux.rstr = nin;
         p.out0.ptr = h->lb[l - 1].dT;
         p.out0.sb = (int64_t)nin * h->mc;
         p.out0.cstr = h->mc;
         p.out0.rstr = 1;
         if (h->lb[l - 1].dR) {
           p.out1.ptr = h->lb[l - 1].dR;
-          p.out1.sb = nin;
-          p.out1.rstr = (int64_t)J * nin;
+          p.out1.sb = h->mc * nin;
+          p.out1.rstr = nin;
         }
         gemm(h, p, SMC_K_GEMM_OTHER, 2.0 * J * nout * (double)nin * mcv);
       }
