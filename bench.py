@@ -54,7 +54,38 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
+    ap.add_argument("--precisions", default="bf16,fp32", help="comma list; the first is the headline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (reference kernel for HBM counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mnist_shaped_bf16_hbm_traffic.json")
+TRAFFIC_SOURCES = ["paper_2601_21983_amd/csrc/gemm.hip", "paper_2601_21983_amd/csrc/head.hip",
+                   "paper_2601_21983_amd/csrc/smc_kernels.hip", "paper_2601_21983_amd/csrc/smc_api.hip"]
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, steps):
+    """HBM bytes per launch of `kernel` from the committed PMC profile, if it was taken
+    on the current kernel sources and the same number of steps; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_digest() or rec.get("steps") != steps:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
 
 
 def make_data():
@@ -137,22 +168,23 @@ def kernel_table(prof, prec):
     return out
 
 
-def roofline(prof, prec):
+def roofline(prof, prec, steps, with_traffic):
     # dominant kernel class by total time
     name, (ms, n, fl, by) = max(prof.items(), key=lambda kv: kv[1][0])
+    traffic = measured_traffic(name, steps) if with_traffic else None
     if fl > 0 and name.startswith("gemm"):
         ach = fl / (ms * 1e-3) / 1e12
         peak = PEAK[prec]
         return {"kernel": name, "bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": None,
+                "frac": round(ach / peak, 4), "traffic": traffic,
                 "avg_launch_us": round(1e3 * ms / n, 3), "flops_per_launch": fl / n}
     if by > 0:
         ach = by / (ms * 1e-3) / 1e9
         return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK, 4), "traffic": None, "avg_launch_us": round(1e3 * ms / n, 3)}
+                "frac": round(ach / HBM_PEAK, 4), "traffic": traffic, "avg_launch_us": round(1e3 * ms / n, 3)}
     ach = fl / (ms * 1e-3) / 1e12
     return {"kernel": name, "bound": "alu", "achieved": round(ach, 2), "peak": ALU_PEAK, "unit": "TFLOP/s",
-            "frac": round(ach / ALU_PEAK, 4), "traffic": None, "avg_launch_us": round(1e3 * ms / n, 3)}
+            "frac": round(ach / ALU_PEAK, 4), "traffic": traffic, "avg_launch_us": round(1e3 * ms / n, 3)}
 
 
 def cpu_baseline(X, y, sizes, budget_s=12.0, J_s=8):
@@ -203,15 +235,22 @@ def main():
     dev = {"X": torch.from_numpy(X).to(cuda), "y": torch.from_numpy(y).to(cuda),
            "Xt": torch.from_numpy(Xt).to(cuda), "yt": torch.from_numpy(yt).to(cuda)}
 
+    precs = [p for p in args.precisions.split(",") if p]
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=cuda)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     res = {}
-    for prec in ("bf16", "fp32"):
+    for prec in precs:
         r = run_timed(P, dev, prec, sizes, steps, args.warmup, args.seed)
         res[prec] = r
         log(f"{prec}: {steps} steps in {r['seconds']:.3f} s, {r['rate']:.4g} grad-evals/s")
         log(json.dumps(kernel_table(r["prof"], prec)))
 
     tta = None
-    if not args.no_tta:
+    if not args.no_tta and "fp32" in precs and "bf16" in precs:
         traces = {p: run_tta(P, dev, p, sizes, steps, args.seed) for p in ("fp32", "bf16")}
         target = traces["fp32"][-1][2] - 0.005
         tta = {"target_accuracy": round(target, 4)}
@@ -226,7 +265,9 @@ def main():
         cpu = cpu_baseline(X, y, sizes)
         log(f"cpu baseline: {cpu}")
 
-    b = res["bf16"]
+    head = precs[0]
+    b = res[head]
+    other = {p: res[p] for p in precs[1:]}
     line = {
         "metric": "particle-sample gradient evaluations per second",
         "value": round(b["rate"], 1),
@@ -238,19 +279,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": head,
         "data": "synthetic",
         "config": {"workload": "MNIST-shaped synthetic templates 60000/10000, MLP 784-100-10 ReLU, J=256, "
                                "Linear schedule C=kappa=1000 K=60, Langevin h=0.002, systematic resampling",
-                   "particles": J, "iterations": steps, "proposal": "fixed", "precision": "bf16"},
-        "roofline": roofline(b["prof"], "bf16"),
+                   "particles": J, "iterations": steps, "proposal": "fixed", "precision": head},
+        "roofline": roofline(b["prof"], head, steps, head == "bf16"),
         "cpu_baseline": cpu,
-        "fp32_plain": {"value": round(res["fp32"]["rate"], 1), "unit": "grad-evals/s",
-                       "ms_per_step": round(1e3 * res["fp32"]["seconds"] / steps, 4),
-                       "roofline": roofline(res["fp32"]["prof"], "fp32")},
         "time_to_accuracy": tta,
-        "kernels": {"bf16": kernel_table(b["prof"], "bf16"), "fp32": kernel_table(res["fp32"]["prof"], "fp32")},
+        "kernels": {p: kernel_table(res[p]["prof"], p) for p in precs},
     }
+    for p, r in other.items():
+        line[f"{p}_plain"] = {"value": round(r["rate"], 1), "unit": "grad-evals/s",
+                              "ms_per_step": round(1e3 * r["seconds"] / steps, 4),
+                              "roofline": roofline(r["prof"], p, steps, False)}
     print(json.dumps(line), flush=True)
 
 
