@@ -81,7 +81,7 @@ typedef struct smc_config {
   int32_t precision;                   /* GEMM operand precision; accumulation is always FP32 */
   int32_t proposal;                    /* SMC_PROPOSAL_FIXED | SMC_PROPOSAL_LEARNED (needs S = 1) */
   int32_t leapfrog_steps;              /* S >= 1 (Section 2.1) */
-  int32_t reserved0;
+  int32_t n_iterations;                /* K (used only by the learned proposal's k/K feature; 0 = unknown) */
   double step_size;                    /* h (Section 2.1) */
   double prior_std;                    /* q0 = N(0, prior_std^2 I) */
   double noise_std;                    /* sigma of the Gaussian likelihood */
@@ -222,6 +222,45 @@ SMC_API smc_status smc_nn_backward(smc_t h, const float* theta_dev, int64_t m, c
 SMC_API int64_t smc_n_params(smc_t h);
 /* Samples per activation chunk chosen from act_budget_bytes (for tests). */
 SMC_API int64_t smc_chunk_samples(smc_t h);
+
+/*
+ * Training targets for the learned proposal from the current population
+ * (an extension; the paper's moves use a fixed step).  Moves the subset to
+ * (m_k, lambda_k) first if it changed (as smc_step would), then for every step
+ * size h_grid[i] runs one preconditioning-free Langevin trial from the current
+ * particles with shared noise and scores it by the squared jump times
+ * min(1, exp(D)), D the Metropolis log-ratio under the current target; the
+ * particles are restored afterwards.  Outputs (device, float32):
+ *   feat_dev   [J x 4]      features at the current state (see smc_proposal_features)
+ *   target_dev [J x (1+G)]  raw-output regression targets: atanh of the clipped
+ *              (log h* - log h)/ln 10 for the best grid step h* (h = step_size),
+ *              and atanh of the clipped centred log RMS gradient / ln 10 per group.
+ * Injected noise (smc_set_noise) is used for every trial and consumed.
+ */
+SMC_API smc_status smc_proposal_targets(smc_t h, int64_t m_k, double lambda_k, const double* h_grid, int32_t n_grid,
+                                        double k_over_K, float* feat_dev, float* target_dev);
+
+/* Parameters of the proposal network for G groups (-1 if G is out of range). */
+SMC_API int32_t smc_mlp_n_params(int32_t n_groups);
+
+/*
+ * Stateless proposal-network passes on R rows of float32 features [R x 4]:
+ *   smc_mlp_forward: mode 0 writes the raw outputs [R x (1+G)]; mode 1 the bounded
+ *     scales (h0 exp(ln10 tanh o_0), exp(ln10 tanh o_g)) with (h0, 1) for rows whose
+ *     outputs are not finite.  bf16 != 0 runs the hidden 64x64 layer on BF16 MFMAs.
+ *   smc_mlp_grad: FP32 gradient of (1/R) sum_r 1/2 |o_r - t_r|^2 w.r.t. the blob
+ *     (zero for the input statistics mu, sd) into grad_dev, loss to *loss (host, nullable).
+ *   smc_mlp_train: n_steps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8) numbered from
+ *     first_step, on the full batch; adam_dev [2 x n_params] holds the moment estimates
+ *     (zero-initialise before the first call).  Synchronises the stream.
+ */
+SMC_API smc_status smc_mlp_forward(const float* params_dev, const float* feat_dev, int64_t R, int32_t n_groups,
+                                   float* out_dev, int32_t mode, double h0, int32_t bf16, void* hip_stream);
+SMC_API smc_status smc_mlp_grad(const float* params_dev, const float* feat_dev, const float* target_dev, int64_t R,
+                                int32_t n_groups, float* grad_dev, double* loss, void* hip_stream);
+SMC_API smc_status smc_mlp_train(float* params_dev, float* adam_dev, const float* feat_dev, const float* target_dev,
+                                 int64_t R, int32_t n_groups, int32_t first_step, int32_t n_steps, double lr,
+                                 double* loss, void* hip_stream);
 
 /* ---------------------------------------------------------------- kernel timing */
 /*

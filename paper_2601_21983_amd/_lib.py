@@ -37,7 +37,7 @@ class smc_config(C.Structure):
         ("precision", C.c_int32),
         ("proposal", C.c_int32),
         ("leapfrog_steps", C.c_int32),
-        ("reserved0", C.c_int32),
+        ("n_iterations", C.c_int32),
         ("step_size", C.c_double),
         ("prior_std", C.c_double),
         ("noise_std", C.c_double),
@@ -94,6 +94,11 @@ _SIGS = {
     "smc_normalise": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "smc_systematic_resample": (_i32, [_vp, _i32, _d, _vp, _vp, _vp]),
     "smc_philox": (_i32, [_u32, _u32, _u32, _u32, _u32, _i64, _vp, _vp]),
+    "smc_proposal_targets": (_i32, [_handle, _i64, _d, C.POINTER(_d), _i32, _d, _vp, _vp]),
+    "smc_mlp_n_params": (_i32, [_i32]),
+    "smc_mlp_forward": (_i32, [_vp, _vp, _i64, _i32, _vp, _i32, _d, _i32, _vp]),
+    "smc_mlp_grad": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, C.POINTER(_d), _vp]),
+    "smc_mlp_train": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32, _d, C.POINTER(_d), _vp]),
     "smc_profile": (_i32, [_handle, _i32]),
     "smc_profile_read": (_i32, [_handle, C.POINTER(_d), C.POINTER(_i64), C.POINTER(_d), C.POINTER(_d)]),
 }
@@ -234,3 +239,34 @@ def smc_profile_read(h) -> dict:
     b = (C.c_double * SMC_K_COUNT)()
     _check(lib.smc_profile_read(h, t, n, f, b), "smc_profile_read")
     return {SMC_K_NAMES[k]: (t[k], n[k], f[k], b[k]) for k in range(SMC_K_COUNT)}
+
+
+def smc_proposal_targets(h, m_k: int, lambda_k: float, h_grid, k_over_K: float, feat_dev, target_dev) -> None:
+    arr = (C.c_double * len(h_grid))(*[float(x) for x in h_grid])
+    _check(lib.smc_proposal_targets(h, m_k, lambda_k, arr, len(h_grid), k_over_K, _opt(feat_dev), _opt(target_dev)),
+           "smc_proposal_targets")
+
+
+def smc_mlp_n_params(n_groups: int) -> int:
+    return lib.smc_mlp_n_params(n_groups)
+
+
+def smc_mlp_forward(params_dev, feat_dev, R: int, n_groups: int, out_dev, mode: int, h0: float, bf16: bool,
+                    stream) -> None:
+    _check(lib.smc_mlp_forward(_opt(params_dev), _opt(feat_dev), R, n_groups, _opt(out_dev), mode, h0,
+                               1 if bf16 else 0, _opt(stream)), "smc_mlp_forward")
+
+
+def smc_mlp_grad(params_dev, feat_dev, target_dev, R: int, n_groups: int, grad_dev, stream) -> float:
+    loss = C.c_double(0.0)
+    _check(lib.smc_mlp_grad(_opt(params_dev), _opt(feat_dev), _opt(target_dev), R, n_groups, _opt(grad_dev),
+                            C.byref(loss), _opt(stream)), "smc_mlp_grad")
+    return loss.value
+
+
+def smc_mlp_train(params_dev, adam_dev, feat_dev, target_dev, R: int, n_groups: int, first_step: int, n_steps: int,
+                  lr: float, stream) -> float:
+    loss = C.c_double(0.0)
+    _check(lib.smc_mlp_train(_opt(params_dev), _opt(adam_dev), _opt(feat_dev), _opt(target_dev), R, n_groups,
+                             first_step, n_steps, lr, C.byref(loss), _opt(stream)), "smc_mlp_train")
+    return loss.value

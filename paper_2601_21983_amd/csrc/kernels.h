@@ -140,5 +140,41 @@ hipError_t fill_f64_run(double* p, int64_t n, double v, hipStream_t s);
 hipError_t grad_with_prior_run(const float* theta, const float* g, float* out, int64_t n, float inv_prior_var,
                                hipStream_t s);
 hipError_t sq_norm_rows_run(const float* a, int J, int64_t D, double* out, hipStream_t s);
+hipError_t lp_current_run(const double* ll, const double* tsq, int J, double lambda, double inv_2pv, double* out,
+                          hipStream_t s);
+hipError_t f64_to_f32_run(const double* in, int64_t n, float* out, hipStream_t s);
+
+// ---------------------------------------------------------------- learned proposal
+struct LearnedMoveArgs {
+  NetShape net;
+  float* theta = nullptr;
+  float* P = nullptr;            // FIRST writes theta' - theta here; LAST reads it
+  const float* g = nullptr;
+  const float* noise = nullptr;
+  const float* scales = nullptr; // [J x NO]: h, m_1..m_G at the state the kernel starts from
+  int NO = 0;
+  double* part = nullptr;        // [3][J][nblk]
+  int nblk = 0;
+  int mode = MOVE_FIRST;
+  float inv_prior_var = 1.0f;
+  uint32_t key0 = 0, key1 = 0, ctr_iter = 0;
+};
+hipError_t mlp_set_smem_limits();
+int mlp_n_params(int G);
+hipError_t mlp_infer_run(const float* params, const void* feat, int feat_f64, int64_t R, int G, float* out, int mode,
+                         float h0, int bf16, hipStream_t s);
+hipError_t mlp_train_step_run(float* params, float* adam, const float* feat, const float* tgt, int64_t R, int G,
+                              float* grad_part, double* loss_part, int step, float lr, float* grad_out,
+                              double* loss_out, hipStream_t s);
+hipError_t learned_move_run(const LearnedMoveArgs& a, hipStream_t s);
+hipError_t learned_extra_run(const float* sc0, const float* sc1, int NO, const double* part, int J, int nblk,
+                             const int64_t* group_n, int64_t D, double* extra, hipStream_t s);
+hipError_t features_run(const NetShape& n, const float* theta, const float* g, const double* ll, float ipv, double m,
+                        double k_over_K, double m_over_N, double* feat, double* gsum, int G, hipStream_t s);
+hipError_t trial_score_run(const double* part, int J, int nblk, const double* ll1, const double* lp0, double lambda,
+                           double inv_2pv, double h, const double* phalf_sq, double* best_score, double* best_logh,
+                           int first, hipStream_t s);
+hipError_t targets_run(const double* best_logh, const double* gsum, const int64_t* group_n, int J, int G, double h0,
+                       double clip, float* tgt, hipStream_t s);
 
 }  // namespace smc

@@ -181,7 +181,16 @@ struct smc_handle {
   float* pnet = nullptr;
   int pnet_n = 0;
   double h0 = 0.0;
-  int G = 0;
+  int G = 0, NO = 0;
+  int64_t* group_n = nullptr;   // device [G]: parameters per group
+  float *sc0 = nullptr, *sc1 = nullptr;
+  double* feat = nullptr;       // [J x 4]
+  double* gsum = nullptr;       // [J x G]
+  int64_t k_iter = 0;           // smc_step calls since init
+  // trace-target scratch
+  float *th_bak = nullptr, *g_bak = nullptr;
+  double *ll_bak = nullptr, *ll1 = nullptr, *phalf = nullptr, *best_score = nullptr, *best_logh = nullptr,
+         *lp0 = nullptr;
   // posterior predictive scratch (grown on demand)
   void* tx = nullptr;
   int64_t tx_rows = 0;
@@ -682,6 +691,83 @@ MoveArgs move_args(smc_t h, int mode) {
   return a;
 }
 
+
+// parameter groups of the learned proposal: W_l and b_l of every layer
+void setup_groups(smc_t h) {
+  h->G = 2 * h->L;
+  h->NO = 1 + h->G;
+  std::vector<int64_t> n(h->G);
+  for (int l = 0; l < h->L; ++l) {
+    n[2 * l] = (int64_t)h->net.nout[l] * h->net.nin[l];
+    n[2 * l + 1] = h->net.nout[l];
+  }
+  h->group_n = dalloc<int64_t>(h->owned, h->G);
+  HIPCHECK(hipMemcpyAsync(h->group_n, n.data(), n.size() * 8, hipMemcpyHostToDevice, h->stream));
+  sync(h);
+  h->sc0 = dalloc<float>(h->owned, (int64_t)h->J * h->NO);
+  h->sc1 = dalloc<float>(h->owned, (int64_t)h->J * h->NO);
+  h->feat = dalloc<double>(h->owned, (int64_t)h->J * 4);
+  h->gsum = dalloc<double>(h->owned, (int64_t)h->J * h->G);
+}
+
+double k_over_K(smc_t h) {
+  return h->cfg.n_iterations > 0 ? (double)h->k_iter / (double)h->cfg.n_iterations : 0.0;
+}
+
+// features at the handle's current (theta, g, ll) and the network's scales into `sc`
+void learned_scales(smc_t h, float* sc) {
+  const float ipv = (float)(1.0 / (h->cfg.prior_std * h->cfg.prior_std));
+  timed(h, SMC_K_OTHER, 0.0, (double)h->J * h->D * 8.0, [&]() {
+    HIPCHECK(features_run(h->net, h->theta, h->g, h->ll, ipv, (double)h->m, k_over_K(h), (double)h->m / h->n_data,
+                          h->feat, nullptr, h->G, h->stream));
+    HIPCHECK(mlp_infer_run(h->pnet, h->feat, 1, h->J, h->G, sc, 1, (float)h->h0, h->bf16, h->stream));
+  });
+}
+
+LearnedMoveArgs learned_args(smc_t h, int mode, const float* sc) {
+  LearnedMoveArgs a;
+  a.net = h->net;
+  a.theta = h->theta;
+  a.P = h->P;
+  a.g = h->g;
+  a.scales = sc;
+  a.NO = h->NO;
+  a.part = h->part;
+  a.nblk = h->nblk;
+  a.mode = mode;
+  a.inv_prior_var = (float)(1.0 / (h->cfg.prior_std * h->cfg.prior_std));
+  a.key0 = key0(h);
+  a.key1 = key1(h);
+  a.ctr_iter = (uint32_t)h->rng_iter;
+  return a;
+}
+
+void mlp_steps(float* params, float* adam, const float* feat, const float* tgt, int64_t R, int G, int first_step,
+               int n_steps, double lr, float* grad_out, double* loss_host, hipStream_t st) {
+  if (R < 1 || G < 1 || G > 2 * SMC_MAX_LAYERS) fail(SMC_ERR_ARG, "bad size");
+  HIPCHECK(mlp_set_smem_limits());
+  const int Pn = mlp_n_params(G);
+  const int64_t ntiles = (R + 63) / 64;
+  float* gp = nullptr;
+  double* lp = nullptr;
+  HIPCHECK(hipMalloc((void**)&gp, (size_t)ntiles * Pn * 4));
+  hipError_t e = hipMalloc((void**)&lp, (size_t)(ntiles + 1) * 8);
+  if (e != hipSuccess) {
+    (void)hipFree(gp);
+    HIPCHECK(e);
+  }
+  for (int i = 0; i < n_steps && e == hipSuccess; ++i)
+    e = mlp_train_step_run(params, adam, feat, tgt, R, G, gp, lp, first_step + i, (float)lr, grad_out,
+                           i == n_steps - 1 ? lp + ntiles : nullptr, st);
+  double loss = 0.0;
+  if (e == hipSuccess && loss_host) e = hipMemcpyAsync(&loss, lp + ntiles, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(gp);
+  (void)hipFree(lp);
+  HIPCHECK(e);
+  if (loss_host) *loss_host = loss;
+}
+
 smc_status guard(void (*body)(void*), void* ctx) {
   try {
     g_last_error.clear();
@@ -743,7 +829,9 @@ smc_status smc_init(const smc_config* cfg, const float* x_dev, const void* y_dev
     setup_shapes(h);
     HIPCHECK(head_set_smem_limits());
     HIPCHECK(kernels_set_smem_limits());
+    HIPCHECK(mlp_set_smem_limits());
     alloc_all(h);
+    setup_groups(h);
     upload_data(h, x_dev, y_dev);
     if (theta0_dev)
       HIPCHECK(hipMemcpyAsync(h->theta, theta0_dev, (size_t)h->J * h->D * 4, hipMemcpyDeviceToDevice, h->stream));
@@ -798,6 +886,40 @@ smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info) 
       h->lam = lambda_k;
     }
     h->rng_iter += 1;
+    h->k_iter += 1;
+    if (h->cfg.proposal == SMC_PROPOSAL_LEARNED) {
+      // learned-scale Langevin move with its Gaussian forward / reverse densities
+      learned_scales(h, h->sc0);
+      LearnedMoveArgs la = learned_args(h, MOVE_FIRST, h->sc0);
+      if (h->noise_pending) la.noise = h->noise;
+      const double nd = (double)h->J * h->D;
+      timed(h, SMC_K_MOVE, 0.0, nd * (16.0 + h->esz + (la.noise ? 4.0 : 0.0)),
+            [&]() { HIPCHECK(learned_move_run(la, h->stream)); });
+      h->noise_pending = false;
+      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g);
+      learned_scales(h, h->sc1);
+      LearnedMoveArgs lb = learned_args(h, MOVE_LAST, h->sc1);
+      timed(h, SMC_K_MOVE, 0.0, nd * 12.0, [&]() { HIPCHECK(learned_move_run(lb, h->stream)); });
+      HIPCHECK(learned_extra_run(h->sc0, h->sc1, h->NO, h->part, h->J, h->nblk, h->group_n, h->D, h->extra,
+                                 h->stream));
+      WeightArgs wa;
+      wa.J = h->J;
+      wa.nblk = h->nblk;
+      wa.lambda = lambda_k;
+      wa.inv_2prior_var = 0.5 / (h->cfg.prior_std * h->cfg.prior_std);
+      wa.ess_frac = h->cfg.ess_frac;
+      wa.ll = h->ll;
+      wa.part = h->part;
+      wa.extra = h->extra;
+      wa.no_kinetic = 1;
+      wa.lp = h->lp;
+      wa.logw = h->logw;
+      wa.w = h->w;
+      wa.stats = h->stats;
+      timed(h, SMC_K_WEIGHT, 0.0, 0.0, [&]() { HIPCHECK(weight_run(wa, h->stream)); });
+      if (info) fill_info(h, info, h->grad_evals - ev0);
+      return;
+    }
     const int S = h->cfg.leapfrog_steps;
     MoveArgs ma = move_args(h, MOVE_FIRST);
     if (h->noise_pending) ma.noise = h->noise;
@@ -998,18 +1120,125 @@ smc_status smc_set_noise(smc_t h, const float* momenta_dev) {
 smc_status smc_set_proposal_net(smc_t h, const float* params_dev, int32_t n_params, double h0) {
   return run([&]() {
     if (!h || !params_dev) fail(SMC_ERR_ARG, "null argument");
-    fail(SMC_ERR_UNSUPPORTED, "learned proposal not built yet");
-    (void)n_params;
-    (void)h0;
+    if (n_params != mlp_n_params(h->G))
+      fail(SMC_ERR_ARG, "proposal network needs " + std::to_string(mlp_n_params(h->G)) + " parameters");
+    if (!(h0 > 0) || !isfinite(h0)) fail(SMC_ERR_ARG, "h0 must be finite and > 0");
+    if (!h->pnet) h->pnet = dalloc<float>(h->owned, n_params);
+    HIPCHECK(hipMemcpyAsync(h->pnet, params_dev, (size_t)n_params * 4, hipMemcpyDeviceToDevice, h->stream));
+    h->pnet_n = n_params;
+    h->h0 = h0;
   });
 }
 
-smc_status smc_proposal_features(smc_t h, double k_over_K, double m_over_N, double* feat_dev) {
+smc_status smc_proposal_features(smc_t h, double kk, double mm, double* feat_dev) {
   return run([&]() {
     if (!h || !feat_dev) fail(SMC_ERR_ARG, "null argument");
-    fail(SMC_ERR_UNSUPPORTED, "learned proposal not built yet");
-    (void)k_over_K;
-    (void)m_over_N;
+    const float ipv = (float)(1.0 / (h->cfg.prior_std * h->cfg.prior_std));
+    HIPCHECK(features_run(h->net, h->theta, h->g, h->ll, ipv, (double)h->m, kk, mm, feat_dev, nullptr, h->G,
+                          h->stream));
+  });
+}
+
+smc_status smc_proposal_targets(smc_t h, int64_t m_k, double lambda_k, const double* h_grid, int32_t n_grid,
+                                double k_over_K_, float* feat_dev, float* target_dev) {
+  return run([&]() {
+    if (!h || !h_grid || !feat_dev || !target_dev) fail(SMC_ERR_ARG, "null argument");
+    if (n_grid < 1 || n_grid > 64) fail(SMC_ERR_ARG, "n_grid must be in [1, 64]");
+    if (m_k < h->m || m_k > h->n_data) fail(SMC_ERR_ARG, "m_k must satisfy previous m <= m_k <= n_data");
+    if (!(lambda_k > 0) || !isfinite(lambda_k)) fail(SMC_ERR_ARG, "lambda_k must be finite and > 0");
+    for (int i = 0; i < n_grid; ++i)
+      if (!(h_grid[i] > 0) || !isfinite(h_grid[i])) fail(SMC_ERR_ARG, "grid step sizes must be finite and > 0");
+    const int J = h->J;
+    const int64_t nd = (int64_t)J * h->D;
+    if (!h->th_bak) {
+      h->th_bak = dalloc<float>(h->owned, nd);
+      h->g_bak = dalloc<float>(h->owned, nd);
+      h->ll_bak = dalloc<double>(h->owned, J);
+      h->ll1 = dalloc<double>(h->owned, J);
+      h->phalf = dalloc<double>(h->owned, J);
+      h->best_score = dalloc<double>(h->owned, J);
+      h->best_logh = dalloc<double>(h->owned, J);
+      h->lp0 = dalloc<double>(h->owned, J);
+    }
+    ensure_cast(h);
+    if (m_k != h->m || lambda_k != h->lam) {
+      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g);
+      h->m = m_k;
+      h->lam = lambda_k;
+    }
+    const float ipv = (float)(1.0 / (h->cfg.prior_std * h->cfg.prior_std));
+    const double i2pv = 0.5 / (h->cfg.prior_std * h->cfg.prior_std);
+    HIPCHECK(features_run(h->net, h->theta, h->g, h->ll, ipv, (double)h->m, k_over_K_, (double)h->m / h->n_data,
+                          h->feat, h->gsum, h->G, h->stream));
+    HIPCHECK(f64_to_f32_run(h->feat, (int64_t)J * 4, feat_dev, h->stream));
+    HIPCHECK(sq_norm_rows_run(h->theta, J, h->D, h->tsq, h->stream));
+    HIPCHECK(lp_current_run(h->ll, h->tsq, J, h->lam, i2pv, h->lp0, h->stream));
+    HIPCHECK(hipMemcpyAsync(h->th_bak, h->theta, nd * 4, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHECK(hipMemcpyAsync(h->g_bak, h->g, nd * 4, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHECK(hipMemcpyAsync(h->ll_bak, h->ll, J * 8, hipMemcpyDeviceToDevice, h->stream));
+    const int64_t ev = h->grad_evals;
+    for (int i = 0; i < n_grid; ++i) {
+      if (i > 0) {
+        HIPCHECK(hipMemcpyAsync(h->theta, h->th_bak, nd * 4, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHECK(hipMemcpyAsync(h->g, h->g_bak, nd * 4, hipMemcpyDeviceToDevice, h->stream));
+      }
+      // one preconditioning-free Langevin trial with step h_grid[i] and the shared noise
+      MoveArgs ma = move_args(h, MOVE_FIRST);
+      ma.h = (float)h_grid[i];
+      ma.ctr_iter = (uint32_t)(h->rng_iter ^ 0x80000000u);
+      if (h->noise_pending) ma.noise = h->noise;
+      HIPCHECK(move_run(ma, h->stream));
+      HIPCHECK(sq_norm_rows_run(h->P, J, h->D, h->phalf, h->stream));
+      grad_pass(h, h->theta, h->m, h->lam, nullptr, h->ll1, h->g);
+      MoveArgs mb = move_args(h, MOVE_LAST);
+      mb.h = (float)h_grid[i];
+      HIPCHECK(move_run(mb, h->stream));
+      HIPCHECK(trial_score_run(h->part, J, h->nblk, h->ll1, h->lp0, h->lam, i2pv, h_grid[i], h->phalf,
+                               h->best_score, h->best_logh, i == 0 ? 1 : 0, h->stream));
+    }
+    h->grad_evals = ev;
+    h->noise_pending = false;
+    HIPCHECK(hipMemcpyAsync(h->theta, h->th_bak, nd * 4, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHECK(hipMemcpyAsync(h->g, h->g_bak, nd * 4, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHECK(hipMemcpyAsync(h->ll, h->ll_bak, J * 8, hipMemcpyDeviceToDevice, h->stream));
+    h->w_dirty = true;
+    ensure_cast(h);
+    HIPCHECK(targets_run(h->best_logh, h->gsum, h->group_n, J, h->G, h->cfg.step_size, 0.95, target_dev, h->stream));
+  });
+}
+
+int32_t smc_mlp_n_params(int32_t n_groups) { return n_groups < 1 || n_groups > 2 * SMC_MAX_LAYERS ? -1 : mlp_n_params(n_groups); }
+
+smc_status smc_mlp_forward(const float* params_dev, const float* feat_dev, int64_t R, int32_t n_groups, float* out_dev,
+                           int32_t mode, double h0, int32_t bf16, void* hip_stream) {
+  return run([&]() {
+    if (!params_dev || !feat_dev || !out_dev) fail(SMC_ERR_ARG, "null argument");
+    if (R < 0 || n_groups < 1 || n_groups > 2 * SMC_MAX_LAYERS || (mode != 0 && mode != 1))
+      fail(SMC_ERR_ARG, "bad size or mode");
+    HIPCHECK(mlp_set_smem_limits());
+    HIPCHECK(mlp_infer_run(params_dev, feat_dev, 0, R, n_groups, out_dev, mode, (float)h0, bf16 ? 1 : 0,
+                           (hipStream_t)hip_stream));
+  });
+}
+
+
+smc_status smc_mlp_grad(const float* params_dev, const float* feat_dev, const float* target_dev, int64_t R,
+                        int32_t n_groups, float* grad_dev, double* loss, void* hip_stream) {
+  return run([&]() {
+    if (!params_dev || !feat_dev || !target_dev || !grad_dev) fail(SMC_ERR_ARG, "null argument");
+    mlp_steps(const_cast<float*>(params_dev), nullptr, feat_dev, target_dev, R, n_groups, 1, 1, 0.0, grad_dev, loss,
+              (hipStream_t)hip_stream);
+  });
+}
+
+smc_status smc_mlp_train(float* params_dev, float* adam_dev, const float* feat_dev, const float* target_dev, int64_t R,
+                         int32_t n_groups, int32_t first_step, int32_t n_steps, double lr, double* loss,
+                         void* hip_stream) {
+  return run([&]() {
+    if (!params_dev || !adam_dev || !feat_dev || !target_dev) fail(SMC_ERR_ARG, "null argument");
+    if (first_step < 1 || n_steps < 1 || !(lr > 0)) fail(SMC_ERR_ARG, "first_step, n_steps >= 1 and lr > 0");
+    mlp_steps(params_dev, adam_dev, feat_dev, target_dev, R, n_groups, first_step, n_steps, lr, nullptr, loss,
+              (hipStream_t)hip_stream);
   });
 }
 

@@ -529,6 +529,17 @@ __global__ __launch_bounds__(256) void sq_norm_rows_kernel(const float* a, int64
   if (threadIdx.x == 0) out[j] = s;
 }
 
+__global__ void lp_current_kernel(const double* ll, const double* tsq, int J, double lambda, double inv_2pv,
+                                  double* out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < J) out[j] = lambda * ll[j] - tsq[j] * inv_2pv;
+}
+
+__global__ void f64_to_f32_kernel(const double* in, int64_t n, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -623,6 +634,18 @@ hipError_t fill_f64_run(double* p, int64_t n, double v, hipStream_t s) {
 hipError_t grad_with_prior_run(const float* theta, const float* g, float* out, int64_t n, float ipv, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(grad_with_prior_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, theta, g, out, n, ipv);
+  return hipGetLastError();
+}
+
+hipError_t lp_current_run(const double* ll, const double* tsq, int J, double lambda, double inv_2pv, double* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(lp_current_kernel, dim3(nblocks(J, 256)), dim3(256), 0, s, ll, tsq, J, lambda, inv_2pv, out);
+  return hipGetLastError();
+}
+
+hipError_t f64_to_f32_run(const double* in, int64_t n, float* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(f64_to_f32_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, in, n, out);
   return hipGetLastError();
 }
 

@@ -50,6 +50,7 @@ class SMCConfig:
     ess_frac: float = 0.5
     seed: int = 0
     act_budget_bytes: int = 0
+    n_iterations: int = 0
 
     def to_c(self) -> L.smc_config:
         c = L.smc_config()
@@ -69,6 +70,7 @@ class SMCConfig:
         c.ess_frac = self.ess_frac
         c.seed = self.seed
         c.act_budget_bytes = self.act_budget_bytes
+        c.n_iterations = self.n_iterations
         return c
 
 
@@ -174,6 +176,28 @@ class SMCSampler:
     def profile_read(self) -> dict:
         """{kernel class: (total_ms, launches, algorithmic flops, algorithmic bytes)}; clears the records."""
         return L.smc_profile_read(self.handle)
+
+    # ---------------------------------------------------------------- learned proposal
+    @property
+    def n_groups(self) -> int:
+        return 2 * (len(self.cfg.widths) - 1)
+
+    def set_proposal_net(self, params: torch.Tensor, h0: float) -> None:
+        L.smc_set_proposal_net(self.handle, _dev(params, torch.float32, "params"), params.numel(), float(h0))
+
+    def proposal_features(self, k_over_K: float, m_over_N: float) -> torch.Tensor:
+        out = torch.empty((self.J, 4), dtype=torch.float64, device="cuda")
+        L.smc_proposal_features(self.handle, float(k_over_K), float(m_over_N), out.data_ptr())
+        return out
+
+    def proposal_targets(self, m: int, lam: float, h_grid, k_over_K: float):
+        """(features [J x 4], raw-output targets [J x (1+G)]) at the current population."""
+        feat = torch.empty((self.J, 4), dtype=torch.float32, device="cuda")
+        tgt = torch.empty((self.J, 1 + self.n_groups), dtype=torch.float32, device="cuda")
+        L.smc_proposal_targets(self.handle, int(m), float(lam), list(h_grid), float(k_over_K), feat.data_ptr(),
+                               tgt.data_ptr())
+        self.m = int(m)
+        return feat, tgt
 
     # ---------------------------------------------------------------- network passes
     def nn_forward(self, theta: torch.Tensor, m: int) -> torch.Tensor:

@@ -1,0 +1,172 @@
+"""GPU parity of the learned proposal: network forward/gradient/Adam against the oracle,
+the learned Langevin step and its density terms against the oracle, the trace targets,
+and the reduction to the fixed-step move when the network output is constant."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import cuda, lib, print_case, rel_err, to_dev, torch
+from oracle import learned as olearned
+from oracle import mlp, smc
+import smc_inputs
+
+pytestmark = pytest.mark.gpu
+
+G = 4  # two layers: W1, b1, W2, b2
+
+
+def _blob(seed, out_scale=1.0):
+    b = olearned.init_blob(G, seed, mu=[1.0, -0.5, 0.3, 0.4], sd=[2.0, 0.7, 0.3, 0.3])
+    p = olearned.unpack_blob(b, G)
+    p["W3"][:] *= out_scale
+    p["b1"][:] = 0.1 * np.arange(64) / 64.0
+    return b
+
+
+def test_mlp_forward_and_scales_vs_oracle():
+    cuda()
+    P = lib()
+    R = 300
+    rng = np.random.default_rng(0)
+    feat = np.stack([rng.normal(1, 2, R), rng.normal(-0.5, 0.7, R), rng.random(R), rng.random(R)], 1)
+    feat[7, 0] = np.nan  # non-finite row -> fixed-step fallback in scales mode
+    blob = _blob(1, out_scale=3.0)
+    ref, _ = olearned.net_forward(blob, feat, G)
+    out = torch.empty((R, 1 + G), dtype=torch.float32, device="cuda")
+    d_blob, d_feat = to_dev(blob.astype(np.float32)), to_dev(feat.astype(np.float32))  # keep alive across calls
+    print_case("mlp-forward", R=R)
+    for bf16, tol in [(False, 2e-5), (True, 3e-2)]:
+        P._lib.smc_mlp_forward(d_blob.data_ptr(), d_feat.data_ptr(), R, G, out.data_ptr(), 0, 0.01, bf16, None)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        ok = np.isfinite(ref).all(1)
+        assert np.max(np.abs(got[ok] - ref[ok])) < tol * max(1.0, np.max(np.abs(ref[ok])))
+    P._lib.smc_mlp_forward(d_blob.data_ptr(), d_feat.data_ptr(), R, G, out.data_ptr(), 1, 0.01, False, None)
+    torch.cuda.synchronize()
+    h, mg = olearned.scales(ref, 0.01)
+    got = out.cpu().numpy()
+    assert rel_err(got[:, 0], h) < 1e-4 and rel_err(got[:, 1:], mg) < 1e-4
+    assert got[7, 0] == pytest.approx(0.01) and np.all(got[7, 1:] == 1.0)
+
+
+def test_mlp_gradient_and_adam_vs_oracle():
+    cuda()
+    P = lib()
+    R = 333
+    rng = np.random.default_rng(1)
+    feat = rng.normal(size=(R, 4)) * [2.0, 0.7, 0.3, 0.3] + [1.0, -0.5, 0.3, 0.4]
+    tgt = rng.normal(size=(R, 1 + G))
+    blob = _blob(2)
+    loss_ref, g_ref = olearned.mse_loss_grad(blob, feat, tgt, G)
+    d_blob = to_dev(blob.astype(np.float32))
+    d_feat, d_tgt = to_dev(feat.astype(np.float32)), to_dev(tgt.astype(np.float32))  # keep alive across calls
+    grad = torch.empty_like(d_blob)
+    print_case("mlp-grad", R=R)
+    loss = P._lib.smc_mlp_grad(d_blob.data_ptr(), d_feat.data_ptr(), d_tgt.data_ptr(), R, G, grad.data_ptr(), None)
+    g = grad.cpu().numpy()
+    assert abs(loss - loss_ref) < 1e-4 * loss_ref
+    assert np.max(np.abs(g - g_ref)) < 1e-4 * np.max(np.abs(g_ref))
+    # one Adam step moves every parameter by lr * g / (|g| + eps) (bias-corrected first step)
+    adam = torch.zeros(2 * blob.shape[0], dtype=torch.float32, device="cuda")
+    P._lib.smc_mlp_train(d_blob.data_ptr(), adam.data_ptr(), d_feat.data_ptr(), d_tgt.data_ptr(), R, G, 1, 1, 1e-2,
+                         None)
+    new = d_blob.cpu().numpy().astype(np.float64)
+    exp, _ = olearned.adam_update(blob.astype(np.float32).astype(np.float64), g.astype(np.float64),
+                                  (np.zeros_like(blob), np.zeros_like(blob), 0), lr=1e-2)
+    exp[:8] = blob[:8]
+    assert np.max(np.abs(new - exp)) < 1e-5
+
+
+def test_mlp_training_fits_a_smooth_target():
+    cuda()
+    from paper_2601_21983_amd import learned as plearned
+    rng = np.random.default_rng(3)
+    R = 2048
+    feat = rng.normal(size=(R, 4)).astype(np.float32)
+    tgt = np.stack([np.tanh(feat[:, 0] - feat[:, 1])] + [0.5 * np.sin(feat[:, 2] * (q + 1)) for q in range(G)], 1)
+    print_case("mlp-train", R=R)
+    d_feat, d_tgt = to_dev(feat), to_dev(tgt.astype(np.float32))
+    params, losses = plearned.train(d_feat, d_tgt, G, steps=600, lr=3e-3)
+    assert losses[-1] < 0.2 * losses[0]
+    ref, _ = olearned.net_forward(params.cpu().numpy().astype(np.float64), feat, G)
+    assert 0.5 * np.mean(np.sum((ref - tgt) ** 2, 1)) == pytest.approx(losses[-1], rel=0.1)
+
+
+def _blobs_pair(blob, h0=0.02, J=24, seed=5):
+    P = lib()
+    X, y = smc_inputs.blobs(256, seed=4)
+    widths = [2, 16, 2]
+    th0 = smc_inputs.prior_draw(seed, J, 82, 1.0)
+    cfg = P.SMCConfig(widths=widths, n_particles=J, activation="tanh", step_size=h0, proposal="learned",
+                      n_iterations=10, seed=seed)
+    g = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=128, lambda0=2.0, theta0=to_dev(th0))
+    g.set_proposal_net(to_dev(blob.astype(np.float32)), h0)
+    o = smc.Sampler(X, y, widths, "tanh", step_size=h0)
+    o.init(th0, 128, 2.0)
+    return g, o, X, y, th0
+
+
+def test_learned_step_matches_oracle():
+    cuda()
+    blob = _blob(6, out_scale=0.5)
+    g, o, X, y, th0 = _blobs_pair(blob)
+    print_case("learned-step", J=24)
+    for k, m in [(1, 192), (2, 256), (3, 256)]:
+        xi = smc_inputs.momenta(40 + k, (24, 82))
+        g.set_noise(to_dev(xi))
+        g.step(m, 256 / m)
+        olearned.learned_step(o, m, 256 / m, xi, blob.astype(np.float32).astype(np.float64), 0.02, k=k, K=10,
+                              N=256)
+        st = g.state()
+        assert np.max(np.abs(st["theta"].cpu().numpy() - o.theta)) < 1e-4 * np.max(np.abs(o.theta))
+        lw = st["logw"].cpu().numpy()
+        big = o.logw > np.log(1e-6)
+        assert np.max(np.abs(lw[big] - o.logw[big])) < 2e-3, k
+    g.close()
+
+
+def test_constant_network_reduces_to_fixed_step():
+    cuda()
+    P = lib()
+    blob = _blob(7)
+    p = olearned.unpack_blob(blob, G)
+    p["W3"][:] = 0.0
+    p["b3"][:] = 0.0
+    g, o, X, y, th0 = _blobs_pair(blob, h0=0.01)
+    cfg = P.SMCConfig(widths=[2, 16, 2], n_particles=24, activation="tanh", step_size=0.01, seed=5)
+    f = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=128, lambda0=2.0, theta0=to_dev(th0))
+    xi = to_dev(smc_inputs.momenta(9, (24, 82)))
+    g.set_noise(xi)
+    f.set_noise(xi)
+    g.step(256, 1.0)
+    f.step(256, 1.0)
+    a, b = g.state(), f.state()
+    assert np.max(np.abs(a["theta"].cpu().numpy() - b["theta"].cpu().numpy())) < 1e-6
+    assert np.max(np.abs(a["logw"].cpu().numpy() - b["logw"].cpu().numpy())) < 1e-3
+    g.close()
+    f.close()
+
+
+def test_proposal_targets_match_oracle():
+    cuda()
+    blob = _blob(8)
+    g, o, X, y, th0 = _blobs_pair(blob, h0=0.01, J=32)
+    grid = [0.01 * 2.0 ** e for e in range(-3, 4)]
+    xi = smc_inputs.momenta(11, (32, 82))
+    g.set_noise(to_dev(xi))
+    print_case("proposal-targets", J=32)
+    feat, tgt = g.proposal_targets(256, 1.0, grid, 0.0)
+    logh, logm = olearned.step_size_targets(o, 256, 1.0, xi, 0.01)
+    ref = olearned.output_targets(logh, logm, 0.01)
+    t = tgt.cpu().numpy()
+    # the argmax over the grid agrees except where two grid scores tie to rounding
+    agree = np.isclose(t[:, 0], ref[:, 0], atol=1e-5)
+    assert agree.mean() >= 0.9, agree
+    assert rel_err(t[:, 1:], ref[:, 1:]) < 1e-3
+    fo = olearned.features(*o.loglik_grad(o.theta, 256, 1.0), 256, 0, 10, 256)
+    assert np.max(np.abs(feat.cpu().numpy()[:, :2] - fo[:, :2])) < 1e-4 * np.max(np.abs(fo[:, :2]))
+    # the trials leave the population untouched
+    st = g.state()
+    assert np.array_equal(st["theta"].cpu().numpy(), th0)
+    g.close()
