@@ -233,7 +233,7 @@ SMC_API int64_t smc_chunk_samples(smc_t h);
  * particles are restored afterwards.  Outputs (device, float32):
  *   feat_dev   [J x 4]      features at the current state (see smc_proposal_features)
  *   target_dev [J x (1+G)]  raw-output regression targets: atanh of the clipped
- *              (log h* - log h)/ln 10 for the best grid step h* (h = step_size),
+ *              (log h* - log h)/ln 8 for the best grid step h* (h = step_size),
  *              and atanh of the clipped centred log RMS gradient / ln 10 per group.
  * Injected noise (smc_set_noise) is used for every trial and consumed.
  */
@@ -246,7 +246,7 @@ SMC_API int32_t smc_mlp_n_params(int32_t n_groups);
 /*
  * Stateless proposal-network passes on R rows of float32 features [R x 4]:
  *   smc_mlp_forward: mode 0 writes the raw outputs [R x (1+G)]; mode 1 the bounded
- *     scales (h0 exp(ln10 tanh o_0), exp(ln10 tanh o_g)) with (h0, 1) for rows whose
+ *     scales (h0 exp(ln8 tanh o_0), exp(ln10 tanh o_g)) with (h0, 1) for rows whose
  *     outputs are not finite.  bf16 != 0 runs the hidden 64x64 layer on BF16 MFMAs.
  *   smc_mlp_grad: FP32 gradient of (1/R) sum_r 1/2 |o_r - t_r|^2 w.r.t. the blob
  *     (zero for the input statistics mu, sd) into grad_dev, loss to *loss (host, nullable).

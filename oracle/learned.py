@@ -18,10 +18,13 @@ recomputed at theta' (the general form of Eq. weight_update):
 With constant network outputs (h, m = 1) this reduces exactly to the fixed-step
 S = 1 update.
 
-Network:  u = (f - mu) / sd;  a1 = tanh(W1 u + b1);  a2 = tanh(W2 a1 + b2);
-o = W3 a2 + b3, with 4 inputs, two hidden layers of 64 and 1 + G outputs.
-Outputs map to bounded scales:  log h = log h0 + ln(10) tanh(o_0),
-log m_g = ln(10) tanh(o_g).  Features: f = (log |grad log pi|, LL / M_k,
+Network:  u = clip((f - mu) / sd, -3, 3);  a1 = tanh(W1 u + b1);
+a2 = tanh(W2 a1 + b2);  o = W3 a2 + b3, with 4 inputs, two hidden layers of 64
+and 1 + G outputs.  The standardised inputs are clipped to three training
+standard deviations so that states outside the training traces do not
+extrapolate the network.
+Outputs map to bounded scales:  log h = log h0 + ln(8) tanh(o_0) (the range
+of the step-size grid the targets come from), log m_g = ln(10) tanh(o_g).  Features: f = (log |grad log pi|, LL / M_k,
 k / K, M_k / N).  Groups: the weight matrix and the bias vector of each layer
 (G = 2 L).
 
@@ -39,7 +42,9 @@ from .smc import Sampler, normalise, log_sum_exp, ess
 
 N_FEAT = 4
 HIDDEN = 64
+U_CLIP = 3.0
 LN10 = math.log(10.0)
+LN_H = math.log(8.0)   # bound of log(h / h0)
 
 
 def n_groups(widths):
@@ -90,7 +95,7 @@ def init_blob(G, seed, mu=None, sd=None):
 def net_forward(blob, f, G):
     """Network outputs o [R x (1+G)] and the activations for backpropagation."""
     p = unpack_blob(blob, G)
-    u = (np.asarray(f, dtype=np.float64) - p["mu"]) / p["sd"]
+    u = np.clip((np.asarray(f, dtype=np.float64) - p["mu"]) / p["sd"], -U_CLIP, U_CLIP)
     a1 = np.tanh(u @ p["W1"].T + p["b1"])
     a2 = np.tanh(a1 @ p["W2"].T + p["b2"])
     o = a2 @ p["W3"].T + p["b3"]
@@ -148,7 +153,7 @@ def scales(o, h0):
     o = np.asarray(o, dtype=np.float64)
     ok = np.all(np.isfinite(o), axis=1)
     o = np.where(ok[:, None], o, 0.0)
-    h = h0 * np.exp(LN10 * np.tanh(o[:, 0]))
+    h = h0 * np.exp(LN_H * np.tanh(o[:, 0]))
     mg = np.exp(LN10 * np.tanh(o[:, 1:]))
     return h, mg
 
@@ -237,7 +242,7 @@ def step_size_targets(s: Sampler, m, lam, xi, h0, grid=tuple(range(-3, 4))):
 
 def output_targets(log_h, log_m, h0, clip=0.95):
     """Raw-output regression targets: the inverse of ``scales`` on clipped values."""
-    t0 = np.arctanh(np.clip((np.asarray(log_h) - math.log(h0)) / LN10, -clip, clip))
+    t0 = np.arctanh(np.clip((np.asarray(log_h) - math.log(h0)) / LN_H, -clip, clip))
     tg = np.arctanh(np.clip(np.asarray(log_m) / LN10, -clip, clip))
     return np.concatenate([t0[:, None], tg], axis=1)
 

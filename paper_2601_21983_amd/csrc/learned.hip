@@ -10,7 +10,8 @@
 // Eq. weight_update.
 //
 // Parameter blob (float): mu[4], sd[4], W1[64x4], b1[64], W2[64x64], b2[64],
-// W3[NO x 64], b3[NO] with NO = 1 + G; matrices [out x in] row-major.
+// W3[NO x 64], b3[NO] with NO = 1 + G; matrices [out x in] row-major.  The
+// standardised inputs (f - mu) / sd are clipped to [-3, 3].
 // Inference runs the 64x64 layer on BF16 MFMAs (v_mfma_f32_16x16x16_bf16);
 // training runs it on FP32 MFMAs (v_mfma_f32_16x16x4_f32) and reduces per-tile
 // gradient partials in a fixed order before the Adam update (Kingma and Ba).
@@ -27,6 +28,7 @@ constexpr int NF = 4;        // features
 constexpr int RT = 64;       // rows per workgroup tile
 constexpr int LA = NH + 4;   // padded LDS row of the activation tiles (floats)
 constexpr float LN10 = 2.302585092994046f;
+constexpr float LN_H = 2.0794415416798357f;  // bound of log(h / h0): the step-size grid spans h0 8^(+-1)
 
 struct MlpOff {
   int mu, sd, W1, b1, W2, b2, W3, b3, P;
@@ -124,7 +126,9 @@ __device__ void stage_inputs(const FT* feat, int64_t R, int64_t r0, const float*
     const int r = e / NF, f = e - r * NF;
     const int64_t gr = r0 + r;
     const float x = gr < R ? (float)feat[gr * NF + f] : 0.0f;
-    u[e] = (x - P[off.mu + f]) / P[off.sd + f];
+    // standardised inputs are clipped to three training standard deviations (NaN passes through)
+    const float z = (x - P[off.mu + f]) / P[off.sd + f];
+    u[e] = z > 3.0f ? 3.0f : (z < -3.0f ? -3.0f : z);
   }
   __syncthreads();
 }
@@ -179,7 +183,7 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const float* params, con
     } else {
       bool ok = true;
       for (int c = 0; c < NO; ++c) ok = ok && isfinite(o[c]);
-      dst[0] = ok ? h0 * expf(LN10 * tanhf(o[0])) : h0;
+      dst[0] = ok ? h0 * expf(LN_H * tanhf(o[0])) : h0;
       for (int c = 1; c < NO; ++c) dst[c] = ok ? expf(LN10 * tanhf(o[c])) : 1.0f;
     }
   }
@@ -493,7 +497,7 @@ __global__ void targets_kernel(const double* best_logh, const double* gsum, cons
   if (j >= J) return;
   const int NO = 1 + G;
   const double ln10 = 2.302585092994046;
-  double t0 = (best_logh[j] - log(h0)) / ln10;
+  double t0 = (best_logh[j] - log(h0)) / 2.0794415416798357;  // ln 8
   t0 = fmax(-clip, fmin(clip, t0));
   tgt[(int64_t)j * NO] = (float)atanh(t0);
   double lm[2 * MAX_LAYERS];

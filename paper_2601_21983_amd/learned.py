@@ -60,7 +60,24 @@ def collect_traces(sampler, sizes, N: int, h_grid, every: int = 1, resample: str
     return torch.cat(feats), torch.cat(tgts)
 
 
-def train(feat: torch.Tensor, tgt: torch.Tensor, n_groups: int, steps: int = 2000, lr: float = 3e-3,
+def traces_from_runs(make_sampler, seeds, sizes, N: int, h_grid, every: int = 1):
+    """Traces of several plain-sampler runs (one per seed) concatenated.
+
+    make_sampler(seed) must return a fresh plain (fixed-step) SMCSampler at M_0 =
+    sizes[0]; several runs cover more of the state space the learned sampler visits.
+    """
+    fs, ts = [], []
+    for sd in seeds:
+        s = make_sampler(sd)
+        s.resample()
+        f, t = collect_traces(s, sizes, N, h_grid, every)
+        s.close()
+        fs.append(f)
+        ts.append(t)
+    return torch.cat(fs), torch.cat(ts)
+
+
+def train(feat: torch.Tensor, tgt: torch.Tensor, n_groups: int, steps: int = 600, lr: float = 3e-3,
           seed: int = 0, chunk: int = 200):
     """Full-batch Adam on the GPU.  Returns (params, losses): the loss at the first step, then at the
     last step of every chunk (each loss is evaluated before that step's update)."""

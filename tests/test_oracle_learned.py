@@ -111,7 +111,7 @@ def test_adam_first_step_is_signed_learning_rate():
 def test_scales_fallback_and_bounds():
     o = np.array([[0.0, 0.0], [50.0, -50.0], [np.nan, 1.0]])
     h, mg = learned.scales(o, 0.01)
-    np.testing.assert_allclose(h, [0.01, 0.1, 0.01], rtol=1e-12)
+    np.testing.assert_allclose(h, [0.01, 0.08, 0.01], rtol=1e-12)
     np.testing.assert_allclose(mg[:, 0], [1.0, 0.1, 1.0], rtol=1e-12)
 
 
