@@ -12,8 +12,12 @@ One "step" is one SMC iteration: the gradient pass on the grown subset, the
 move with its gradient pass, the FP64 reweighting/normalisation/ESS and the
 (device-decided) resampling.  `value` is particle-sample gradient evaluations
 per second (sum over gradient passes of J * M_k, divided by the wall time of
-the timed steps) of the BF16 sampler; the FP32 sampler, time-to-accuracy, the
-dominant kernel's roofline fraction and the CPU oracle are reported beside it.
+the timed steps) of the headline leg, the BF16 sampler with the learned
+proposal-scale network; the plain FP32 and plain BF16 samplers,
+time-to-accuracy of each leg, the dominant kernel's roofline fraction and the
+CPU oracle are reported beside it.  The network is trained before any timed
+region on traces of two plain FP32 runs (its cost is reported separately and
+added to the learned leg's time-to-accuracy in `seconds_with_training`).
 
     python bench.py [--gpus 1] [--steps 60] [--warmup 2]
 """
@@ -54,7 +58,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
-    ap.add_argument("--precisions", default="bf16,fp32", help="comma list; the first is the headline")
+    ap.add_argument("--legs", default="bf16-learned,fp32,bf16",
+                    help="comma list of precision[-learned]; the first is the headline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -101,19 +106,52 @@ def passes(sizes, k):
     return 1 + (1 if sizes[k] != sizes[k - 1] else 0)
 
 
-def run_timed(P, dev, prec, sizes, steps, warmup, seed):
-    import torch
-    X, y = dev["X"], dev["y"]
+def leg_parts(leg):
+    prec, _, prop = leg.partition("-")
+    return prec, ("learned" if prop == "learned" else "fixed")
+
+
+def new_sampler(P, dev, leg, sizes, seed, net=None):
+    prec, prop = leg_parts(leg)
     cfg = P.SMCConfig(widths=WIDTHS, n_particles=J, activation="relu", precision=prec, step_size=STEP,
-                      prior_std=1.0, seed=seed)
+                      prior_std=1.0, seed=seed, proposal=prop, n_iterations=K_FULL)
+    s = P.SMCSampler(cfg, dev["X"], dev["y"], m0=sizes[0], lambda0=N_TRAIN / sizes[0])
+    if prop == "learned":
+        s.set_proposal_net(net, STEP)
+    return s
+
+
+def train_proposal(P, dev, sizes, seeds=(11, 12), every=2, steps=600):
+    """Traces of plain FP32 runs, then full-batch Adam on the GPU; returns (params, info)."""
+    import torch
+    from paper_2601_21983_amd import learned as PL
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    feat, tgt = PL.traces_from_runs(lambda sd: new_sampler(P, dev, "fp32", sizes, sd), seeds, sizes, N_TRAIN,
+                                    PL.default_grid(STEP), every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    params, losses = PL.train(feat, tgt, 2 * (len(WIDTHS) - 1), steps=steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = {"trace_seconds": round(t1 - t0, 3), "train_seconds": round(t2 - t1, 3),
+            "seconds": round(t2 - t0, 3), "rows": int(feat.shape[0]), "adam_steps": steps,
+            "loss_initial": round(losses[0], 5), "loss_final": round(losses[-1], 5),
+            "traces": f"plain FP32 runs with seeds {list(seeds)}, every {every} iterations, "
+                      f"step grid h0*2^-3..h0*2^3"}
+    return params, info
+
+
+def run_timed(P, dev, leg, sizes, steps, warmup, seed, net=None):
+    import torch
     if warmup > 0:
-        w = P.SMCSampler(cfg, X, y, m0=sizes[0], lambda0=N_TRAIN / sizes[0])
+        w = new_sampler(P, dev, leg, sizes, seed, net)
         for k in range(1, min(warmup, len(sizes) - 1) + 1):
             w.step(sizes[k], N_TRAIN / sizes[k], info=False)
             w.resample()
         torch.cuda.synchronize()
         w.close()
-    s = P.SMCSampler(cfg, X, y, m0=sizes[0], lambda0=N_TRAIN / sizes[0])
+    s = new_sampler(P, dev, leg, sizes, seed, net)
     s.resample()
     s.profile(True)
     s.profile_read()
@@ -130,28 +168,27 @@ def run_timed(P, dev, prec, sizes, steps, warmup, seed):
     return {"seconds": t1 - t0, "evals": evals, "rate": evals / (t1 - t0), "prof": prof}
 
 
-def run_tta(P, dev, prec, sizes, steps, seed):
-    """Cumulative wall time (init + steps, evaluation excluded) and test accuracy per iteration."""
+def run_tta(P, dev, leg, sizes, steps, seed, net=None):
+    """Cumulative wall time (init + steps, evaluation excluded), test accuracy and mean log
+    predictive per iteration, and the mean ESS of the moves."""
     import torch
-    cfg = P.SMCConfig(widths=WIDTHS, n_particles=J, activation="relu", precision=prec, step_size=STEP,
-                      prior_std=1.0, seed=seed)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s = P.SMCSampler(cfg, dev["X"], dev["y"], m0=sizes[0], lambda0=N_TRAIN / sizes[0])
+    s = new_sampler(P, dev, leg, sizes, seed, net)
     s.resample()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    trace = []
+    trace, ess = [], []
     for k in range(1, steps + 1):
         t = time.perf_counter()
-        s.step(sizes[k], N_TRAIN / sizes[k], info=False)
+        ess.append(s.step(sizes[k], N_TRAIN / sizes[k])["ess"])
         s.resample()
         torch.cuda.synchronize()
         elapsed += time.perf_counter() - t
         r = s.predict(dev["Xt"], dev["yt"])
         trace.append((k, elapsed, r["accuracy"], r["mean_log_pred"]))
     s.close()
-    return trace
+    return trace, float(np.mean(ess))
 
 
 def kernel_table(prof, prec):
@@ -235,29 +272,46 @@ def main():
     dev = {"X": torch.from_numpy(X).to(cuda), "y": torch.from_numpy(y).to(cuda),
            "Xt": torch.from_numpy(Xt).to(cuda), "yt": torch.from_numpy(yt).to(cuda)}
 
-    precs = [p for p in args.precisions.split(",") if p]
+    legs = [l for l in args.legs.split(",") if l]
+    for l in legs:
+        if leg_parts(l)[0] not in PEAK or l.count("-") > 1 or (l.count("-") == 1 and not l.endswith("-learned")):
+            sys.exit(f"unknown leg {l!r}: use bf16, fp32, bf16-learned or fp32-learned")
     if args.calibrate_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=cuda)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    net, training = None, None
+    if any(leg_parts(l)[1] == "learned" for l in legs):
+        net, training = train_proposal(P, dev, sizes)
+        log(f"proposal network: {training}")
     res = {}
-    for prec in precs:
-        r = run_timed(P, dev, prec, sizes, steps, args.warmup, args.seed)
-        res[prec] = r
-        log(f"{prec}: {steps} steps in {r['seconds']:.3f} s, {r['rate']:.4g} grad-evals/s")
-        log(json.dumps(kernel_table(r["prof"], prec)))
+    for leg in legs:
+        r = run_timed(P, dev, leg, sizes, steps, args.warmup, args.seed, net)
+        res[leg] = r
+        log(f"{leg}: {steps} steps in {r['seconds']:.3f} s, {r['rate']:.4g} grad-evals/s")
+        log(json.dumps(kernel_table(r["prof"], leg_parts(leg)[0])))
 
     tta = None
-    if not args.no_tta and "fp32" in precs and "bf16" in precs:
-        traces = {p: run_tta(P, dev, p, sizes, steps, args.seed) for p in ("fp32", "bf16")}
-        target = traces["fp32"][-1][2] - 0.005
-        tta = {"target_accuracy": round(target, 4)}
-        for p, tr in traces.items():
+    if not args.no_tta:
+        traces = {l: run_tta(P, dev, l, sizes, steps, args.seed, net) for l in legs}
+        ref = "fp32" if "fp32" in traces else legs[-1]
+        ref_tr = traces[ref][0]
+        target = ref_tr[-1][2] - 0.005
+        target_mlp = ref_tr[-1][3] - 0.005
+        tta = {"reference_leg": ref, "target_accuracy": round(target, 4), "target_mean_log_pred": round(target_mlp, 5)}
+        for l, (tr, mess) in traces.items():
             hit = next((e for e in tr if e[2] >= target), None)
-            tta[p] = {"seconds": round(hit[1], 4) if hit else None, "iteration": hit[0] if hit else None,
-                      "final_accuracy": round(tr[-1][2], 4), "final_mean_log_pred": round(tr[-1][3], 5)}
+            hit_m = next((e for e in tr if e[3] >= target_mlp), None)
+            e = {"seconds": round(hit[1], 4) if hit else None, "iteration": hit[0] if hit else None,
+                 "seconds_to_mean_log_pred": round(hit_m[1], 4) if hit_m else None,
+                 "iteration_to_mean_log_pred": hit_m[0] if hit_m else None,
+                 "final_accuracy": round(tr[-1][2], 4), "final_mean_log_pred": round(tr[-1][3], 5),
+                 "mean_ess": round(mess, 2)}
+            if leg_parts(l)[1] == "learned":
+                e["seconds_with_training"] = round(hit[1] + training["seconds"], 4) if hit else None
+            tta[l] = e
         log("time-to-accuracy: " + json.dumps(tta))
 
     cpu = None
@@ -265,9 +319,9 @@ def main():
         cpu = cpu_baseline(X, y, sizes)
         log(f"cpu baseline: {cpu}")
 
-    head = precs[0]
+    head = legs[0]
+    hprec, hprop = leg_parts(head)
     b = res[head]
-    other = {p: res[p] for p in precs[1:]}
     line = {
         "metric": "particle-sample gradient evaluations per second",
         "value": round(b["rate"], 1),
@@ -279,20 +333,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": head,
+        "dtype": hprec,
         "data": "synthetic",
         "config": {"workload": "MNIST-shaped synthetic templates 60000/10000, MLP 784-100-10 ReLU, J=256, "
                                "Linear schedule C=kappa=1000 K=60, Langevin h=0.002, systematic resampling",
-                   "particles": J, "iterations": steps, "proposal": "fixed", "precision": head},
-        "roofline": roofline(b["prof"], head, steps, head == "bf16"),
+                   "particles": J, "iterations": steps, "proposal": hprop, "precision": hprec},
+        "roofline": roofline(b["prof"], hprec, steps, head == "bf16-learned"),
         "cpu_baseline": cpu,
         "time_to_accuracy": tta,
-        "kernels": {p: kernel_table(res[p]["prof"], p) for p in precs},
+        "proposal_network": training,
+        "kernels": {l: kernel_table(res[l]["prof"], leg_parts(l)[0]) for l in legs},
     }
-    for p, r in other.items():
-        line[f"{p}_plain"] = {"value": round(r["rate"], 1), "unit": "grad-evals/s",
-                              "ms_per_step": round(1e3 * r["seconds"] / steps, 4),
-                              "roofline": roofline(r["prof"], p, steps, False)}
+    for l in legs[1:]:
+        r = res[l]
+        line[l.replace("-", "_") + ("" if leg_parts(l)[1] == "learned" else "_plain")] = {
+            "value": round(r["rate"], 1), "unit": "grad-evals/s", "ms_per_step": round(1e3 * r["seconds"] / steps, 4),
+            "roofline": roofline(r["prof"], leg_parts(l)[0], steps, False)}
     print(json.dumps(line), flush=True)
 
 

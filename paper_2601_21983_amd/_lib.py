@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsmc.so")
 SMC_MAX_LAYERS = 8
 SMC_ACT_TANH, SMC_ACT_RELU = 0, 1
 SMC_LIK_CATEGORICAL, SMC_LIK_GAUSSIAN = 0, 1
-SMC_PREC_FP32, SMC_PREC_BF16 = 0, 1
+SMC_PREC_FP32, SMC_PREC_BF16, SMC_PREC_BF16X3 = 0, 1, 2
 SMC_PROPOSAL_FIXED, SMC_PROPOSAL_LEARNED = 0, 1
 SMC_MODEL_MLP, SMC_MODEL_CNN = 0, 1
 SMC_RESAMPLE_IF_NEEDED, SMC_RESAMPLE_ALWAYS, SMC_RESAMPLE_NEVER = 0, 1, 2

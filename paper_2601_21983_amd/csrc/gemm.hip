@@ -80,7 +80,8 @@ __device__ __forceinline__ float act_deriv(float a) {
 }
 
 // ACT: activation of the FWD epilogue / derivative of the DELTA epilogue (-1: none)
-template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT>
+// LO:  the FWD epilogue also stores the split-BF16 residual plane at out0 + lo_off
+template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT, bool LO>
 __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
   constexpr int VEC = Mf<T>::VEC;
   constexpr int BKE = ROW_BYTES / (int)sizeof(T);
@@ -213,13 +214,16 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
     O* slab = (O*)smem;                 // [NWM*32][SROW]
     constexpr int NWM = BM / WM;
     constexpr int SLAB_BYTES = NWM * 32 * SROW * OS;
-    static_assert(SLAB_BYTES + (NWM * 32 + BN) * 8 <= 2 * STAGE, "slab does not fit in LDS");
-    int64_t* rowaddr = (int64_t*)(smem + SLAB_BYTES);
+    // the split-BF16 residual goes through a second slab right after the first
+    static_assert(2 * SLAB_BYTES + (NWM * 32 + BN) * 8 <= 2 * STAGE, "slab does not fit in LDS");
+    O* slab_lo = (O*)(smem + SLAB_BYTES);
+    int64_t* rowaddr = (int64_t*)(smem + 2 * SLAB_BYTES);
     int64_t* colpart = rowaddr + NWM * 32;
     const OutDesc& d = p.out0;
+    constexpr bool lo = LO && EPI == EPI_FWD && sizeof(O) == 2;
     auto aligned = [&](int ve) {
       return ((uintptr_t)d.ptr % (uintptr_t)(ve * OS)) == 0 && d.rstr % ve == 0 && d.sR % ve == 0 &&
-             d.sb % ve == 0 && d.sC % ve == 0 && d.cs % ve == 0;
+             d.sb % ve == 0 && d.sC % ve == 0 && d.cs % ve == 0 && (!lo || p.lo_off % ve == 0);
     };
     const int vw = aligned(16 / OS) ? 16 / OS : (aligned(8 / OS) ? 8 / OS : 1);
     for (int lc = tid; lc < BN; lc += THREADS) {
@@ -240,7 +244,9 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
           const int lr = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
           float v = acc[i][j][q];
           if (EPI == EPI_FWD) v = act_apply<ACT>(v + bias);
-          slab[lr * SROW + lc] = cvt_out<O>(v);
+          const O vo = cvt_out<O>(v);
+          slab[lr * SROW + lc] = vo;
+          if (lo) slab_lo[lr * SROW + lc] = cvt_out<O>(v - cvt_in<O>(vo));
         }
       }
       if (tid < NWM * 32) {
@@ -257,6 +263,22 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
         if (ra < 0 || col >= N) continue;
         O* dst = (O*)d.ptr + ra + colpart[lc];
         const O* src = slab + lr * SROW + lc;
+        if (lo) {
+          // forward epilogue with BF16 output: plain copies of both planes
+          O* dlo = dst + p.lo_off;
+          const O* slo = slab_lo + lr * SROW + lc;
+          if (col + vw <= N && vw * OS == 16) {
+            *(u32x4*)dst = *(const u32x4*)src;
+            *(u32x4*)dlo = *(const u32x4*)slo;
+          } else {
+            const int n = min(vw, N - col);
+            for (int q = 0; q < n; ++q) {
+              dst[q] = src[q];
+              dlo[q] = slo[q];
+            }
+          }
+          continue;
+        }
         if (col + vw <= N && vw * OS == 16) {
           u32x4 v = *(const u32x4*)src;
           if (EPI == EPI_GRAD && p.beta) {
@@ -313,6 +335,8 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
         } else {
           if (EPI == EPI_FWD) {
             v = act_apply<ACT>(v + bias);
+            if (LO && sizeof(T) == 2)
+              *((T*)p.out0.ptr + p.lo_off + split_at(p.out0, s0, dr)) = cvt_out<T>(v - cvt_in<T>(cvt_out<T>(v)));
           } else {
             const float a = cvt_in<T>(*((const T*)p.aux.ptr + split_at(p.aux, sa, dr)));
             v *= act_deriv<ACT>(a);
@@ -327,7 +351,15 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
 
 template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT>
 hipError_t launch_one(const GemmParams& p, dim3 grid, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI, ACT>), grid, dim3(THREADS), 0, s, p);
+  if constexpr (EPI == EPI_FWD && std::is_same<T, __bf16>::value) {
+    if (p.lo_off) {
+      hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI, ACT, true>), grid, dim3(THREADS), 0, s, p);
+      return hipGetLastError();
+    }
+  } else {
+    if (p.lo_off) return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI, ACT, false>), grid, dim3(THREADS), 0, s, p);
   return hipGetLastError();
 }
 
@@ -359,8 +391,9 @@ hipError_t gemm_run(const GemmParams& p, int type, hipStream_t stream) {
   if (p.K % vec || p.lda % vec || p.ldb % vec) return hipErrorInvalidValue;
   if (((uintptr_t)p.A | (uintptr_t)p.B) & 15) return hipErrorInvalidValue;
   // the 256x128 tile keeps its 128 accumulators in registers only with the lean
-  // epilogues (identity/ReLU forward, gradient); tanh and delta epilogues use 128x128
-  const bool lean = p.epi == EPI_GRAD || (p.epi == EPI_FWD && p.act != ACT_TANH);
+  // epilogues (identity/ReLU forward without residual plane, gradient); tanh, residual
+  // and delta epilogues use 128x128
+  const bool lean = p.epi == EPI_GRAD || (p.epi == EPI_FWD && p.act != ACT_TANH && !p.lo_off);
   const bool big = lean && (int64_t)p.M * p.N >= (int64_t)256 * 128 * 512;
   if (type == GEMM_BF16) {
     return big ? launch_cfg<__bf16, 256, 128, 128, 64>(p, stream) : launch_cfg<__bf16, 128, 128, 64, 64>(p, stream);

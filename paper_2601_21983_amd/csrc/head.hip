@@ -20,6 +20,12 @@
 //   4. dW_L [16 x Hp] += delta^T . [A | 1] over the tile's samples (bias column
 //      included), kept in registers across tiles; each wave owns every fourth
 //      16-column block.
+// Split-BF16 form (SPL): every operand value v that differs between particles or
+// states is carried as hi = bf16(v) and lo = bf16(v - hi); the products use
+// hi*hi + hi*lo + lo*hi (lo*lo is below FP32 resolution), so logits and errors
+// carry about 16 mantissa bits although every MFMA input is BF16.  Data X stays
+// single BF16: its rounding is the same at every state and cancels in the
+// log-likelihood differences that enter the importance weights.
 // MFMA forms: bf16 v_mfma_f32_16x16x16_bf16 (a lane supplies 4 consecutive K
 // values), fp32 v_mfma_f32_16x16x4_f32 issued four times over a 4-wide K slice
 // (instruction t takes component t; lane groups cover K offsets 4g + t), so both
@@ -91,25 +97,28 @@ struct HeadLayout {
   int Hp, AS, WT, DS, SS;  // padded widths / LDS row strides (elements)
   int offWt, offAs, offDt, offSt, offRed, total;  // byte offsets
   bool stage;
+  int planes;              // 2 with split operands: Wc, Wt and As each have a lo plane after the hi plane
 };
 
 __host__ __device__ inline int rup(int x, int m) { return (x + m - 1) / m * m; }
 
 template <typename T>
-__host__ __device__ inline HeadLayout head_layout(int H, bool stage) {
+__host__ __device__ inline HeadLayout head_layout(int H, bool stage, bool spl) {
   HeadLayout L;
   const int e = (int)sizeof(T);
+  L.planes = spl ? 2 : 1;
   L.Hp = rup(H + 1, 16);
   L.AS = L.Hp + 16 / e * 2;  // pad: keeps 16 consecutive rows on distinct banks
   L.WT = 16 + 8 / e * 2;
   L.DS = HT + 16 / e;
   L.SS = HT + 16 / e;
-  int off = 16 * L.AS * e;  // Wc [16][AS]
+  int off = L.planes * 16 * L.AS * e;  // Wc [16][AS] (per plane)
+  off = rup(off, 16);
   L.offWt = off;
-  off += L.Hp * L.WT * e;
+  off += L.planes * L.Hp * L.WT * e;
   off = rup(off, 16);
   L.offAs = off;
-  off += HT * L.AS * e;
+  off += L.planes * HT * L.AS * e;
   off = rup(off, 16);
   L.offDt = off;
   off += 16 * L.DS * e;
@@ -126,12 +135,16 @@ __host__ __device__ inline HeadLayout head_layout(int H, bool stage) {
 
 typedef __attribute__((__vector_size__(2 * sizeof(uint32_t)))) uint32_t u32x2;
 
-template <typename T, int MODE, int NQ>
+template <typename T, int MODE, int NQ, bool SPL>
 __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const HeadLayout Lo) {
   extern __shared__ __attribute__((aligned(16))) char hsm[];
   T* Wc = (T*)hsm;
   T* Wt = (T*)(hsm + Lo.offWt);
   T* As = (T*)(hsm + Lo.offAs);
+  T* WcLo = Wc + 16 * Lo.AS;     // lo planes (SPL only)
+  T* WtLo = Wt + Lo.Hp * Lo.WT;
+  T* AsLo = As + HT * Lo.AS;
+  const bool alo = SPL && a.Alo != nullptr;  // activations carry a lo plane
   T* Dt = (T*)(hsm + Lo.offDt);
   T* St = (T*)(hsm + Lo.offSt);
   double* red = (double*)(hsm + Lo.offRed);
@@ -147,34 +160,41 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
   for (int e = tid; e < 16 * AS; e += HTHREADS) {
     const int c = e / AS, h = e - c * AS;
     const float v = (c < C && h <= H) ? wsrc[c * (H + 1) + h] : 0.0f;
-    Wc[e] = cvt_out<T>(v);
+    const T hi = cvt_out<T>(v);
+    Wc[e] = hi;
+    if (SPL) WcLo[e] = cvt_out<T>(v - cvt_in<T>(hi));
   }
   if (MODE == HEAD_TRAIN) {
     for (int e = tid; e < Hp * WT; e += HTHREADS) {
       const int h = e / WT, c = e - h * WT;
       const float v = (c < C && h < H) ? wsrc[c * (H + 1) + h] : 0.0f;
-      Wt[e] = cvt_out<T>(v);
+      const T hi = cvt_out<T>(v);
+      Wt[e] = hi;
+      if (SPL) WtLo[e] = cvt_out<T>(v - cvt_in<T>(hi));
     }
   }
   // activation tile: columns >= H are constant (1 at H, 0 beyond) for the whole kernel
   for (int e = tid; e < HT * (AS - H); e += HTHREADS) {
     const int s = e / (AS - H), h = H + (e - s * (AS - H));
     As[s * AS + h] = cvt_out<T>(h == H ? 1.0f : 0.0f);
+    if (SPL) AsLo[s * AS + h] = cvt_out<T>(0.0f);
   }
 
   const float lam = a.scale ? (float)a.scale[j] : (float)a.lambda;
   const T* Aj = (const T*)a.A + (int64_t)j * a.sAj;
+  const T* Alj = alo ? (const T*)a.Alo + (int64_t)j * a.sAj : nullptr;
   const int ntiles = (a.m_valid + HT - 1) / HT;
   const int t0 = split * a.tiles_per_split;
   const int t1 = min(ntiles, t0 + a.tiles_per_split);
 
   // activation tile loader: 8-byte chunks when rows allow it, else single elements
   constexpr int CE = 8 / (int)sizeof(T);  // elements per chunk
-  const bool vec = (H % CE) == 0 && (a.sAm % CE) == 0 && (a.sAj % CE) == 0 && ((uintptr_t)a.A % 8) == 0;
+  const bool vec = (H % CE) == 0 && (a.sAm % CE) == 0 && (a.sAj % CE) == 0 && ((uintptr_t)a.A % 8) == 0 &&
+                   (!alo || ((uintptr_t)a.Alo % 8) == 0);
   const int cpr = vec ? H / CE : H;       // chunks per row
   const int nch = HT * cpr;
   const float rcpr = 1.0f / (float)cpr;
-  u32x2 pre[PF];
+  u32x2 pre[PF], prelo[SPL ? PF : 1];
   auto chunk_rc = [&](int e, int& s, int& c) {
     s = (int)(((float)e + 0.5f) * rcpr);
     c = e - s * cpr;
@@ -189,6 +209,7 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
         int s, c;
         chunk_rc(e, s, c);
         pre[q] = *(const u32x2*)(Aj + (int64_t)(tile * HT + s) * a.sAm + c * CE);
+        if (alo) prelo[SPL ? q : 0] = *(const u32x2*)(Alj + (int64_t)(tile * HT + s) * a.sAm + c * CE);
       }
     }
   };
@@ -201,18 +222,22 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
           int s, c;
           chunk_rc(e, s, c);
           *(u32x2*)(As + s * AS + c * CE) = pre[q];
+          if (alo) *(u32x2*)(AsLo + s * AS + c * CE) = prelo[SPL ? q : 0];
         }
       }
       for (int e = tid + PF * HTHREADS; e < nch; e += HTHREADS) {
         int s, c;
         chunk_rc(e, s, c);
         *(u32x2*)(As + s * AS + c * CE) = *(const u32x2*)(Aj + (int64_t)(tile * HT + s) * a.sAm + c * CE);
+        if (alo)
+          *(u32x2*)(AsLo + s * AS + c * CE) = *(const u32x2*)(Alj + (int64_t)(tile * HT + s) * a.sAm + c * CE);
       }
     } else {
       for (int e = tid; e < nch; e += HTHREADS) {
         int s, c;
         chunk_rc(e, s, c);
         As[s * AS + c] = Aj[(int64_t)(tile * HT + s) * a.sAm + c];
+        if (alo) AsLo[s * AS + c] = Alj[(int64_t)(tile * HT + s) * a.sAm + c];
       }
     }
   };
@@ -234,7 +259,18 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
     const T* arow = As + (w * 16 + cl) * AS + 4 * g;
     const T* wrow = Wc + cl * AS + 4 * g;
     f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int kb = 0; kb < NHB; ++kb) z = mma16(ld4(wrow + kb * 16), ld4(arow + kb * 16), z);
+    if (SPL) {
+      const T* wrowlo = WcLo + cl * AS + 4 * g;
+      const T* arowlo = AsLo + (w * 16 + cl) * AS + 4 * g;
+      for (int kb = 0; kb < NHB; ++kb) {
+        const typename V4<T>::type wv = ld4(wrow + kb * 16), av = ld4(arow + kb * 16);
+        z = mma16(ld4(wrowlo + kb * 16), av, z);
+        if (alo) z = mma16(wv, ld4(arowlo + kb * 16), z);
+        z = mma16(wv, av, z);
+      }
+    } else {
+      for (int kb = 0; kb < NHB; ++kb) z = mma16(ld4(wrow + kb * 16), ld4(arow + kb * 16), z);
+    }
 
     // ---- 2. likelihood and output error (sample cl, classes 4g + i)
     const int sl = w * 16 + cl;           // sample within the tile
@@ -291,12 +327,13 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
         const typename V4<T>::type bd = pack4<T>(d);
         for (int hb = 0; hb < NHB; ++hb) {
           f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+          if (SPL) v = mma16(ld4(WtLo + (hb * 16 + cl) * WT + 4 * g), bd, v);
           v = mma16(ld4(Wt + (hb * 16 + cl) * WT + 4 * g), bd, v);
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int h = hb * 16 + 4 * g + i;
             if (h < H) {
-              const float av = cvt_in<T>(As[sl * AS + h]);
+              const float av = cvt_in<T>(As[sl * AS + h]) + (alo ? cvt_in<T>(AsLo[sl * AS + h]) : 0.0f);
               const float dv = v[i] * act_grad_from_out(av, a.act);
               if (Lo.stage) St[h * SS + sl] = cvt_out<T>(dv);
               else ((T*)a.dT)[(int64_t)j * a.sdTj + (int64_t)h * a.sdTh + sg] = cvt_out<T>(dv);
@@ -327,6 +364,7 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
         for (int kb = 0; kb < HT / 16; ++kb) {
           const typename V4<T>::type av = ld4(Dt + cl * DS + kb * 16 + 4 * g);
           const typename V4<T>::type bv = gather4(As + (kb * 16 + 4 * g) * AS + hb * 16 + cl, AS);
+          if (alo) dacc[q] = mma16(av, gather4(AsLo + (kb * 16 + 4 * g) * AS + hb * 16 + cl, AS), dacc[q]);
           dacc[q] = mma16(av, bv, dacc[q]);
         }
       }
@@ -380,44 +418,49 @@ __global__ void head_reduce_kernel(const HeadArgs a, int beta, int with_grad) {
 constexpr int LDS_LIMIT = 160 * 1024;
 
 template <typename T>
-HeadLayout pick_layout(int H) {
-  HeadLayout L = head_layout<T>(H, true);
-  if (L.total > LDS_LIMIT) L = head_layout<T>(H, false);
+HeadLayout pick_layout(int H, bool spl) {
+  HeadLayout L = head_layout<T>(H, true, spl);
+  if (L.total > LDS_LIMIT) L = head_layout<T>(H, false, spl);
   return L;
 }
 
 }  // namespace
 
-bool head_supported(int H, int C, int bf16) {
+bool head_supported(int H, int C, int type) {
   if (C < 1 || C > 16 || H < 1) return false;
-  const HeadLayout L = bf16 ? pick_layout<__bf16>(H) : pick_layout<float>(H);
+  const HeadLayout L = type ? pick_layout<__bf16>(H, type == HEAD_BF16_SPLIT) : pick_layout<float>(H, false);
   return L.Hp <= 4 * 16 * MAXHB && L.total <= LDS_LIMIT;
 }
 
-hipError_t head_run(const HeadArgs& a, int mode, int bf16, hipStream_t s) {
+hipError_t head_run(const HeadArgs& a, int mode, int type, hipStream_t s) {
   const int ntiles = (a.m_valid + HT - 1) / HT;
   if (ntiles <= 0) return hipSuccess;
-  if (!head_supported(a.H, a.C, bf16)) return hipErrorInvalidValue;
+  if (!head_supported(a.H, a.C, type)) return hipErrorInvalidValue;
+  if (a.Alo && type != HEAD_BF16_SPLIT) return hipErrorInvalidValue;
   dim3 grid(a.nsplit, a.J);
-#define HEAD_LAUNCH(T, MODE)                                                                             \
+#define HEAD_LAUNCH(T, MODE, SPL)                                                                        \
   do {                                                                                                   \
-    const HeadLayout L = pick_layout<T>(a.H);                                                            \
+    const HeadLayout L = pick_layout<T>(a.H, SPL);                                                       \
     const int nq = (L.Hp / 16 + 3) / 4;                                                                  \
     if (nq <= 2)                                                                                         \
-      hipLaunchKernelGGL((head_kernel<T, MODE, 2>), grid, dim3(HTHREADS), (size_t)L.total, s, a, L);      \
+      hipLaunchKernelGGL((head_kernel<T, MODE, 2, SPL>), grid, dim3(HTHREADS), (size_t)L.total, s, a, L); \
     else if (nq <= 4)                                                                                    \
-      hipLaunchKernelGGL((head_kernel<T, MODE, 4>), grid, dim3(HTHREADS), (size_t)L.total, s, a, L);      \
+      hipLaunchKernelGGL((head_kernel<T, MODE, 4, SPL>), grid, dim3(HTHREADS), (size_t)L.total, s, a, L); \
     else                                                                                                 \
-      hipLaunchKernelGGL((head_kernel<T, MODE, 8>), grid, dim3(HTHREADS), (size_t)L.total, s, a, L);      \
+      hipLaunchKernelGGL((head_kernel<T, MODE, 8, SPL>), grid, dim3(HTHREADS), (size_t)L.total, s, a, L); \
   } while (0)
-  if (bf16) {
-    if (mode == HEAD_TRAIN) HEAD_LAUNCH(__bf16, HEAD_TRAIN);
-    else if (mode == HEAD_FORWARD) HEAD_LAUNCH(__bf16, HEAD_FORWARD);
-    else HEAD_LAUNCH(__bf16, HEAD_PREDICT);
+  if (type == HEAD_BF16_SPLIT) {
+    if (mode == HEAD_TRAIN) HEAD_LAUNCH(__bf16, HEAD_TRAIN, true);
+    else if (mode == HEAD_FORWARD) HEAD_LAUNCH(__bf16, HEAD_FORWARD, true);
+    else HEAD_LAUNCH(__bf16, HEAD_PREDICT, true);
+  } else if (type == HEAD_BF16) {
+    if (mode == HEAD_TRAIN) HEAD_LAUNCH(__bf16, HEAD_TRAIN, false);
+    else if (mode == HEAD_FORWARD) HEAD_LAUNCH(__bf16, HEAD_FORWARD, false);
+    else HEAD_LAUNCH(__bf16, HEAD_PREDICT, false);
   } else {
-    if (mode == HEAD_TRAIN) HEAD_LAUNCH(float, HEAD_TRAIN);
-    else if (mode == HEAD_FORWARD) HEAD_LAUNCH(float, HEAD_FORWARD);
-    else HEAD_LAUNCH(float, HEAD_PREDICT);
+    if (mode == HEAD_TRAIN) HEAD_LAUNCH(float, HEAD_TRAIN, false);
+    else if (mode == HEAD_FORWARD) HEAD_LAUNCH(float, HEAD_FORWARD, false);
+    else HEAD_LAUNCH(float, HEAD_PREDICT, false);
   }
 #undef HEAD_LAUNCH
   hipError_t e = hipGetLastError();
@@ -427,18 +470,22 @@ hipError_t head_run(const HeadArgs& a, int mode, int bf16, hipStream_t s) {
 }
 
 hipError_t head_set_smem_limits() {
-#define HEAD_ATTR(T, MODE, NQ) \
-  hipFuncSetAttribute((const void*)head_kernel<T, MODE, NQ>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_LIMIT)
-#define HEAD_ATTR3(T, MODE) \
-  if ((e = HEAD_ATTR(T, MODE, 2)) != hipSuccess || (e = HEAD_ATTR(T, MODE, 4)) != hipSuccess || \
-      (e = HEAD_ATTR(T, MODE, 8)) != hipSuccess) return e
+#define HEAD_ATTR(T, MODE, NQ, SPL)                                                                       \
+  hipFuncSetAttribute((const void*)head_kernel<T, MODE, NQ, SPL>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                      LDS_LIMIT)
+#define HEAD_ATTR3(T, MODE, SPL)                                                                         \
+  if ((e = HEAD_ATTR(T, MODE, 2, SPL)) != hipSuccess || (e = HEAD_ATTR(T, MODE, 4, SPL)) != hipSuccess || \
+      (e = HEAD_ATTR(T, MODE, 8, SPL)) != hipSuccess) return e
   hipError_t e = hipSuccess;
-  HEAD_ATTR3(float, HEAD_TRAIN);
-  HEAD_ATTR3(float, HEAD_FORWARD);
-  HEAD_ATTR3(float, HEAD_PREDICT);
-  HEAD_ATTR3(__bf16, HEAD_TRAIN);
-  HEAD_ATTR3(__bf16, HEAD_FORWARD);
-  HEAD_ATTR3(__bf16, HEAD_PREDICT);
+  HEAD_ATTR3(float, HEAD_TRAIN, false);
+  HEAD_ATTR3(float, HEAD_FORWARD, false);
+  HEAD_ATTR3(float, HEAD_PREDICT, false);
+  HEAD_ATTR3(__bf16, HEAD_TRAIN, false);
+  HEAD_ATTR3(__bf16, HEAD_FORWARD, false);
+  HEAD_ATTR3(__bf16, HEAD_PREDICT, false);
+  HEAD_ATTR3(__bf16, HEAD_TRAIN, true);
+  HEAD_ATTR3(__bf16, HEAD_FORWARD, true);
+  HEAD_ATTR3(__bf16, HEAD_PREDICT, true);
 #undef HEAD_ATTR3
 #undef HEAD_ATTR
   return e;

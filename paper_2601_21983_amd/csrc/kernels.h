@@ -16,6 +16,7 @@ enum { TAG_MOMENTUM = 1, TAG_RESAMPLE_U = 2, TAG_PRIOR = 3 };
 
 struct HeadArgs {
   const void* A = nullptr;          // activation (j, m, h) at A + j*sAj + m*sAm + h
+  const void* Alo = nullptr;        // split-BF16 residual plane of A (same strides), or null
   int64_t sAj = 0, sAm = 0;
   const float* theta = nullptr;     // master parameters [J x D]
   int64_t D = 0, offL = 0;          // output-layer block offset
@@ -43,8 +44,10 @@ struct HeadArgs {
   int64_t ld_logp = 0;
 };
 
-bool head_supported(int H, int C, int bf16);
-hipError_t head_run(const HeadArgs& a, int mode, int bf16, hipStream_t s);
+// operand types of the output-layer kernel
+enum HeadType { HEAD_F32 = 0, HEAD_BF16 = 1, HEAD_BF16_SPLIT = 2 };
+bool head_supported(int H, int C, int type);
+hipError_t head_run(const HeadArgs& a, int mode, int type, hipStream_t s);
 hipError_t head_set_smem_limits();
 
 // Network shape shared by the elementwise kernels.
@@ -59,7 +62,30 @@ struct NetShape {
   int64_t D = 0;
   int J = 0;
   int bf16 = 0;
+  int split = 0;                      // BF16 copies hold rows [hi | lo] of 2*ldw elements
 };
+
+// Store parameter v of particle j (layer l, output unit o, input i; i == nin is the
+// bias) into the GEMM copy of that layer.
+__device__ __forceinline__ void weight_copy_store(const NetShape& n, int j, int l, int o, int i, float v) {
+  const int64_t r = (int64_t)j * n.nout[l] + o;
+  if (i >= n.nin[l]) {
+    n.bias[l][r] = v;
+    return;
+  }
+  if (!n.bf16) {
+    ((float*)n.w[l])[r * n.ldw[l] + i] = v;
+    return;
+  }
+  __bf16* w = (__bf16*)n.w[l];
+  const __bf16 hi = to_bf16(v);
+  if (n.split) {
+    w[r * 2 * n.ldw[l] + i] = hi;
+    w[r * 2 * n.ldw[l] + n.ldw[l] + i] = to_bf16(v - from_bf16(hi));
+  } else {
+    w[r * n.ldw[l] + i] = hi;
+  }
+}
 
 struct MoveArgs {
   NetShape net;

@@ -342,12 +342,6 @@ __device__ __forceinline__ void group_of(const NetShape& n, int64_t e, int& l, i
   i = ep - o * rowlen;
 }
 
-template <typename T>
-__device__ __forceinline__ void cast_to(const NetShape& n, int j, int l, int o, int i, float v) {
-  const int64_t r = (int64_t)j * n.nout[l] + o;
-  if (i < n.nin[l]) ((T*)n.w[l])[r * n.ldw[l] + i] = cvt_out<T>(v);
-  else n.bias[l][r] = v;
-}
 
 // Learned Langevin move.  FIRST: theta' = theta + (h^2/2) gf / m + h xi / sqrt(m), P <- theta' - theta,
 // partial sums |xi|^2 (row 0) and |theta'|^2 (row 1).  LAST: reverse-kernel quadratic form
@@ -385,8 +379,7 @@ __global__ __launch_bounds__(256) void learned_move_kernel(const LearnedMoveArgs
       th[e] = t1;
       s0 += xi * xi;
       s1 += t1 * t1;
-      if (a.net.bf16) cast_to<__bf16>(a.net, j, l, o, i, t1);
-      else cast_to<float>(a.net, j, l, o, i, t1);
+      weight_copy_store(a.net, j, l, o, i, t1);
     } else {
       const float r = -P[e] - 0.5f * h * h * gf / m;
       s2 += r * r * m / (2.0f * h * h);

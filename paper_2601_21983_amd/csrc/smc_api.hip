@@ -2,8 +2,11 @@
 // orchestration of one iteration on a single HIP stream.
 //
 // Device memory layout (all owned by the handle):
-//   X   [n_pad x ldx]      inputs in the GEMM operand type, rows in annealing order,
-//                          features padded with zeros to a multiple of 8
+//   X   [n_pad x xld]      inputs in the GEMM operand type, rows in annealing order,
+//                          features padded with zeros to ldx (a multiple of 8); split
+//                          BF16 stores each row twice ([x | x], xld = 2 ldx) so that
+//                          the first-layer GEMM over K = 2 ldw computes
+//                          x . w_hi + x . w_lo with w rows stored as [w_hi | w_lo]
 //   XT  [(n_0+1) x n_pad]  the same inputs transposed, plus a row of ones so that
 //                          the weight-gradient GEMM of layer 1 also yields the bias
 //                          gradient (column n_0 of the augmented block [W | b])
@@ -12,6 +15,7 @@
 //                          is added where it is used) and momenta
 //   w_l  [J*n_l x ldw_l]   GEMM copy of each layer's weights (operand type), b_l [J*n_l]
 //   act_l [J x mc x n_l]   hidden activations of one chunk of samples, particle-major
+//                          (split BF16: followed by the residual plane of the same shape)
 //                          (one contiguous [samples x units] block per particle); layer 1
 //                          is still a single dense GEMM over the J*n_1 concatenated units,
 //                          whose epilogue scatters each particle's columns to its block
@@ -68,14 +72,15 @@ T* dalloc(std::vector<void*>& owned, int64_t n) {
 }
 
 // ------------------------------------------------------------------ data preparation kernels
+// X[r][q*ldx + c] = x[r][c] (zero padded) for q < reps; rows of reps*ldx elements
 template <typename T>
-__global__ void pack_x_kernel(const float* x, int64_t n, int F, int ldx, int64_t n_pad, T* X) {
+__global__ void pack_x_kernel(const float* x, int64_t n, int F, int ldx, int reps, int64_t n_pad, T* X) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pad * ldx) return;
   const int64_t r = i / ldx;
   const int c = (int)(i - r * ldx);
-  const float v = (r < n && c < F) ? x[r * F + c] : 0.0f;
-  X[i] = cvt_out<T>(v);
+  const T v = cvt_out<T>((r < n && c < F) ? x[r * F + c] : 0.0f);
+  for (int q = 0; q < reps; ++q) X[r * ldx * reps + q * ldx + c] = v;
 }
 
 template <typename T>
@@ -149,10 +154,11 @@ struct smc_handle {
   smc_config cfg{};
   hipStream_t stream = nullptr;
   std::vector<void*> owned;
-  int J = 0, L = 0, F = 0, C = 0, bf16 = 0;
+  int J = 0, L = 0, F = 0, C = 0, bf16 = 0, split = 0;
   int64_t D = 0;
   int64_t n_data = 0, n_pad = 0;
-  int ldx = 0;
+  int ldx = 0;  // padded feature count
+  int xld = 0;  // row stride of the X operand (2 ldx with split BF16)
   size_t esz = 4;  // operand element size
   NetShape net;
   LayerBufs lb[MAX_LAYERS];
@@ -236,6 +242,10 @@ void timed(smc_t h, int cls, double flops, double bytes, F&& launch) {
 uint32_t key0(smc_t h) { return (uint32_t)(h->cfg.seed & 0xffffffffu); }
 uint32_t key1(smc_t h) { return (uint32_t)(h->cfg.seed >> 32); }
 
+int head_type(int precision) {
+  return precision == SMC_PREC_BF16X3 ? HEAD_BF16_SPLIT : precision == SMC_PREC_BF16 ? HEAD_BF16 : HEAD_F32;
+}
+
 void check_config(const smc_config* c) {
   if (!c) fail(SMC_ERR_ARG, "null config");
   if (c->n_particles < 1 || c->n_particles > MAX_J)
@@ -254,7 +264,10 @@ void check_config(const smc_config* c) {
   } else {
     fail(SMC_ERR_ARG, "likelihood");
   }
-  if (c->precision != SMC_PREC_FP32 && c->precision != SMC_PREC_BF16) fail(SMC_ERR_ARG, "precision");
+  if (c->precision != SMC_PREC_FP32 && c->precision != SMC_PREC_BF16 && c->precision != SMC_PREC_BF16X3)
+    fail(SMC_ERR_ARG, "precision");
+  if (c->precision == SMC_PREC_BF16X3 && c->n_layers > 2)
+    fail(SMC_ERR_UNSUPPORTED, "split BF16 supports at most one hidden layer");
   if (c->proposal != SMC_PROPOSAL_FIXED && c->proposal != SMC_PROPOSAL_LEARNED) fail(SMC_ERR_ARG, "proposal");
   if (c->proposal == SMC_PROPOSAL_LEARNED && c->leapfrog_steps != 1)
     fail(SMC_ERR_UNSUPPORTED, "the learned proposal is a Langevin (S = 1) move");
@@ -268,7 +281,7 @@ void check_config(const smc_config* c) {
     for (int l = 1; l < c->n_layers; ++l)
       if (c->widths[l] % 8) fail(SMC_ERR_UNSUPPORTED, "with two or more hidden layers every hidden width must be a multiple of 8");
   const int H = c->widths[c->n_layers - 1], C = c->widths[c->n_layers];
-  if (!head_supported(H, C, c->precision == SMC_PREC_BF16))
+  if (!head_supported(H, C, head_type(c->precision)))
     fail(SMC_ERR_UNSUPPORTED, "last hidden layer too wide for the output-layer kernel (at most 495 units)");
 }
 
@@ -278,12 +291,14 @@ void setup_shapes(smc_t h) {
   h->L = c.n_layers;
   h->F = c.widths[0];
   h->C = c.widths[c.n_layers];
-  h->bf16 = c.precision == SMC_PREC_BF16;
+  h->bf16 = c.precision != SMC_PREC_FP32;
+  h->split = c.precision == SMC_PREC_BF16X3;
   h->esz = h->bf16 ? 2 : 4;
   NetShape& n = h->net;
   n.L = h->L;
   n.J = h->J;
   n.bf16 = h->bf16;
+  n.split = h->split;
   int64_t off = 0;
   for (int l = 0; l < h->L; ++l) {
     n.nin[l] = c.widths[l];
@@ -298,6 +313,7 @@ void setup_shapes(smc_t h) {
   h->D = off;
   if (h->D > (1 << 24)) fail(SMC_ERR_UNSUPPORTED, "more than 2^24 parameters per particle");
   h->ldx = (int)round_up(h->F, 8);
+  h->xld = h->split ? 2 * h->ldx : h->ldx;
   h->nblk = (int)((h->D + MOVE_ELEMS - 1) / MOVE_ELEMS);
 }
 
@@ -307,7 +323,7 @@ int64_t choose_chunk(smc_t h) {
   int64_t per_sample = 0;  // bytes of activation buffers per sample
   for (int l = 0; l < h->L - 1; ++l) {
     const int64_t u = (int64_t)h->J * h->net.nout[l];
-    per_sample += u * h->esz * 2;                                  // act + dT
+    per_sample += u * h->esz * (h->split ? 3 : 2);                 // act (+ lo plane) + dT
     if (l >= 1) per_sample += u * h->esz;                          // dR
     if (l + 1 < h->L - 1) per_sample += (int64_t)h->J * (h->net.nout[l] + 1) * h->esz;  // actT
   }
@@ -323,7 +339,7 @@ void alloc_all(smc_t h) {
   const int J = h->J;
   const int64_t D = h->D;
   h->n_pad = round_up(h->n_data, 256);
-  h->X = dalloc<char>(h->owned, h->n_pad * h->ldx * (int64_t)h->esz);
+  h->X = dalloc<char>(h->owned, h->n_pad * h->xld * (int64_t)h->esz);
   h->XT = dalloc<char>(h->owned, (int64_t)(h->F + 1) * h->n_pad * (int64_t)h->esz);
   if (h->cfg.likelihood == SMC_LIK_GAUSSIAN) h->yreal = dalloc<float>(h->owned, h->n_pad);
   else h->ylab = dalloc<int32_t>(h->owned, h->n_pad);
@@ -343,7 +359,7 @@ void alloc_all(smc_t h) {
   HIPCHECK(hipMemsetAsync(h->stats, 0, 16 * sizeof(double), h->stream));
   HIPCHECK(hipMemsetAsync(h->part, 0, (size_t)3 * J * h->nblk * sizeof(double), h->stream));
   for (int l = 0; l < h->L; ++l) {
-    const int64_t n = (int64_t)J * h->net.nout[l] * h->net.ldw[l] * (int64_t)h->esz;
+    const int64_t n = (int64_t)J * h->net.nout[l] * h->net.ldw[l] * (int64_t)h->esz * (h->split ? 2 : 1);
     h->net.w[l] = dalloc<char>(h->owned, n);
     HIPCHECK(hipMemsetAsync(h->net.w[l], 0, (size_t)n, h->stream));  // row padding stays zero
     h->net.bias[l] = dalloc<float>(h->owned, (int64_t)J * h->net.nout[l]);
@@ -353,7 +369,7 @@ void alloc_all(smc_t h) {
   for (int l = 0; l < h->L - 1; ++l) {
     const int64_t u = (int64_t)J * h->net.nout[l];
     LayerBufs& b = h->lb[l];
-    b.act = dalloc<char>(h->owned, mc * u * (int64_t)h->esz);
+    b.act = dalloc<char>(h->owned, mc * u * (int64_t)h->esz * (h->split ? 2 : 1));
     b.dT = dalloc<char>(h->owned, mc * u * (int64_t)h->esz);
     if (l >= 1) b.dR = dalloc<char>(h->owned, mc * u * (int64_t)h->esz);
     if (l + 1 < h->L - 1) {
@@ -388,12 +404,12 @@ void upload_data(smc_t h, const float* x, const void* y) {
   const int64_t nt = (int64_t)(h->F + 1) * h->n_pad;
   if (h->bf16) {
     hipLaunchKernelGGL(pack_x_kernel<__bf16>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream, x,
-                       h->n_data, h->F, h->ldx, h->n_pad, (__bf16*)h->X);
+                       h->n_data, h->F, h->ldx, h->split ? 2 : 1, h->n_pad, (__bf16*)h->X);
     hipLaunchKernelGGL(pack_xt_kernel<__bf16>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, h->stream, x,
                        h->n_data, h->F, h->n_pad, (__bf16*)h->XT);
   } else {
     hipLaunchKernelGGL(pack_x_kernel<float>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream, x,
-                       h->n_data, h->F, h->ldx, h->n_pad, (float*)h->X);
+                       h->n_data, h->F, h->ldx, 1, h->n_pad, (float*)h->X);
     hipLaunchKernelGGL(pack_xt_kernel<float>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, h->stream, x,
                        h->n_data, h->F, h->n_pad, (float*)h->XT);
   }
@@ -426,7 +442,7 @@ void gemm(smc_t h, const GemmParams& p, int cls, double flops) {
 }
 
 // Forward through the hidden layers for samples [c0, c0 + rows) of the operand X
-// (ldx-strided rows).  Writes act_l (and actT_l when a hidden layer follows).
+// (xld-strided rows).  Writes act_l (and actT_l when a hidden layer follows).
 void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows, int m_valid) {
   const int J = h->J;
   for (int l = 0; l < h->L - 1; ++l) {
@@ -439,10 +455,14 @@ void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows, int m_valid)
     p.K = h->net.ldw[l];
     if (l == 0) {
       // one dense GEMM over the concatenation of all particles' units
-      p.A = (const char*)Xop + c0 * h->ldx * (int64_t)h->esz;
-      p.lda = h->ldx;
+      p.A = (const char*)Xop + c0 * h->xld * (int64_t)h->esz;
+      p.lda = h->xld;
       p.B = h->net.w[0];
-      p.ldb = h->net.ldw[0];
+      p.ldb = h->net.ldw[0] * (h->split ? 2 : 1);
+      if (h->split) {
+        p.K = 2 * h->net.ldw[0];  // [x | x] . [w_hi | w_lo]
+        p.lo_off = h->mc * U;     // residual plane of act_0
+      }
       p.N = (int)U;
       p.batch = 1;
       p.bias = h->net.bias[0];
@@ -506,10 +526,11 @@ HeadArgs head_args(smc_t h, const float* theta) {
     a.A = h->lb[L - 2].act;
     a.sAj = h->mc * a.H;
     a.sAm = a.H;
+    if (h->split) a.Alo = (const char*)a.A + h->mc * (int64_t)h->J * a.H * (int64_t)h->esz;
   } else {
     a.A = h->X;
     a.sAj = 0;
-    a.sAm = h->ldx;
+    a.sAm = h->xld;
   }
   a.llpart = h->llpart;
   a.dWpart = h->dWpart;
@@ -537,7 +558,7 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
     const int beta = c0 > 0 ? 1 : 0;
     forward_hidden(h, h->X, c0, rows, mcv);
     HeadArgs a = head_args(h, theta);
-    if (L == 1) a.A = (const char*)h->X + c0 * h->ldx * (int64_t)h->esz;
+    if (L == 1) a.A = (const char*)h->X + c0 * h->xld * (int64_t)h->esz;
     a.m_valid = mcv;
     a.c0 = c0;
     a.lambda = lambda;
@@ -557,7 +578,7 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
       }
     }
     timed(h, SMC_K_HEAD, (train ? 6.0 : 2.0) * a.C * (double)a.H * J * mcv, 0.0,
-          [&]() { HIPCHECK(head_run(a, train ? HEAD_TRAIN : HEAD_FORWARD, h->bf16, h->stream)); });
+          [&]() { HIPCHECK(head_run(a, train ? HEAD_TRAIN : HEAD_FORWARD, head_type(h->cfg.precision), h->stream)); });
     if (!train) continue;
     // backward through the hidden layers, top down
     for (int l = L - 2; l >= 0; --l) {
@@ -1007,7 +1028,7 @@ smc_status smc_posterior_predict(smc_t h, const float* x_dev, const int32_t* y_d
     if (np > h->tx_rows) {
       if (h->tx) HIPCHECK(hipFree(h->tx));
       h->tx = nullptr;
-      HIPCHECK(hipMalloc(&h->tx, (size_t)np * h->ldx * h->esz));
+      HIPCHECK(hipMalloc(&h->tx, (size_t)np * h->xld * h->esz));
       h->tx_rows = np;
     }
     if (n > h->logp_n) {
@@ -1022,23 +1043,23 @@ smc_status smc_posterior_predict(smc_t h, const float* x_dev, const int32_t* y_d
     const int64_t nx = np * h->ldx;
     if (h->bf16)
       hipLaunchKernelGGL(pack_x_kernel<__bf16>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream, x_dev, n,
-                         h->F, h->ldx, np, (__bf16*)h->tx);
+                         h->F, h->ldx, h->split ? 2 : 1, np, (__bf16*)h->tx);
     else
       hipLaunchKernelGGL(pack_x_kernel<float>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream, x_dev, n,
-                         h->F, h->ldx, np, (float*)h->tx);
+                         h->F, h->ldx, 1, np, (float*)h->tx);
     HIPCHECK(hipGetLastError());
     for (int64_t c0 = 0; c0 < n; c0 += h->mc) {
       const int mcv = (int)std::min<int64_t>(h->mc, n - c0);
       const int rows = (int)round_up(mcv, 64);
       forward_hidden(h, h->tx, c0, rows, mcv);
       HeadArgs a = head_args(h, h->theta);
-      if (h->L == 1) a.A = (const char*)h->tx + c0 * h->ldx * (int64_t)h->esz;
+      if (h->L == 1) a.A = (const char*)h->tx + c0 * h->xld * (int64_t)h->esz;
       a.m_valid = mcv;
       a.c0 = c0;
       a.logp = h->logp;
       a.ld_logp = n;
       set_splits(h, a, mcv);
-      HIPCHECK(head_run(a, HEAD_PREDICT, h->bf16, h->stream));
+      HIPCHECK(head_run(a, HEAD_PREDICT, head_type(h->cfg.precision), h->stream));
     }
     double* pred_out = h->per_sample + 2 * n;
     HIPCHECK(predictive_run(h->logp, n, h->logw, h->J, h->C, n, y_dev, probs_dev, y_dev ? h->per_sample : nullptr,

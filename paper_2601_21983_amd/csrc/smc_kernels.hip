@@ -18,8 +18,7 @@ namespace smc {
 namespace {
 
 // ------------------------------------------------------------------ GEMM-layout cast
-template <typename T>
-__device__ __forceinline__ void cast_one(const NetShape& n, int j, int64_t e, float v) {
+__device__ __forceinline__ void cast_any(const NetShape& n, int j, int64_t e, float v) {
   int l = 0;
 #pragma unroll
   for (int q = 1; q < MAX_LAYERS; ++q)
@@ -29,15 +28,7 @@ __device__ __forceinline__ void cast_one(const NetShape& n, int j, int64_t e, fl
   int o = (int)((float)ep * n.rinv[l]);
   while (o * rowlen > ep) --o;
   while ((o + 1) * rowlen <= ep) ++o;
-  const int i = ep - o * rowlen;
-  const int64_t r = (int64_t)j * n.nout[l] + o;
-  if (i < n.nin[l]) ((T*)n.w[l])[r * n.ldw[l] + i] = cvt_out<T>(v);
-  else n.bias[l][r] = v;
-}
-
-__device__ __forceinline__ void cast_any(const NetShape& n, int j, int64_t e, float v) {
-  if (n.bf16) cast_one<__bf16>(n, j, e, v);
-  else cast_one<float>(n, j, e, v);
+  weight_copy_store(n, j, l, o, ep - o * rowlen, v);
 }
 
 __global__ __launch_bounds__(256) void cast_kernel(const NetShape n, const float* __restrict__ theta,

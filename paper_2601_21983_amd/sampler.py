@@ -16,7 +16,7 @@ from . import _lib as L
 
 _ACT = {"tanh": L.SMC_ACT_TANH, "relu": L.SMC_ACT_RELU}
 _LIK = {"categorical": L.SMC_LIK_CATEGORICAL, "gaussian": L.SMC_LIK_GAUSSIAN}
-_PREC = {"fp32": L.SMC_PREC_FP32, "bf16": L.SMC_PREC_BF16}
+_PREC = {"fp32": L.SMC_PREC_FP32, "bf16": L.SMC_PREC_BF16, "bf16x3": L.SMC_PREC_BF16X3}
 _PROP = {"fixed": L.SMC_PROPOSAL_FIXED, "learned": L.SMC_PROPOSAL_LEARNED}
 _RES = {"if_needed": L.SMC_RESAMPLE_IF_NEEDED, "always": L.SMC_RESAMPLE_ALWAYS, "never": L.SMC_RESAMPLE_NEVER}
 

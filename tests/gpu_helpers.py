@@ -29,5 +29,15 @@ def rel_err(a, b):
     return np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300))
 
 
+def bf16_round(a):
+    """Inputs rounded to the nearest BF16 value (ties to even), returned as float64.
+
+    Split-BF16 GEMMs read the data as one BF16 value; the oracle evaluated on these
+    rounded inputs is the exact quantity that mode approximates."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def print_case(name, **kw):
     print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)

@@ -5,7 +5,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import cuda, lib, print_case, rel_err, to_dev, torch
+from gpu_helpers import bf16_round, cuda, lib, print_case, rel_err, to_dev, torch
 from oracle import mlp, smc
 from oracle.philox import philox4x32
 import smc_inputs
@@ -101,6 +101,10 @@ NET_CASES = [
     ([5, 1], "relu", "gaussian", 33, 999, "fp32", 0),
     ([784, 100, 10], "relu", "categorical", 24, 1000, "bf16", 0),
     ([784, 64, 32, 10], "tanh", "categorical", 12, 700, "bf16", 0),
+    ([784, 100, 10], "relu", "categorical", 24, 1000, "bf16x3", 0),
+    ([784, 100, 10], "relu", "categorical", 24, 1000, "bf16x3", 24 * 100 * 2 * 3 * 256),
+    ([2, 16, 2], "tanh", "categorical", 64, 1000, "bf16x3", 0),
+    ([5, 1], "relu", "gaussian", 33, 999, "bf16x3", 0),
 ]
 
 
@@ -142,4 +146,41 @@ def test_loglik_and_gradient_vs_oracle(case):
     gs = np.max(np.abs(g_ref), axis=1, keepdims=True)
     err = np.max(np.abs(g_g - g_ref) / gs)
     assert err < (2e-4 if prec == "fp32" else 3e-2), err
+    if prec == "bf16x3":
+        # against the oracle on BF16-rounded inputs only the split rounding of weights and
+        # activations (relative 2^-16 per product) and of the backward errors remains
+        llb, gb = mlp.loglik_grad(theta, bf16_round(X[:M]), y[:M], widths, act, lik, 0.7, scale=scale)
+        e_ll = max(rel_err(ll_g, llb), rel_err(ll_f, llb))
+        e_g = np.max(np.abs(g_g - gb) / np.max(np.abs(gb), axis=1, keepdims=True))
+        print(f"split BF16 vs oracle on rounded inputs: ll {e_ll:.3g} grad {e_g:.3g}", flush=True)
+        assert e_ll < 1e-4, e_ll
+        assert e_g < 5e-3, e_g
     s.close()
+
+
+def test_split_bf16_loglik_differences():
+    """Log-likelihood differences between nearby parameters, the quantity the importance
+    weights depend on: plain BF16 rounds the weights and activations independently at each
+    state, split BF16 keeps that rounding at the 2^-16 level, leaving only the rounding of the
+    shared inputs."""
+    cuda()
+    P = lib()
+    widths, J, M = [784, 100, 10], 32, 2000
+    X, y = smc_inputs.templates28(M, seed=11)
+    D = mlp.n_params(widths)
+    theta = smc_inputs.prior_draw(12, J, D, 0.3)
+    theta1 = theta + 0.002 * smc_inputs.momenta(13, (J, D))
+    lam = 30.0
+    print_case("split-bf16-differences", J=J, M=M, lam=lam)
+    ref = lam * (mlp.loglik(theta1, X, y, widths, "relu") - mlp.loglik(theta, X, y, widths, "relu"))
+    err = {}
+    for prec in ("bf16", "bf16x3", "fp32"):
+        cfg = P.SMCConfig(widths=widths, n_particles=J, activation="relu", precision=prec)
+        s = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=M, lambda0=1.0, theta0=to_dev(theta))
+        d = lam * (s.nn_forward(to_dev(theta1), M) - s.nn_forward(to_dev(theta), M)).cpu().numpy()
+        s.close()
+        err[prec] = float(np.sqrt(np.mean((d - ref) ** 2)))
+    print(f"rms error of lambda * (LL(theta') - LL(theta)): {err}; sd of the exact differences "
+          f"{np.std(ref):.3g}", flush=True)
+    assert err["bf16x3"] < 0.05 * err["bf16"]
+    assert err["bf16x3"] < 0.1 * np.std(ref)

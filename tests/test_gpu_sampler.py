@@ -80,7 +80,7 @@ def test_blobs_hmc_trajectory_matches_oracle():
     g.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
 def test_mnist_shaped_trajectory(prec):
     cuda()
     N = 3000
