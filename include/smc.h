@@ -239,8 +239,11 @@ SMC_API int64_t smc_chunk_samples(smc_t h);
  * (m_k, lambda_k) first if it changed (as smc_step would), then for every step
  * size h_grid[i] runs one preconditioning-free Langevin trial from the current
  * particles with shared noise and scores it by the squared jump times
- * min(1, exp(D)), D the Metropolis log-ratio under the current target; the
- * particles are restored afterwards.  Outputs (device, float32):
+ * min(1, exp(D))^accept_power, D the Metropolis log-ratio under the current
+ * target (which is also the move's log-weight increment); accept_power = 1 is
+ * the expected squared jump distance, larger values favour steps whose
+ * increments stay near zero and so keep the ESS.  The particles are restored
+ * afterwards.  Outputs (device, float32):
  *   feat_dev   [J x 4]      features at the current state (see smc_proposal_features)
  *   target_dev [J x (1+G)]  raw-output regression targets: atanh of the clipped
  *              (log h* - log h)/ln 8 for the best grid step h* (h = step_size),
@@ -248,7 +251,7 @@ SMC_API int64_t smc_chunk_samples(smc_t h);
  * Injected noise (smc_set_noise) is used for every trial and consumed.
  */
 SMC_API smc_status smc_proposal_targets(smc_t h, int64_t m_k, double lambda_k, const double* h_grid, int32_t n_grid,
-                                        double k_over_K, float* feat_dev, float* target_dev);
+                                        double k_over_K, double accept_power, float* feat_dev, float* target_dev);
 
 /* Parameters of the proposal network for G groups (-1 if G is out of range). */
 SMC_API int32_t smc_mlp_n_params(int32_t n_groups);

@@ -198,13 +198,15 @@ def learned_step(s: Sampler, m, lam, xi, blob, h0, k, K, N):
     return s
 
 
-def step_size_targets(s: Sampler, m, lam, xi, h0, grid=tuple(range(-3, 4))):
+def step_size_targets(s: Sampler, m, lam, xi, h0, grid=tuple(range(-3, 4)), accept_power=1.0):
     """Per-particle training targets from one replayed sampler state.
 
     For every step h = h0 2^e on the grid, one preconditioning-free Langevin
-    move from the current state with the shared noise xi is scored by its
-    expected-squared-jump proxy |theta' - theta|^2 min(1, exp(D)), where D is
-    the Metropolis log-ratio of that move under the fixed target pi_k.  The
+    move from the current state with the shared noise xi is scored by
+    |theta' - theta|^2 min(1, exp(D))^p, where D is the Metropolis log-ratio of
+    that move under the fixed target pi_k (also the move's log-weight
+    increment) and p = accept_power (p = 1: the expected-squared-jump proxy;
+    larger p prefers steps whose increments stay near zero).  The
     target for log h is the best grid value.  The mass targets are the log
     RMS gradient per parameter group, centred over the groups.
     Returns (log h* [J], log m* [J x G]).
@@ -227,7 +229,7 @@ def step_size_targets(s: Sampler, m, lam, xi, h0, grid=tuple(range(-3, 4))):
         log_q = np.sum(_normal_logpdf(theta1, theta + 0.5 * h * h * g, h), axis=1)
         log_l = np.sum(_normal_logpdf(theta, theta1 + 0.5 * h * h * g1, h), axis=1)
         d = lp1 - lp0 + log_l - log_q
-        score = np.sum((theta1 - theta) ** 2, axis=1) * np.exp(np.minimum(d, 0.0))
+        score = np.sum((theta1 - theta) ** 2, axis=1) * np.exp(accept_power * np.minimum(d, 0.0))
         score = np.where(np.isfinite(score), score, -np.inf)
         better = score > best
         best = np.where(better, score, best)

@@ -94,7 +94,7 @@ _SIGS = {
     "smc_normalise": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "smc_systematic_resample": (_i32, [_vp, _i32, _d, _vp, _vp, _vp]),
     "smc_philox": (_i32, [_u32, _u32, _u32, _u32, _u32, _i64, _vp, _vp]),
-    "smc_proposal_targets": (_i32, [_handle, _i64, _d, C.POINTER(_d), _i32, _d, _vp, _vp]),
+    "smc_proposal_targets": (_i32, [_handle, _i64, _d, C.POINTER(_d), _i32, _d, _d, _vp, _vp]),
     "smc_mlp_n_params": (_i32, [_i32]),
     "smc_mlp_forward": (_i32, [_vp, _vp, _i64, _i32, _vp, _i32, _d, _i32, _vp]),
     "smc_mlp_grad": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, C.POINTER(_d), _vp]),
@@ -241,10 +241,11 @@ def smc_profile_read(h) -> dict:
     return {SMC_K_NAMES[k]: (t[k], n[k], f[k], b[k]) for k in range(SMC_K_COUNT)}
 
 
-def smc_proposal_targets(h, m_k: int, lambda_k: float, h_grid, k_over_K: float, feat_dev, target_dev) -> None:
+def smc_proposal_targets(h, m_k: int, lambda_k: float, h_grid, k_over_K: float, accept_power: float, feat_dev,
+                         target_dev) -> None:
     arr = (C.c_double * len(h_grid))(*[float(x) for x in h_grid])
-    _check(lib.smc_proposal_targets(h, m_k, lambda_k, arr, len(h_grid), k_over_K, _opt(feat_dev), _opt(target_dev)),
-           "smc_proposal_targets")
+    _check(lib.smc_proposal_targets(h, m_k, lambda_k, arr, len(h_grid), k_over_K, accept_power, _opt(feat_dev),
+                                    _opt(target_dev)), "smc_proposal_targets")
 
 
 def smc_mlp_n_params(n_groups: int) -> int:

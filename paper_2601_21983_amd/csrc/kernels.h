@@ -198,7 +198,8 @@ hipError_t learned_extra_run(const float* sc0, const float* sc1, int NO, const d
 hipError_t features_run(const NetShape& n, const float* theta, const float* g, const double* ll, float ipv, double m,
                         double k_over_K, double m_over_N, double* feat, double* gsum, int G, hipStream_t s);
 hipError_t trial_score_run(const double* part, int J, int nblk, const double* ll1, const double* lp0, double lambda,
-                           double inv_2pv, double h, const double* phalf_sq, double* best_score, double* best_logh,
+                           double inv_2pv, double h, double accept_power, const double* phalf_sq, double* best_score,
+                           double* best_logh,
                            int first, hipStream_t s);
 hipError_t targets_run(const double* best_logh, const double* gsum, const int64_t* group_n, int J, int G, double h0,
                        double clip, float* tgt, hipStream_t s);

@@ -462,8 +462,8 @@ __global__ __launch_bounds__(256) void features_kernel(const NetShape n, const f
 // Metropolis log-ratio of the Langevin trial under the current target) and the squared jump
 // h^2 |P_half|^2; keeps the best log h per particle.
 __global__ void trial_score_kernel(const double* part, int J, int nblk, const double* ll1, const double* lp0,
-                                   double lambda, double inv_2pv, double h, const double* phalf_sq, double* best_score,
-                                   double* best_logh, int first) {
+                                   double lambda, double inv_2pv, double h, double accept_power, const double* phalf_sq,
+                                   double* best_score, double* best_logh, int first) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= J) return;
   double xi2 = 0.0, t2 = 0.0, pe2 = 0.0;
@@ -474,7 +474,7 @@ __global__ void trial_score_kernel(const double* part, int J, int nblk, const do
   }
   const double lp1 = lambda * ll1[j] - t2 * inv_2pv;
   const double d = lp1 - lp0[j] - 0.5 * pe2 + 0.5 * xi2;
-  double score = h * h * phalf_sq[j] * exp(fmin(d, 0.0));
+  double score = h * h * phalf_sq[j] * exp(accept_power * fmin(d, 0.0));
   if (!isfinite(score)) score = -INFINITY;
   if (first || score > best_score[j]) {
     best_score[j] = score;
@@ -591,10 +591,11 @@ hipError_t features_run(const NetShape& n, const float* theta, const float* g, c
 }
 
 hipError_t trial_score_run(const double* part, int J, int nblk, const double* ll1, const double* lp0, double lambda,
-                           double inv_2pv, double h, const double* phalf_sq, double* best_score, double* best_logh,
+                           double inv_2pv, double h, double accept_power, const double* phalf_sq, double* best_score,
+                           double* best_logh,
                            int first, hipStream_t s) {
   hipLaunchKernelGGL(trial_score_kernel, dim3((J + 255) / 256), dim3(256), 0, s, part, J, nblk, ll1, lp0, lambda,
-                     inv_2pv, h, phalf_sq, best_score, best_logh, first);
+                     inv_2pv, h, accept_power, phalf_sq, best_score, best_logh, first);
   return hipGetLastError();
 }
 

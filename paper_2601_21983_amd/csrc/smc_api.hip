@@ -1161,9 +1161,10 @@ smc_status smc_proposal_features(smc_t h, double kk, double mm, double* feat_dev
 }
 
 smc_status smc_proposal_targets(smc_t h, int64_t m_k, double lambda_k, const double* h_grid, int32_t n_grid,
-                                double k_over_K_, float* feat_dev, float* target_dev) {
+                                double k_over_K_, double accept_power, float* feat_dev, float* target_dev) {
   return run([&]() {
     if (!h || !h_grid || !feat_dev || !target_dev) fail(SMC_ERR_ARG, "null argument");
+    if (!(accept_power >= 0) || !isfinite(accept_power)) fail(SMC_ERR_ARG, "accept_power must be finite and >= 0");
     if (n_grid < 1 || n_grid > 64) fail(SMC_ERR_ARG, "n_grid must be in [1, 64]");
     if (m_k < h->m || m_k > h->n_data) fail(SMC_ERR_ARG, "m_k must satisfy previous m <= m_k <= n_data");
     if (!(lambda_k > 0) || !isfinite(lambda_k)) fail(SMC_ERR_ARG, "lambda_k must be finite and > 0");
@@ -1214,7 +1215,7 @@ smc_status smc_proposal_targets(smc_t h, int64_t m_k, double lambda_k, const dou
       MoveArgs mb = move_args(h, MOVE_LAST);
       mb.h = (float)h_grid[i];
       HIPCHECK(move_run(mb, h->stream));
-      HIPCHECK(trial_score_run(h->part, J, h->nblk, h->ll1, h->lp0, h->lam, i2pv, h_grid[i], h->phalf,
+      HIPCHECK(trial_score_run(h->part, J, h->nblk, h->ll1, h->lp0, h->lam, i2pv, h_grid[i], accept_power, h->phalf,
                                h->best_score, h->best_logh, i == 0 ? 1 : 0, h->stream));
     }
     h->grad_evals = ev;

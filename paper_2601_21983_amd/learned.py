@@ -40,7 +40,8 @@ def init_params(n_groups: int, mu, sd, seed: int = 0) -> torch.Tensor:
     return torch.from_numpy(blob).cuda()
 
 
-def collect_traces(sampler, sizes, N: int, h_grid, every: int = 1, resample: str = "if_needed"):
+def collect_traces(sampler, sizes, N: int, h_grid, every: int = 1, resample: str = "if_needed",
+                   accept_power: float = 1.0):
     """Run the plain sampler over the schedule `sizes` ([M_0, ..., M_K]) and, every `every`
     iterations, record (features, targets) of its population before the move.
 
@@ -52,7 +53,7 @@ def collect_traces(sampler, sizes, N: int, h_grid, every: int = 1, resample: str
         lam = N / sizes[k]
         if (k - 1) % every == 0:
             # the move of iteration k sees the feature k / K
-            f, t = sampler.proposal_targets(sizes[k], lam, h_grid, k / K)
+            f, t = sampler.proposal_targets(sizes[k], lam, h_grid, k / K, accept_power)
             feats.append(f)
             tgts.append(t)
         sampler.step(sizes[k], lam, info=False)
@@ -60,7 +61,7 @@ def collect_traces(sampler, sizes, N: int, h_grid, every: int = 1, resample: str
     return torch.cat(feats), torch.cat(tgts)
 
 
-def traces_from_runs(make_sampler, seeds, sizes, N: int, h_grid, every: int = 1):
+def traces_from_runs(make_sampler, seeds, sizes, N: int, h_grid, every: int = 1, accept_power: float = 1.0):
     """Traces of several plain-sampler runs (one per seed) concatenated.
 
     make_sampler(seed) must return a fresh plain (fixed-step) SMCSampler at M_0 =
@@ -70,7 +71,7 @@ def traces_from_runs(make_sampler, seeds, sizes, N: int, h_grid, every: int = 1)
     for sd in seeds:
         s = make_sampler(sd)
         s.resample()
-        f, t = collect_traces(s, sizes, N, h_grid, every)
+        f, t = collect_traces(s, sizes, N, h_grid, every, accept_power=accept_power)
         s.close()
         fs.append(f)
         ts.append(t)

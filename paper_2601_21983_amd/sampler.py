@@ -190,12 +190,12 @@ class SMCSampler:
         L.smc_proposal_features(self.handle, float(k_over_K), float(m_over_N), out.data_ptr())
         return out
 
-    def proposal_targets(self, m: int, lam: float, h_grid, k_over_K: float):
+    def proposal_targets(self, m: int, lam: float, h_grid, k_over_K: float, accept_power: float = 1.0):
         """(features [J x 4], raw-output targets [J x (1+G)]) at the current population."""
         feat = torch.empty((self.J, 4), dtype=torch.float32, device="cuda")
         tgt = torch.empty((self.J, 1 + self.n_groups), dtype=torch.float32, device="cuda")
-        L.smc_proposal_targets(self.handle, int(m), float(lam), list(h_grid), float(k_over_K), feat.data_ptr(),
-                               tgt.data_ptr())
+        L.smc_proposal_targets(self.handle, int(m), float(lam), list(h_grid), float(k_over_K), float(accept_power),
+                               feat.data_ptr(), tgt.data_ptr())
         self.m = int(m)
         return feat, tgt
 

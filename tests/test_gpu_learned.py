@@ -148,16 +148,17 @@ def test_constant_network_reduces_to_fixed_step():
     f.close()
 
 
-def test_proposal_targets_match_oracle():
+@pytest.mark.parametrize("power", [1.0, 3.0])
+def test_proposal_targets_match_oracle(power):
     cuda()
     blob = _blob(8)
     g, o, X, y, th0 = _blobs_pair(blob, h0=0.01, J=32)
     grid = [0.01 * 2.0 ** e for e in range(-3, 4)]
     xi = smc_inputs.momenta(11, (32, 82))
     g.set_noise(to_dev(xi))
-    print_case("proposal-targets", J=32)
-    feat, tgt = g.proposal_targets(256, 1.0, grid, 0.0)
-    logh, logm = olearned.step_size_targets(o, 256, 1.0, xi, 0.01)
+    print_case("proposal-targets", J=32, accept_power=power)
+    feat, tgt = g.proposal_targets(256, 1.0, grid, 0.0, power)
+    logh, logm = olearned.step_size_targets(o, 256, 1.0, xi, 0.01, accept_power=power)
     ref = olearned.output_targets(logh, logm, 0.01)
     t = tgt.cpu().numpy()
     # the argmax over the grid agrees except where two grid scores tie to rounding

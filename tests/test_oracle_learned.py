@@ -122,3 +122,20 @@ def test_step_size_targets_prefer_stable_steps():
     logh, logm = learned.step_size_targets(s, 128, 1.0, smc_inputs.momenta(4, (12, 82)), 0.01)
     assert np.all(logh >= math.log(0.01 / 8) - 1e-12) and np.all(logh <= math.log(0.08) + 1e-12)
     np.testing.assert_allclose(logm.mean(axis=1), 0.0, atol=1e-12)
+
+
+def test_step_size_targets_without_acceptance_pick_the_longest_jump():
+    # accept_power = 0 scores a step by its squared jump alone; for a Langevin move from
+    # gradient g with noise xi that jump is |h^2/2 g + h xi|^2, computed here directly
+    s, _, _ = _sampler(0.01)
+    s.init(smc_inputs.prior_draw(5, 10, 82, 1.0), 128, 1.0)
+    xi = smc_inputs.momenta(6, (10, 82)).astype(np.float64)
+    logh, _ = learned.step_size_targets(s, 128, 1.0, xi, 0.01, accept_power=0.0)
+    _, g = s.loglik_grad(s.theta, 128, 1.0)  # gradient of log pi_k (likelihood and prior)
+    hs = 0.01 * 2.0 ** np.arange(-3, 4)
+    jumps = np.stack([np.sum((0.5 * h * h * g + h * xi) ** 2, axis=1) for h in hs], axis=1)
+    np.testing.assert_allclose(logh, np.log(hs[np.argmax(jumps, axis=1)]), rtol=1e-12)
+    # a larger exponent never prefers a step with a lower score at exponent 1 and a worse increment
+    lh1, _ = learned.step_size_targets(s, 128, 1.0, xi, 0.01, accept_power=1.0)
+    lh4, _ = learned.step_size_targets(s, 128, 1.0, xi, 0.01, accept_power=4.0)
+    assert np.all(lh4 <= logh + 1e-12) and np.all(lh1 <= logh + 1e-12)
