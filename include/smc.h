@@ -172,6 +172,18 @@ SMC_API smc_status smc_posterior_predict(smc_t h, const float* x_dev, const int3
 SMC_API smc_status smc_posterior_mean(smc_t h, double* mean_dev);
 
 /*
+ * Settling test for adaptive subset growth (an extension in the spirit of
+ * Section 3: grow the subset once the sampler has settled on the current one).
+ * Computes the weighted posterior mean theta_bar of the current population
+ * (FP64), returns in *rel_change (host) |theta_bar - theta_bar_prev| /
+ * |theta_bar_prev| against the mean of the previous call, and keeps the new
+ * mean for the next call.  The first call after smc_init or smc_set_state
+ * returns +infinity.  A caller appends kappa points when the value is below its
+ * tolerance.  Synchronises the stream.
+ */
+SMC_API smc_status smc_posterior_mean_change(smc_t h, double* rel_change);
+
+/*
  * Copy the population out (any pointer may be NULL):
  *   theta_dev [J x D] float32, logw_dev [J] normalised log-weights (float64),
  *   loglik_dev [J] subset log-likelihoods LL_k (float64),

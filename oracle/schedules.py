@@ -59,3 +59,36 @@ def sizes(name, K, N, C, kappa):
     """[M_0, M_1, ..., M_K] for the named schedule (M_0 = C)."""
     f = SCHEDULES[name]
     return [C] + [f(k, K, N, C, kappa) for k in range(1, K + 1)]
+
+
+# ---------------------------------------------------------------------------
+# Adaptive growth by the posterior-mean criterion.  The paper motivates growing
+# the subset only once the sampler has settled on the current one; here the
+# settling test is the relative change of the weighted posterior mean
+# theta_bar_k = sum_j w~_j theta_j (the Section 2 estimator with f = identity):
+# a mini-batch of kappa points is appended when
+#     |theta_bar_k - theta_bar_{k-1}| / |theta_bar_{k-1}| < tol.
+
+def posterior_mean(theta, logw):
+    """sum_j w~_j theta_j with w~ the normalised weights of the log-weights."""
+    import numpy as np
+    lw = np.asarray(logw, dtype=np.float64)
+    m = np.max(lw)
+    w = np.exp(lw - m)
+    w = w / np.sum(w)
+    return w @ np.asarray(theta, dtype=np.float64)
+
+
+def mean_change(prev, cur):
+    """|cur - prev| / |prev| (Euclidean norms); +inf when prev is zero and cur is not."""
+    import numpy as np
+    num = float(np.sqrt(np.sum((np.asarray(cur, np.float64) - np.asarray(prev, np.float64)) ** 2)))
+    den = float(np.sqrt(np.sum(np.asarray(prev, np.float64) ** 2)))
+    if den == 0.0:
+        return 0.0 if num == 0.0 else float("inf")
+    return num / den
+
+
+def adaptive_next(m, change, tol, kappa, N):
+    """Subset size of the next iteration: grow by kappa (clamped to N) once the change is below tol."""
+    return min(N, m + kappa) if change < tol else m

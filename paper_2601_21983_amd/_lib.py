@@ -81,6 +81,7 @@ _SIGS = {
     "smc_resample": (_i32, [_handle, _i32, C.POINTER(_d), C.POINTER(_i32), C.POINTER(_i32)]),
     "smc_posterior_predict": (_i32, [_handle, _vp, _vp, _i64, _vp, C.POINTER(_d), C.POINTER(_d)]),
     "smc_posterior_mean": (_i32, [_handle, _vp]),
+    "smc_posterior_mean_change": (_i32, [_handle, C.POINTER(_d)]),
     "smc_get_state": (_i32, [_handle, _vp, _vp, _vp, _vp, _vp]),
     "smc_set_state": (_i32, [_handle, _vp, _vp, _vp, _u64]),
     "smc_get_rng_counter": (_i32, [_handle, C.POINTER(_u64)]),
@@ -168,6 +169,12 @@ def smc_posterior_predict(h, x_dev, y_dev, n: int, probs_dev=None, want_metrics:
 
 def smc_posterior_mean(h, mean_dev) -> None:
     _check(lib.smc_posterior_mean(h, _opt(mean_dev)), "smc_posterior_mean")
+
+
+def smc_posterior_mean_change(h) -> float:
+    r = C.c_double(0.0)
+    _check(lib.smc_posterior_mean_change(h, C.byref(r)), "smc_posterior_mean_change")
+    return r.value
 
 
 def smc_get_state(h, theta_dev=None, logw_dev=None, loglik_dev=None, logpi_dev=None, grad_dev=None) -> None:

@@ -1,6 +1,7 @@
 """Build libsmc.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2601_21983_amd.build          # or: python paper_2601_21983_amd/build.py
+    python paper_2601_21983_amd/build.py   (runs without importing the package, whose
+                                           binding needs a library that exports every symbol)
 
 Every source under csrc/ is compiled to an object with
 ``hipcc --offload-arch=gfx950 -O3`` and linked into ``libsmc.so`` next to this

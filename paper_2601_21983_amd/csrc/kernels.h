@@ -154,6 +154,7 @@ hipError_t philox_run(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32
                       hipStream_t s);
 hipError_t prior_draw_run(float* theta, int J, int64_t D, float prior_std, uint32_t k0, uint32_t k1, hipStream_t s);
 
+hipError_t mean_change_run(const double* cur, const double* prev, int64_t D, double* out2, hipStream_t s);
 hipError_t posterior_mean_run(const float* theta, const double* w, int J, int64_t D, double* out, hipStream_t s);
 
 // combine per-particle log-probabilities into the predictive mixture for samples [0, n)

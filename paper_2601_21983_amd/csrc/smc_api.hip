@@ -197,6 +197,9 @@ struct smc_handle {
   float *th_bak = nullptr, *g_bak = nullptr;
   double *ll_bak = nullptr, *ll1 = nullptr, *phalf = nullptr, *best_score = nullptr, *best_logh = nullptr,
          *lp0 = nullptr;
+  // posterior-mean change criterion: the mean of the previous call
+  double *pm_prev = nullptr, *pm_cur = nullptr, *pm_out = nullptr;
+  bool pm_have = false;
   // posterior predictive scratch (grown on demand)
   void* tx = nullptr;
   int64_t tx_rows = 0;
@@ -1082,6 +1085,29 @@ smc_status smc_posterior_mean(smc_t h, double* mean_dev) {
   });
 }
 
+smc_status smc_posterior_mean_change(smc_t h, double* rel_change) {
+  return run([&]() {
+    if (!h || !rel_change) fail(SMC_ERR_ARG, "null argument");
+    if (!h->pm_prev) {
+      h->pm_prev = dalloc<double>(h->owned, h->D);
+      h->pm_cur = dalloc<double>(h->owned, h->D);
+      h->pm_out = dalloc<double>(h->owned, 2);
+    }
+    HIPCHECK(posterior_mean_run(h->theta, h->w, h->J, h->D, h->pm_cur, h->stream));
+    double r = INFINITY;
+    if (h->pm_have) {
+      double host[2];
+      HIPCHECK(mean_change_run(h->pm_cur, h->pm_prev, h->D, h->pm_out, h->stream));
+      HIPCHECK(hipMemcpyAsync(host, h->pm_out, sizeof(host), hipMemcpyDeviceToHost, h->stream));
+      sync(h);
+      r = host[1] > 0.0 ? sqrt(host[0]) / sqrt(host[1]) : (host[0] == 0.0 ? 0.0 : INFINITY);
+    }
+    std::swap(h->pm_prev, h->pm_cur);
+    h->pm_have = true;
+    *rel_change = r;
+  });
+}
+
 smc_status smc_get_state(smc_t h, float* theta_dev, double* logw_dev, double* loglik_dev, double* logpi_dev,
                          float* grad_dev) {
   return run([&]() {
@@ -1103,6 +1129,7 @@ smc_status smc_set_state(smc_t h, const float* theta_dev, const double* logw_dev
     if (!h || !theta_dev) fail(SMC_ERR_ARG, "handle and theta_dev are required");
     HIPCHECK(hipMemcpyAsync(h->theta, theta_dev, (size_t)h->J * h->D * 4, hipMemcpyDeviceToDevice, h->stream));
     h->w_dirty = true;
+    h->pm_have = false;
     ensure_cast(h);
     grad_pass(h, h->theta, h->m, h->lam, nullptr, h->ll, h->g);
     h->rng_iter = rng_counter;

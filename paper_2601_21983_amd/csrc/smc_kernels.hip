@@ -431,6 +431,35 @@ __global__ __launch_bounds__(256) void posterior_mean_kernel(const float* theta,
   out[d] = s;
 }
 
+// out[0] = |cur - prev|^2, out[1] = |prev|^2 in FP64; one workgroup, fixed summation order
+__global__ __launch_bounds__(1024) void mean_change_kernel(const double* cur, const double* prev, int64_t D,
+                                                          double* out) {
+  __shared__ double red[2][16];
+  double a = 0.0, b = 0.0;
+  for (int64_t d = threadIdx.x; d < D; d += blockDim.x) {
+    const double p = prev[d], e = cur[d] - p;
+    a += e * e;
+    b += p * p;
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+      sa += red[0][q];
+      sb += red[1][q];
+    }
+    out[0] = sa;
+    out[1] = sb;
+  }
+}
+
 __global__ __launch_bounds__(256) void predictive_kernel(const float* logp, int64_t ld, const double* logw, int J,
                                                          int C, int64_t n, const int32_t* y, float* probs,
                                                          double* per_sample) {
@@ -599,6 +628,11 @@ hipError_t prior_draw_run(float* theta, int J, int64_t D, float prior_std, uint3
 
 hipError_t posterior_mean_run(const float* theta, const double* w, int J, int64_t D, double* out, hipStream_t s) {
   hipLaunchKernelGGL(posterior_mean_kernel, dim3(nblocks(D, 256)), dim3(256), 0, s, theta, w, J, D, out);
+  return hipGetLastError();
+}
+
+hipError_t mean_change_run(const double* cur, const double* prev, int64_t D, double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(mean_change_kernel, dim3(1), dim3(1024), 0, s, cur, prev, D, out2);
   return hipGetLastError();
 }
 

@@ -144,6 +144,10 @@ class SMCSampler:
         L.smc_posterior_mean(self.handle, out.data_ptr())
         return out
 
+    def posterior_mean_change(self) -> float:
+        """|theta_bar - theta_bar_prev| / |theta_bar_prev| against the previous call (+inf on the first)."""
+        return L.smc_posterior_mean_change(self.handle)
+
     def state(self) -> dict:
         dev = torch.device("cuda")
         th = torch.empty((self.J, self.D), dtype=torch.float32, device=dev)

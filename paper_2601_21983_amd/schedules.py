@@ -39,3 +39,28 @@ def sizes(name: str, K: int, N: int, C: int, kappa: int) -> list[int]:
 
 
 NAMES = ("constant", "fb", "ctr", "linear", "automated")
+
+
+class PosteriorMeanSchedule:
+    """Adaptive subset growth: append kappa points (up to N) once the relative change of the
+    weighted posterior mean between consecutive iterations falls below tol.
+
+    Call ``start(sampler)`` after initialisation, then ``next(sampler)`` after every
+    iteration for the next subset size.  The change is computed on the device
+    (smc_posterior_mean_change)."""
+
+    def __init__(self, m0: int, kappa: int, tol: float, N: int):
+        if not (0 < m0 <= N) or kappa < 1 or not tol > 0:
+            raise ValueError("need 0 < m0 <= N, kappa >= 1 and tol > 0")
+        self.m, self.kappa, self.tol, self.N = int(m0), int(kappa), float(tol), int(N)
+        self.changes = []
+
+    def start(self, sampler) -> None:
+        sampler.posterior_mean_change()
+
+    def next(self, sampler) -> int:
+        c = sampler.posterior_mean_change()
+        self.changes.append(c)
+        if c < self.tol:
+            self.m = min(self.N, self.m + self.kappa)
+        return self.m

@@ -218,3 +218,39 @@ def test_argument_errors():
     with pytest.raises(P.SMCError):
         s.resample("always", u=1.5)
     s.close()
+
+
+def test_posterior_mean_criterion_drives_adaptive_growth():
+    """The device's relative posterior-mean change equals the oracle's on the GPU's own
+    populations, and the adaptive schedule appends kappa points exactly when it is below tol."""
+    cuda()
+    P = lib()
+    from oracle import schedules as osched
+    from paper_2601_21983_amd.schedules import PosteriorMeanSchedule
+    N, J, kappa, tol = 1024, 48, 128, 0.05
+    X, y = smc_inputs.blobs(N, seed=4)
+    cfg = P.SMCConfig(widths=[2, 16, 2], n_particles=J, activation="tanh", step_size=0.05, seed=3)
+    s = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=kappa, lambda0=N / kappa)
+    print_case("posterior-mean-criterion", J=J, N=N, kappa=kappa, tol=tol)
+    s.resample()
+    sched = PosteriorMeanSchedule(kappa, kappa, tol, N)
+    sched.start(s)
+    st = s.state()
+    prev = osched.posterior_mean(st["theta"].cpu().numpy(), st["logw"].cpu().numpy())
+    m, grew = kappa, 0
+    for k in range(1, 31):
+        s.step(m, N / m, info=False)
+        s.resample()
+        st = s.state()
+        cur = osched.posterior_mean(st["theta"].cpu().numpy(), st["logw"].cpu().numpy())
+        ref = osched.mean_change(prev, cur)
+        m_next = sched.next(s)
+        assert abs(sched.changes[-1] - ref) <= 1e-9 * ref + 1e-15, (k, sched.changes[-1], ref)
+        assert m_next == osched.adaptive_next(m, sched.changes[-1], tol, kappa, N)
+        grew += m_next > m
+        m, prev = m_next, cur
+    assert grew >= 1 and m <= N
+    # restoring a population forgets the previous mean
+    s.set_state(st["theta"])
+    assert s.posterior_mean_change() == float("inf")
+    s.close()

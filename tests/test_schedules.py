@@ -3,7 +3,10 @@ hand-worked values of the schedule equations (Section 3.1)."""
 import importlib.util
 import os
 
+import numpy as np
+
 from oracle import schedules as oracle_schedules
+from oracle import schedules
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -31,3 +34,24 @@ def test_product_schedules_golden():
             continue
         name, K, N, C, kap, k, mk = line.split()
         assert m.subset_size(name, int(k), int(K), int(N), int(C), int(kap)) == int(mk), line
+
+
+def test_posterior_mean_and_change():
+    theta = np.array([[1.0, 2.0, 3.0], [3.0, 2.0, 1.0], [5.0, -1.0, 0.5]])
+    # equal weights: the arithmetic mean; a one-hot weight picks that particle
+    np.testing.assert_allclose(schedules.posterior_mean(theta, np.zeros(3)), theta.mean(axis=0), rtol=1e-15)
+    np.testing.assert_array_equal(schedules.posterior_mean(theta, [-np.inf, 0.0, -np.inf]), theta[1])
+    # weights 1/4, 1/4, 1/2 from log-weights shifted by an arbitrary constant
+    lw = np.log([1.0, 1.0, 2.0]) + 123.0
+    np.testing.assert_allclose(schedules.posterior_mean(theta, lw), [3.5, 0.5, 1.25], rtol=1e-14)
+    # |(0.3, 0.4)| / |(3, 4)| = 0.5 / 5
+    assert abs(schedules.mean_change([3.0, 4.0], [3.3, 4.4]) - 0.1) < 1e-15
+    assert schedules.mean_change([0.0, 0.0], [0.0, 0.0]) == 0.0
+    assert schedules.mean_change([0.0, 0.0], [1.0, 0.0]) == float("inf")
+
+
+def test_adaptive_growth_rule():
+    assert schedules.adaptive_next(1000, 0.005, 1e-2, 1000, 50000) == 2000
+    assert schedules.adaptive_next(1000, 0.02, 1e-2, 1000, 50000) == 1000
+    assert schedules.adaptive_next(1000, 1e-2, 1e-2, 1000, 50000) == 1000  # strict comparison
+    assert schedules.adaptive_next(49500, 0.0, 1e-2, 1000, 50000) == 50000  # clamped to N
