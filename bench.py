@@ -12,8 +12,9 @@ One "step" is one SMC iteration: the gradient pass on the grown subset, the
 move with its gradient pass, the FP64 reweighting/normalisation/ESS and the
 (device-decided) resampling.  `value` is particle-sample gradient evaluations
 per second (sum over gradient passes of J * M_k, divided by the wall time of
-the timed steps) of the headline leg, the BF16 sampler with the learned
-proposal-scale network; the plain FP32 and plain BF16 samplers,
+the timed steps) of the headline leg, the split-BF16 sampler (BF16 matrix-core
+operands carried as hi/lo pairs, FP32 accumulation) with the learned
+proposal-scale network; the plain FP32, split-BF16 and plain BF16 samplers,
 time-to-accuracy of each leg, the dominant kernel's roofline fraction and the
 CPU oracle are reported beside it.  The network is trained before any timed
 region on traces of two plain FP32 runs (its cost is reported separately and
@@ -41,7 +42,7 @@ N_TRAIN, N_TEST = 60000, 10000
 K_FULL = 60
 C0 = KAPPA = 1000
 STEP = 0.002
-PEAK = {"bf16": 2500.0, "fp32": 157.3}  # dense MFMA TFLOP/s (MI355X datasheet)
+PEAK = {"bf16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3}  # dense MFMA TFLOP/s of the operand type (MI355X datasheet)
 HBM_PEAK = 8000.0  # GB/s
 ALU_PEAK = 157.3   # fp32 vector TFLOP/s
 
@@ -58,16 +59,18 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
-    ap.add_argument("--legs", default="bf16-learned,fp32,bf16",
+    ap.add_argument("--legs", default="bf16x3-learned,fp32,bf16x3,bf16",
                     help="comma list of precision[-learned]; the first is the headline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference kernel for HBM counters)")
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mnist_shaped_bf16_hbm_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mnist_shaped_bf16x3_learned_hbm_traffic.json")
+TRAFFIC_LEG = "bf16x3-learned"
 TRAFFIC_SOURCES = ["paper_2601_21983_amd/csrc/gemm.hip", "paper_2601_21983_amd/csrc/head.hip",
-                   "paper_2601_21983_amd/csrc/smc_kernels.hip", "paper_2601_21983_amd/csrc/smc_api.hip"]
+                   "paper_2601_21983_amd/csrc/smc_kernels.hip", "paper_2601_21983_amd/csrc/learned.hip",
+                   "paper_2601_21983_amd/csrc/smc_api.hip"]
 
 
 def source_digest():
@@ -275,7 +278,7 @@ def main():
     legs = [l for l in args.legs.split(",") if l]
     for l in legs:
         if leg_parts(l)[0] not in PEAK or l.count("-") > 1 or (l.count("-") == 1 and not l.endswith("-learned")):
-            sys.exit(f"unknown leg {l!r}: use bf16, fp32, bf16-learned or fp32-learned")
+            sys.exit(f"unknown leg {l!r}: use fp32, bf16 or bf16x3, optionally with -learned")
     if args.calibrate_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=cuda)
         b = torch.empty_like(a)
@@ -338,7 +341,7 @@ def main():
         "config": {"workload": "MNIST-shaped synthetic templates 60000/10000, MLP 784-100-10 ReLU, J=256, "
                                "Linear schedule C=kappa=1000 K=60, Langevin h=0.002, systematic resampling",
                    "particles": J, "iterations": steps, "proposal": hprop, "precision": hprec},
-        "roofline": roofline(b["prof"], hprec, steps, head == "bf16-learned"),
+        "roofline": roofline(b["prof"], hprec, steps, head == TRAFFIC_LEG),
         "cpu_baseline": cpu,
         "time_to_accuracy": tta,
         "proposal_network": training,
