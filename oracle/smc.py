@@ -143,10 +143,10 @@ class Sampler:
     """
 
     def __init__(self, X, y, widths, act, likelihood=mlp.CATEGORICAL, noise_std=1.0,
-                 prior_std=1.0, step_size=1e-3, leapfrog_steps=1, ess_frac=0.5):
+                 prior_std=1.0, step_size=1e-3, leapfrog_steps=1, ess_frac=0.5, model=None):
         self.X = np.asarray(X, dtype=np.float64)
         self.y = np.asarray(y)
-        self.widths = list(widths)
+        self.widths = list(widths) if widths is not None else None
         self.act = act
         self.likelihood = likelihood
         self.noise_std = float(noise_std)
@@ -154,14 +154,19 @@ class Sampler:
         self.h = float(step_size)
         self.S = int(leapfrog_steps)
         self.ess_frac = float(ess_frac)
-        self.D = mlp.n_params(self.widths)
+        # another network (e.g. oracle.cnn.Model) replaces the dense one when given
+        self.model = model
+        self.D = model.D if model is not None else mlp.n_params(self.widths)
 
     # ---- target (reading: lambda scales LL and gradient; Gaussian prior)
     def loglik_grad(self, theta, m, lam):
         """(LL_m(theta) [J], grad log pi(theta) [J x D]) on the first m samples."""
-        ll, g = mlp.loglik_grad(theta, self.X[:m], self.y[:m], self.widths, self.act,
-                                self.likelihood, self.noise_std,
-                                scale=np.full(theta.shape[0], lam))
+        if self.model is not None:
+            ll, g = self.model.loglik_grad(theta, self.X[:m], self.y[:m], np.full(theta.shape[0], lam))
+        else:
+            ll, g = mlp.loglik_grad(theta, self.X[:m], self.y[:m], self.widths, self.act,
+                                    self.likelihood, self.noise_std,
+                                    scale=np.full(theta.shape[0], lam))
         return ll, g - theta / self.prior_std ** 2
 
     def log_target(self, ll, theta, lam):
@@ -246,14 +251,17 @@ class Sampler:
         Returns (probs [n x C], accuracy or None, mean log predictive or None).
         Accuracy uses the arg-max with the lowest class index on ties.
         """
-        return predictive(self.theta, self.logw, Xt, yt, self.widths, self.act)
+        return predictive(self.theta, self.logw, Xt, yt, self.widths, self.act, self.model)
 
     def posterior_mean(self):
         return np.exp(self.logw) @ self.theta
 
 
-def predictive(theta, logw, Xt, yt, widths, act):
-    lp = mlp.predict_logprobs(theta, Xt, widths, act)          # [J x n x C]
+def predictive(theta, logw, Xt, yt, widths, act, model=None):
+    if model is not None:
+        lp = model.predict_logprobs(theta, Xt)                 # [J x n x C]
+    else:
+        lp = mlp.predict_logprobs(theta, Xt, widths, act)      # [J x n x C]
     lw = np.asarray(logw, dtype=np.float64)
     probs = np.einsum("j,jnc->nc", np.exp(lw), np.exp(lp))
     if yt is None:

@@ -79,8 +79,8 @@ def templates28(n: int, seed: int, template_seed: int = 0, n_cls: int = 10,
     return X, y
 
 
-def textures32(n: int, seed: int, template_seed: int = 0, n_cls: int = 10) -> tuple[np.ndarray, np.ndarray]:
-    """CIFAR-shaped class-conditional textures, NHWC float32 [n x 32 x 32 x 3].
+def textures32(n: int, seed: int, template_seed: int = 0, n_cls: int = 10, size: int = 32) -> tuple[np.ndarray, np.ndarray]:
+    """CIFAR-shaped class-conditional textures, NHWC float32 [n x size x size x 3] (size 32 by default).
 
     Class c has a mean colour m_c ~ N(0, 0.5) per channel and a 3x3 kernel k_c ~
     N(0, 1/9) per channel; an image is m_c + (k_c convolved with white noise),
@@ -91,13 +91,13 @@ def textures32(n: int, seed: int, template_seed: int = 0, n_cls: int = 10) -> tu
     kern = trng.normal(0.0, 1.0 / 3.0, size=(n_cls, 3, 3, 3))  # [class, dy, dx, channel]
     rng = np.random.default_rng(seed)
     y = _balanced_labels(rng, n, n_cls)
-    X = np.empty((n, 32, 32, 3), dtype=np.float32)
+    X = np.empty((n, size, size, 3), dtype=np.float32)
     step = 4096
     for s in range(0, n, step):
         e = min(n, s + step)
-        eps = rng.standard_normal((e - s, 32, 32, 3))
+        eps = rng.standard_normal((e - s, size, size, 3))
         k = kern[y[s:e]]
-        acc = np.zeros((e - s, 32, 32, 3))
+        acc = np.zeros((e - s, size, size, 3))
         for dy in range(3):
             for dx in range(3):
                 acc += k[:, dy, dx, :][:, None, None, :] * np.roll(eps, (1 - dy, 1 - dx), axis=(1, 2))
