@@ -81,12 +81,25 @@ enum { SMC_RESAMPLE_IF_NEEDED = 0, SMC_RESAMPLE_ALWAYS = 1, SMC_RESAMPLE_NEVER =
 
 #define SMC_MAX_LAYERS 8
 
+/*
+ * SMC_MODEL_CNN: the image classifier conv3x3(C1) -> ReLU -> conv3x3(C2) -> ReLU ->
+ * 2x2 average pool -> linear(n_cls), "same" zero padding, stride 1, on H x W images
+ * with Cin channels stored channel-last (x_dev row = H*W*Cin values, NHWC).  H and W
+ * even with H*W a multiple of 8, C1 and C2 multiples of 8, 2 <= n_cls <= 16,
+ * categorical likelihood, FP32 or BF16 operands.  Parameter blocks, each output
+ * unit's weights followed by its bias: conv1 [C1 x (9 Cin + 1)] with weight index
+ * (ky*3 + kx)*Cin + c, conv2 [C2 x (9 C1 + 1)] with index (ky*3 + kx)*C1 + c, linear
+ * [n_cls x ((H/2)(W/2) C2 + 1)] with input index (py*(W/2) + px)*C2 + c; output pixel
+ * (y, x) reads input pixel (y + ky - 1, x + kx - 1).  act_budget_bytes bounds the
+ * per-chunk operand buffers (patch matrices, activations and errors of all particles).
+ */
 typedef struct smc_config {
   int32_t n_particles;                 /* J >= 1 (at most 8192) */
-  int32_t n_layers;                    /* L >= 1 weight layers (at most SMC_MAX_LAYERS) */
-  int32_t widths[SMC_MAX_LAYERS + 1];  /* n_0 = input features, ..., n_L = outputs */
-  int32_t activation;                  /* hidden activation: SMC_ACT_TANH | SMC_ACT_RELU */
-  int32_t model_kind;                  /* SMC_MODEL_MLP (SMC_MODEL_CNN: see smc_cnn.h) */
+  int32_t n_layers;                    /* L >= 1 weight layers (at most SMC_MAX_LAYERS); 3 for SMC_MODEL_CNN */
+  int32_t widths[SMC_MAX_LAYERS + 1];  /* MLP: n_0 = input features, ..., n_L = outputs.
+                                          CNN: {H, W, Cin, C1, C2, n_cls} (see below) */
+  int32_t activation;                  /* hidden activation: SMC_ACT_TANH | SMC_ACT_RELU (CNN: ReLU) */
+  int32_t model_kind;                  /* SMC_MODEL_MLP | SMC_MODEL_CNN */
   int32_t likelihood;                  /* SMC_LIK_CATEGORICAL (n_L <= 16 classes) | SMC_LIK_GAUSSIAN (n_L = 1) */
   int32_t precision;                   /* GEMM operand precision; accumulation is always FP32 */
   int32_t proposal;                    /* SMC_PROPOSAL_FIXED | SMC_PROPOSAL_LEARNED (needs S = 1) */

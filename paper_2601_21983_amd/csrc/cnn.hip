@@ -1,0 +1,350 @@
+// Data-movement and reduction kernels of the particle-batched convolutional network
+// (conv3x3 -> ReLU -> conv3x3 -> ReLU -> 2x2 average pool -> linear, NHWC images).
+//
+// The contractions run on the MFMA GEMM (gemm.hip) over explicit patch matrices:
+//   conv1   [R x K1p] . [J*C1 x K1p]^T          one dense GEMM, the image patches are shared by
+//                                                 every particle (R = images x H x W pixel rows)
+//   conv2   [R x 9C1] . [C2 x 9C1]^T            batched over particles
+//   linear  [n x F3]  . [ncls x F3]^T           batched over particles
+//   backward: errors through the linear layer ([n x 16] . [F3 x 16]^T), the conv2 weight
+//   gradient ([C2 x R] . [(9C1+1) x R]^T, the ones row yields the bias), the conv2 input error
+//   ([R x C2] . [9C1 x C2]^T, then summed back onto pixels) and the conv1 weight gradient
+//   ([J*C1 x R] . [(K1+1) x R]^T).
+// The kernels here build those operands (im2col in both orientations, pooling and its
+// adjoint with the ReLU masks, the col2im sum), the per-particle log-likelihood with its
+// output error, and the linear layer's weight gradient.  Patch index k = tap * C + c with
+// tap = ky * 3 + kx; output pixel (y, x) reads input pixel (y + ky - 1, x + kx - 1).
+#include "kernels.h"
+
+namespace smc {
+
+namespace {
+
+__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+// input pixel read by patch element (tap) of output pixel pix, or -1 outside the image
+__device__ __forceinline__ int tap_src(const CnnDims& d, int pix, int tap) {
+  const int y = pix / d.W, x = pix - y * d.W;
+  const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+  return (yy >= 0 && yy < d.H && xx >= 0 && xx < d.W) ? yy * d.W + xx : -1;
+}
+
+// p1[r][k] = patch of image pixel r (k < K1), zero for K1 <= k < K1p
+template <typename T>
+__global__ void im2col_x_kernel(const T* __restrict__ X, int64_t xld, int64_t c0, int mcv, CnnDims d,
+                                T* __restrict__ p1) {
+  const int64_t i = gtid();
+  const int64_t R = (int64_t)mcv * d.HW;
+  if (i >= R * d.K1p) return;
+  const int64_t r = i / d.K1p;
+  const int k = (int)(i - r * d.K1p);
+  const int64_t n = r / d.HW;
+  const int pix = (int)(r - n * d.HW);
+  float v = 0.0f;
+  if (k < d.K1) {
+    const int tap = k / d.Cin, c = k - tap * d.Cin;
+    const int s = tap_src(d, pix, tap);
+    if (s >= 0) v = cvt_in<T>(X[(c0 + n) * xld + (int64_t)s * d.Cin + c]);
+  }
+  p1[i] = cvt_out<T>(v);
+}
+
+// p1t[k][r] (row stride ld): the same patches transposed, with a ones row at k = K1
+template <typename T>
+__global__ void im2col_xt_kernel(const T* __restrict__ X, int64_t xld, int64_t c0, int mcv, CnnDims d, int64_t ld,
+                                 T* __restrict__ p1t) {
+  const int64_t i = gtid();
+  const int64_t R = (int64_t)mcv * d.HW;
+  if (i >= R * (d.K1 + 1)) return;
+  const int k = (int)(i / R);
+  const int64_t r = i - (int64_t)k * R;
+  float v = 1.0f;
+  if (k < d.K1) {
+    const int64_t n = r / d.HW;
+    const int pix = (int)(r - n * d.HW);
+    const int tap = k / d.Cin, c = k - tap * d.Cin;
+    const int s = tap_src(d, pix, tap);
+    v = s >= 0 ? cvt_in<T>(X[(c0 + n) * xld + (int64_t)s * d.Cin + c]) : 0.0f;
+  }
+  p1t[(int64_t)k * ld + r] = cvt_out<T>(v);
+}
+
+// big[j][r][k] (row length K2 = 9 C1) = act1 patch, in 16-byte vectors of channels
+template <typename T>
+__global__ void im2col_a_kernel(const T* __restrict__ act1, int64_t sA, int mcv, CnnDims d, int J,
+                                T* __restrict__ big, int64_t sB) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  const int64_t i = gtid();
+  const int64_t R = (int64_t)mcv * d.HW;
+  const int nv = d.K2 / VEC;
+  if (i >= (int64_t)J * R * nv) return;
+  const int64_t jr = i / nv;
+  const int kv = (int)(i - jr * nv);
+  const int j = (int)(jr / R);
+  const int64_t r = jr - (int64_t)j * R;
+  const int64_t n = r / d.HW;
+  const int pix = (int)(r - n * d.HW);
+  const int k = kv * VEC, tap = k / d.C1, c = k - tap * d.C1;
+  const int s = tap_src(d, pix, tap);
+  u32x4 v = {0u, 0u, 0u, 0u};
+  if (s >= 0) v = *(const u32x4*)(act1 + (int64_t)j * sA + (n * d.HW + s) * d.C1 + c);
+  *(u32x4*)(big + (int64_t)j * sB + r * d.K2 + k) = v;
+}
+
+// bigT[j][k][r] (row stride ld) = act1 patch transposed, ones row at k = K2
+template <typename T>
+__global__ void im2col_at_kernel(const T* __restrict__ act1, int64_t sA, int mcv, CnnDims d, int J, int64_t ld,
+                                 T* __restrict__ bigT, int64_t sB) {
+  const int64_t i = gtid();
+  const int64_t R = (int64_t)mcv * d.HW;
+  const int64_t per = (int64_t)(d.K2 + 1) * R;
+  if (i >= (int64_t)J * per) return;
+  const int j = (int)(i / per);
+  const int64_t e = i - (int64_t)j * per;
+  const int k = (int)(e / R);
+  const int64_t r = e - (int64_t)k * R;
+  float v = 1.0f;
+  if (k < d.K2) {
+    const int64_t n = r / d.HW;
+    const int pix = (int)(r - n * d.HW);
+    const int tap = k / d.C1, c = k - tap * d.C1;
+    const int s = tap_src(d, pix, tap);
+    v = s >= 0 ? cvt_in<T>(act1[(int64_t)j * sA + (n * d.HW + s) * d.C1 + c]) : 0.0f;
+  }
+  bigT[(int64_t)j * sB + (int64_t)k * ld + r] = cvt_out<T>(v);
+}
+
+// pooled[j][n][(py Wp + px) C2 + c] = mean of the 2x2 block of act2
+template <typename T>
+__global__ void pool_kernel(const T* __restrict__ act2, int64_t sA, int mcv, CnnDims d, int J,
+                            T* __restrict__ pooled, int64_t sP) {
+  const int64_t i = gtid();
+  const int64_t per = (int64_t)mcv * d.F3;
+  if (i >= (int64_t)J * per) return;
+  const int j = (int)(i / per);
+  const int64_t e = i - (int64_t)j * per;
+  const int64_t n = e / d.F3;
+  const int f = (int)(e - n * d.F3);
+  const int p = f / d.C2, c = f - p * d.C2;
+  const int py = p / d.Wp, px = p - py * d.Wp;
+  const T* a = act2 + (int64_t)j * sA + (n * d.HW + (2 * py) * d.W + 2 * px) * d.C2 + c;
+  const float s = cvt_in<T>(a[0]) + cvt_in<T>(a[d.C2]) + cvt_in<T>(a[(int64_t)d.W * d.C2]) +
+                  cvt_in<T>(a[(int64_t)(d.W + 1) * d.C2]);
+  pooled[(int64_t)j * sP + n * d.F3 + f] = cvt_out<T>(0.25f * s);
+}
+
+// Per particle (one workgroup): log p(y_n | x_n) from logits + bias, summed in FP64 in a
+// fixed order into ll_acc[j]; TRAIN also writes d3[j][n][c] = lambda_j (1{c = y_n} - softmax)
+// (zero for ncls <= c < 16); PREDICT writes log-probabilities instead.
+template <typename T>
+__global__ __launch_bounds__(256) void cnn_ll_kernel(const CnnLLArgs a) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  const float lam = a.scale ? (float)a.scale[j] : (float)a.lambda;
+  const float* b3 = a.bias + (int64_t)j * a.ncls;
+  double acc = 0.0;
+  for (int n = threadIdx.x; n < a.mcv; n += blockDim.x) {
+    const float* z = a.logits + ((int64_t)j * a.mc + n) * a.ncls;
+    float zz[16];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      zz[c] = c < a.ncls ? z[c] + b3[c] : -INFINITY;
+      mx = fmaxf(mx, zz[c]);
+    }
+    float se = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) se += c < a.ncls ? expf(zz[c] - mx) : 0.0f;
+    const float lse = mx + logf(se);
+    if (a.mode == HEAD_PREDICT) {
+      float* lp = a.logp + ((int64_t)j * a.ld_logp + a.c0 + n) * a.ncls;
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < a.ncls) lp[c] = zz[c] - lse;
+      continue;
+    }
+    const int y = a.ylab[a.c0 + n];
+    float zy = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c == y) zy = zz[c];
+    acc += (double)(zy - lse);
+    if (a.mode == HEAD_TRAIN) {
+      T* d = (T*)a.d3 + ((int64_t)j * a.mc + n) * 16;
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        d[c] = cvt_out<T>(c < a.ncls ? lam * ((c == y ? 1.0f : 0.0f) - expf(zz[c] - lse)) : 0.0f);
+    }
+  }
+  if (a.mode == HEAD_PREDICT) return;
+  const double v = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
+    a.ll_acc[j] = a.beta ? a.ll_acc[j] + s : s;
+  }
+}
+
+// linear-layer gradient g[j][off + c (F3+1) + f] (+)= sum_n d3[j][n][c] * [pooled[j][n] | 1][f]
+template <typename T>
+__global__ __launch_bounds__(256) void cnn_dw3_kernel(const T* __restrict__ d3, const T* __restrict__ pooled,
+                                                      int64_t sP, int mc, int mcv, int F3, int ncls, float* g,
+                                                      int64_t D, int64_t off, int beta) {
+  extern __shared__ float dsh[];  // [mcv][16]
+  const int j = blockIdx.y;
+  for (int e = threadIdx.x; e < mcv * 16; e += blockDim.x) dsh[e] = cvt_in<T>(d3[((int64_t)j * mc) * 16 + e]);
+  __syncthreads();
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f > F3) return;
+  float acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = 0.0f;
+  const T* pj = pooled + (int64_t)j * sP;
+  for (int n = 0; n < mcv; ++n) {
+    const float pv = f < F3 ? cvt_in<T>(pj[(int64_t)n * F3 + f]) : 1.0f;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] += dsh[n * 16 + c] * pv;
+  }
+  float* gj = g + (int64_t)j * D + off;
+  for (int c = 0; c < ncls; ++c) {
+    float* p = gj + (int64_t)c * (F3 + 1) + f;
+    *p = beta ? *p + acc[c] : acc[c];
+  }
+}
+
+// error at the conv2 output: d2 = (unpooled dpool / 4) * 1{act2 > 0}, written as rows
+// d2[j][r][c] and transposed d2t[j][c][r] (row stride ld)
+template <typename T>
+__global__ void unpool_kernel(const T* __restrict__ dpool, int64_t sP, const T* __restrict__ act2, int64_t sA,
+                              int mcv, CnnDims d, int J, int64_t ld, T* __restrict__ d2, T* __restrict__ d2t) {
+  const int64_t i = gtid();
+  const int64_t R = (int64_t)mcv * d.HW;
+  const int64_t per = (int64_t)d.C2 * R;
+  if (i >= (int64_t)J * per) return;
+  const int j = (int)(i / per);
+  const int64_t e = i - (int64_t)j * per;
+  const int c = (int)(e / R);
+  const int64_t r = e - (int64_t)c * R;
+  const int64_t n = r / d.HW;
+  const int pix = (int)(r - n * d.HW);
+  const int y = pix / d.W, x = pix - y * d.W;
+  const int64_t ai = (int64_t)j * sA + r * d.C2 + c;
+  float v = 0.0f;
+  if (cvt_in<T>(act2[ai]) > 0.0f)
+    v = 0.25f * cvt_in<T>(dpool[(int64_t)j * sP + n * d.F3 + ((y >> 1) * d.Wp + (x >> 1)) * d.C2 + c]);
+  const T o = cvt_out<T>(v);
+  d2[ai] = o;
+  d2t[((int64_t)j * d.C2 + c) * ld + r] = o;
+}
+
+// error at the conv1 output: sum over taps of the patch errors that read pixel r, times
+// 1{act1 > 0}; written transposed as d1t[j C1 + c][r] (row stride ld)
+template <typename T>
+__global__ void col2im_kernel(const T* __restrict__ dp2, int64_t sB, const T* __restrict__ act1, int64_t sA,
+                              int mcv, CnnDims d, int J, int64_t ld, T* __restrict__ d1t) {
+  const int64_t i = gtid();
+  const int64_t R = (int64_t)mcv * d.HW;
+  const int64_t per = (int64_t)d.C1 * R;
+  if (i >= (int64_t)J * per) return;
+  const int j = (int)(i / per);
+  const int64_t e = i - (int64_t)j * per;
+  const int c = (int)(e / R);
+  const int64_t r = e - (int64_t)c * R;
+  const int64_t n = r / d.HW;
+  const int pix = (int)(r - n * d.HW);
+  const int y = pix / d.W, x = pix - y * d.W;
+  float v = 0.0f;
+  if (cvt_in<T>(act1[(int64_t)j * sA + r * d.C1 + c]) > 0.0f) {
+    const T* pj = dp2 + (int64_t)j * sB;
+    for (int tap = 0; tap < 9; ++tap) {
+      // output pixel (y - ky + 1, x - kx + 1) reads this pixel through tap (ky, kx)
+      const int yo = y - tap / 3 + 1, xo = x - tap % 3 + 1;
+      if (yo >= 0 && yo < d.H && xo >= 0 && xo < d.W)
+        v += cvt_in<T>(pj[(n * d.HW + yo * d.W + xo) * d.K2 + tap * d.C1 + c]);
+    }
+  }
+  d1t[((int64_t)j * d.C1 + c) * ld + r] = cvt_out<T>(v);
+}
+
+inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t cnn_im2col_x_run(const void* X, int64_t xld, int64_t c0, int mcv, const CnnDims& d, void* p1, int bf16,
+                            hipStream_t s) {
+  const int64_t n = (int64_t)mcv * d.HW * d.K1p;
+  if (bf16) hipLaunchKernelGGL(im2col_x_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)X, xld, c0, mcv, d, (__bf16*)p1);
+  else hipLaunchKernelGGL(im2col_x_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)X, xld, c0, mcv, d, (float*)p1);
+  return hipGetLastError();
+}
+
+hipError_t cnn_im2col_xt_run(const void* X, int64_t xld, int64_t c0, int mcv, const CnnDims& d, int64_t ld, void* p1t,
+                             int bf16, hipStream_t s) {
+  const int64_t n = (int64_t)mcv * d.HW * (d.K1 + 1);
+  if (bf16) hipLaunchKernelGGL(im2col_xt_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)X, xld, c0, mcv, d, ld, (__bf16*)p1t);
+  else hipLaunchKernelGGL(im2col_xt_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)X, xld, c0, mcv, d, ld, (float*)p1t);
+  return hipGetLastError();
+}
+
+hipError_t cnn_im2col_a_run(const void* act1, int64_t sA, int mcv, const CnnDims& d, int J, void* big, int64_t sB,
+                            int bf16, hipStream_t s) {
+  const int vec = bf16 ? 8 : 4;
+  if (d.C1 % vec) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)J * mcv * d.HW * (d.K2 / vec);
+  if (bf16) hipLaunchKernelGGL(im2col_a_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)act1, sA, mcv, d, J, (__bf16*)big, sB);
+  else hipLaunchKernelGGL(im2col_a_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)act1, sA, mcv, d, J, (float*)big, sB);
+  return hipGetLastError();
+}
+
+hipError_t cnn_im2col_at_run(const void* act1, int64_t sA, int mcv, const CnnDims& d, int J, int64_t ld, void* bigT,
+                             int64_t sB, int bf16, hipStream_t s) {
+  const int64_t n = (int64_t)J * (d.K2 + 1) * mcv * d.HW;
+  if (bf16) hipLaunchKernelGGL(im2col_at_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)act1, sA, mcv, d, J, ld, (__bf16*)bigT, sB);
+  else hipLaunchKernelGGL(im2col_at_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)act1, sA, mcv, d, J, ld, (float*)bigT, sB);
+  return hipGetLastError();
+}
+
+hipError_t cnn_pool_run(const void* act2, int64_t sA, int mcv, const CnnDims& d, int J, void* pooled, int64_t sP,
+                        int bf16, hipStream_t s) {
+  const int64_t n = (int64_t)J * mcv * d.F3;
+  if (bf16) hipLaunchKernelGGL(pool_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)act2, sA, mcv, d, J, (__bf16*)pooled, sP);
+  else hipLaunchKernelGGL(pool_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)act2, sA, mcv, d, J, (float*)pooled, sP);
+  return hipGetLastError();
+}
+
+hipError_t cnn_ll_run(const CnnLLArgs& a, int J, int bf16, hipStream_t s) {
+  if (a.ncls < 1 || a.ncls > 16) return hipErrorInvalidValue;
+  if (bf16) hipLaunchKernelGGL(cnn_ll_kernel<__bf16>, dim3(J), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(cnn_ll_kernel<float>, dim3(J), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t cnn_dw3_run(const void* d3, const void* pooled, int64_t sP, int mc, int mcv, int F3, int ncls, int J,
+                       float* g, int64_t D, int64_t off, int beta, int bf16, hipStream_t s) {
+  const size_t smem = (size_t)mcv * 16 * sizeof(float);
+  if (smem > 64 * 1024) return hipErrorInvalidValue;
+  dim3 grid(nb(F3 + 1, 256), J);
+  if (bf16) hipLaunchKernelGGL(cnn_dw3_kernel<__bf16>, grid, dim3(256), smem, s, (const __bf16*)d3, (const __bf16*)pooled, sP, mc, mcv, F3, ncls, g, D, off, beta);
+  else hipLaunchKernelGGL(cnn_dw3_kernel<float>, grid, dim3(256), smem, s, (const float*)d3, (const float*)pooled, sP, mc, mcv, F3, ncls, g, D, off, beta);
+  return hipGetLastError();
+}
+
+hipError_t cnn_unpool_run(const void* dpool, int64_t sP, const void* act2, int64_t sA, int mcv, const CnnDims& d,
+                          int J, int64_t ld, void* d2, void* d2t, int bf16, hipStream_t s) {
+  const int64_t n = (int64_t)J * d.C2 * mcv * d.HW;
+  if (bf16) hipLaunchKernelGGL(unpool_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)dpool, sP, (const __bf16*)act2, sA, mcv, d, J, ld, (__bf16*)d2, (__bf16*)d2t);
+  else hipLaunchKernelGGL(unpool_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)dpool, sP, (const float*)act2, sA, mcv, d, J, ld, (float*)d2, (float*)d2t);
+  return hipGetLastError();
+}
+
+hipError_t cnn_col2im_run(const void* dp2, int64_t sB, const void* act1, int64_t sA, int mcv, const CnnDims& d, int J,
+                          int64_t ld, void* d1t, int bf16, hipStream_t s) {
+  const int64_t n = (int64_t)J * d.C1 * mcv * d.HW;
+  if (bf16) hipLaunchKernelGGL(col2im_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)dp2, sB, (const __bf16*)act1, sA, mcv, d, J, ld, (__bf16*)d1t);
+  else hipLaunchKernelGGL(col2im_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)dp2, sB, (const float*)act1, sA, mcv, d, J, ld, (float*)d1t);
+  return hipGetLastError();
+}
+
+}  // namespace smc

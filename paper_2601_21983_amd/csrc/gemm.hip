@@ -395,9 +395,15 @@ hipError_t gemm_run(const GemmParams& p, int type, hipStream_t stream) {
   // and delta epilogues use 128x128
   const bool lean = p.epi == EPI_GRAD || (p.epi == EPI_FWD && p.act != ACT_TANH && !p.lo_off);
   const bool big = lean && (int64_t)p.M * p.N >= (int64_t)256 * 128 * 512;
+  // narrow outputs (convolution channels, small weight-gradient blocks): 256x32 tiles for
+  // N <= 32 and 32x128 tiles for M <= 32, so the matrix cores do not multiply padding
   if (type == GEMM_BF16) {
+    if (p.N <= 32) return launch_cfg<__bf16, 256, 32, 64, 32>(p, stream);
+    if (p.M <= 32) return launch_cfg<__bf16, 32, 128, 32, 32>(p, stream);
     return big ? launch_cfg<__bf16, 256, 128, 128, 64>(p, stream) : launch_cfg<__bf16, 128, 128, 64, 64>(p, stream);
   }
+  if (p.N <= 32) return launch_cfg<float, 256, 32, 64, 32>(p, stream);
+  if (p.M <= 32) return launch_cfg<float, 32, 128, 32, 32>(p, stream);
   return big ? launch_cfg<float, 256, 128, 128, 64>(p, stream) : launch_cfg<float, 128, 128, 64, 64>(p, stream);
 }
 

@@ -50,6 +50,47 @@ bool head_supported(int H, int C, int type);
 hipError_t head_run(const HeadArgs& a, int mode, int type, hipStream_t s);
 hipError_t head_set_smem_limits();
 
+// Convolutional network dimensions (conv3x3 C1 -> conv3x3 C2 -> 2x2 avgpool -> linear ncls).
+struct CnnDims {
+  int H = 0, W = 0, Cin = 0, C1 = 0, C2 = 0, ncls = 0;
+  int Hp = 0, Wp = 0, HW = 0;
+  int K1 = 0, K1p = 0;  // conv1 patch length 9 Cin and its padded row length
+  int K2 = 0;           // conv2 patch length 9 C1
+  int F3 = 0;           // linear-layer inputs Hp Wp C2
+};
+
+struct CnnLLArgs {
+  const float* logits = nullptr;  // [J x mc x ncls] (before the bias)
+  const float* bias = nullptr;    // linear-layer bias [J x ncls]
+  const int32_t* ylab = nullptr;
+  int64_t c0 = 0;
+  int mc = 0, mcv = 0, ncls = 0, mode = HEAD_TRAIN, beta = 0;
+  double lambda = 1.0;
+  const double* scale = nullptr;  // per-particle gradient scale (overrides lambda)
+  void* d3 = nullptr;             // [J x mc x 16] operand type
+  double* ll_acc = nullptr;       // [J]
+  float* logp = nullptr;          // predict: logp[(j*ld_logp + c0 + n)*ncls + c]
+  int64_t ld_logp = 0;
+};
+
+hipError_t cnn_im2col_x_run(const void* X, int64_t xld, int64_t c0, int mcv, const CnnDims& d, void* p1, int bf16,
+                            hipStream_t s);
+hipError_t cnn_im2col_xt_run(const void* X, int64_t xld, int64_t c0, int mcv, const CnnDims& d, int64_t ld, void* p1t,
+                             int bf16, hipStream_t s);
+hipError_t cnn_im2col_a_run(const void* act1, int64_t sA, int mcv, const CnnDims& d, int J, void* big, int64_t sB,
+                            int bf16, hipStream_t s);
+hipError_t cnn_im2col_at_run(const void* act1, int64_t sA, int mcv, const CnnDims& d, int J, int64_t ld, void* bigT,
+                             int64_t sB, int bf16, hipStream_t s);
+hipError_t cnn_pool_run(const void* act2, int64_t sA, int mcv, const CnnDims& d, int J, void* pooled, int64_t sP,
+                        int bf16, hipStream_t s);
+hipError_t cnn_ll_run(const CnnLLArgs& a, int J, int bf16, hipStream_t s);
+hipError_t cnn_dw3_run(const void* d3, const void* pooled, int64_t sP, int mc, int mcv, int F3, int ncls, int J,
+                       float* g, int64_t D, int64_t off, int beta, int bf16, hipStream_t s);
+hipError_t cnn_unpool_run(const void* dpool, int64_t sP, const void* act2, int64_t sA, int mcv, const CnnDims& d,
+                          int J, int64_t ld, void* d2, void* d2t, int bf16, hipStream_t s);
+hipError_t cnn_col2im_run(const void* dp2, int64_t sB, const void* act1, int64_t sA, int mcv, const CnnDims& d, int J,
+                          int64_t ld, void* d1t, int bf16, hipStream_t s);
+
 // Network shape shared by the elementwise kernels.
 struct NetShape {
   int L = 0;

@@ -148,13 +148,29 @@ struct LayerBufs {
   int ldwT = 0;
 };
 
+// convolutional network: per-chunk operand buffers (element strides per particle)
+struct CnnBufs {
+  CnnDims d;
+  void *p1 = nullptr, *p1t = nullptr;           // [RP x K1p], [(K1+1) x RP] image patches (shared)
+  void *act1 = nullptr, *big = nullptr;         // [J][RP][C1], [J][RP*(K2+1)] conv2 patches / errors
+  void *act2 = nullptr, *pooled = nullptr;      // [J][RP][C2], [J][mc][F3]
+  void *d3 = nullptr, *dpool = nullptr;         // [J][mc][16], [J][mc][F3]
+  void *d2 = nullptr, *d2t = nullptr;           // [J][RP][C2], [J][C2][RP]
+  void* d1t = nullptr;                          // [J*C1][RP]
+  float* logits = nullptr;                      // [J][mc][ncls]
+  void* wT[3] = {nullptr, nullptr, nullptr};    // transposed copies of layers 1, 2: [J][nin][ldwT]
+  int ldwT[3] = {0, 0, 0};
+  int64_t RP = 0, s_act1 = 0, s_big = 0, s_act2 = 0, s_pool = 0;
+};
+
 }  // namespace
 
 struct smc_handle {
   smc_config cfg{};
   hipStream_t stream = nullptr;
   std::vector<void*> owned;
-  int J = 0, L = 0, F = 0, C = 0, bf16 = 0, split = 0;
+  int J = 0, L = 0, F = 0, C = 0, bf16 = 0, split = 0, cnn = 0;
+  CnnBufs cb;
   int64_t D = 0;
   int64_t n_data = 0, n_pad = 0;
   int ldx = 0;  // padded feature count
@@ -253,12 +269,29 @@ void check_config(const smc_config* c) {
   if (!c) fail(SMC_ERR_ARG, "null config");
   if (c->n_particles < 1 || c->n_particles > MAX_J)
     fail(SMC_ERR_ARG, "n_particles must be in [1, " + std::to_string(MAX_J) + "]");
+  if (c->model_kind == SMC_MODEL_CNN) {
+    const int* w = c->widths;
+    if (c->n_layers != 3) fail(SMC_ERR_ARG, "the convolutional network has n_layers = 3 (widths H, W, Cin, C1, C2, n_cls)");
+    for (int q = 0; q < 6; ++q)
+      if (w[q] < 1) fail(SMC_ERR_ARG, "every CNN dimension must be >= 1");
+    if (w[0] % 2 || w[1] % 2 || (w[0] * w[1]) % 8) fail(SMC_ERR_UNSUPPORTED, "H and W must be even with H*W a multiple of 8");
+    if (w[3] % 8 || w[4] % 8) fail(SMC_ERR_UNSUPPORTED, "C1 and C2 must be multiples of 8");
+    if ((int64_t)w[0] * w[1] * w[2] > (1 << 20) || w[3] > 256 || w[4] > 256) fail(SMC_ERR_UNSUPPORTED, "CNN too large");
+    if (w[5] < 2 || w[5] > 16) fail(SMC_ERR_UNSUPPORTED, "categorical likelihood needs 2..16 classes");
+    if (c->activation != SMC_ACT_RELU) fail(SMC_ERR_UNSUPPORTED, "the convolutional network uses ReLU");
+    if (c->likelihood != SMC_LIK_CATEGORICAL) fail(SMC_ERR_UNSUPPORTED, "the convolutional network is a classifier");
+    if (c->precision == SMC_PREC_BF16X3) fail(SMC_ERR_UNSUPPORTED, "split BF16 is not built for the convolutional network");
+  } else if (c->model_kind != SMC_MODEL_MLP) {
+    fail(SMC_ERR_ARG, "model_kind");
+  }
   if (c->n_layers < 1 || c->n_layers > SMC_MAX_LAYERS) fail(SMC_ERR_ARG, "n_layers must be in [1, 8]");
-  for (int l = 0; l <= c->n_layers; ++l)
-    if (c->widths[l] < 1) fail(SMC_ERR_ARG, "every width must be >= 1");
-  if (c->model_kind != SMC_MODEL_MLP) fail(SMC_ERR_UNSUPPORTED, "model_kind: only SMC_MODEL_MLP through smc_init");
+  if (c->model_kind == SMC_MODEL_MLP)
+    for (int l = 0; l <= c->n_layers; ++l)
+      if (c->widths[l] < 1) fail(SMC_ERR_ARG, "every width must be >= 1");
   if (c->activation != SMC_ACT_TANH && c->activation != SMC_ACT_RELU) fail(SMC_ERR_ARG, "activation");
-  if (c->likelihood == SMC_LIK_CATEGORICAL) {
+  if (c->model_kind == SMC_MODEL_CNN) {
+    // checked above
+  } else if (c->likelihood == SMC_LIK_CATEGORICAL) {
     if (c->widths[c->n_layers] < 2 || c->widths[c->n_layers] > 16)
       fail(SMC_ERR_UNSUPPORTED, "categorical likelihood needs 2..16 classes");
   } else if (c->likelihood == SMC_LIK_GAUSSIAN) {
@@ -279,6 +312,7 @@ void check_config(const smc_config* c) {
   if (!(c->prior_std > 0)) fail(SMC_ERR_ARG, "prior_std must be > 0");
   if (!(c->ess_frac >= 0 && c->ess_frac <= 1)) fail(SMC_ERR_ARG, "ess_frac must be in [0, 1]");
   if (c->act_budget_bytes < 0) fail(SMC_ERR_ARG, "act_budget_bytes must be >= 0");
+  if (c->model_kind == SMC_MODEL_CNN) return;
   // hidden layers that feed another GEMM layer use 16-byte aligned per-particle rows
   if (c->n_layers >= 3)
     for (int l = 1; l < c->n_layers; ++l)
@@ -294,6 +328,28 @@ void setup_shapes(smc_t h) {
   h->L = c.n_layers;
   h->F = c.widths[0];
   h->C = c.widths[c.n_layers];
+  h->cnn = c.model_kind == SMC_MODEL_CNN;
+  int cnn_in[3] = {0, 0, 0}, cnn_out[3] = {0, 0, 0};
+  if (h->cnn) {
+    CnnDims& d = h->cb.d;
+    d.H = c.widths[0];
+    d.W = c.widths[1];
+    d.Cin = c.widths[2];
+    d.C1 = c.widths[3];
+    d.C2 = c.widths[4];
+    d.ncls = c.widths[5];
+    d.Hp = d.H / 2;
+    d.Wp = d.W / 2;
+    d.HW = d.H * d.W;
+    d.K1 = 9 * d.Cin;
+    d.K1p = (int)round_up(d.K1, 8);
+    d.K2 = 9 * d.C1;
+    d.F3 = d.Hp * d.Wp * d.C2;
+    h->F = d.HW * d.Cin;
+    h->C = d.ncls;
+    cnn_in[0] = d.K1, cnn_in[1] = d.K2, cnn_in[2] = d.F3;
+    cnn_out[0] = d.C1, cnn_out[1] = d.C2, cnn_out[2] = d.ncls;
+  }
   h->bf16 = c.precision != SMC_PREC_FP32;
   h->split = c.precision == SMC_PREC_BF16X3;
   h->esz = h->bf16 ? 2 : 4;
@@ -304,8 +360,8 @@ void setup_shapes(smc_t h) {
   n.split = h->split;
   int64_t off = 0;
   for (int l = 0; l < h->L; ++l) {
-    n.nin[l] = c.widths[l];
-    n.nout[l] = c.widths[l + 1];
+    n.nin[l] = h->cnn ? cnn_in[l] : c.widths[l];
+    n.nout[l] = h->cnn ? cnn_out[l] : c.widths[l + 1];
     n.off[l] = off;
     n.ldw[l] = (int)round_up(n.nin[l], 8);
     n.rinv[l] = 1.0f / (float)(n.nin[l] + 1);
@@ -323,6 +379,16 @@ void setup_shapes(smc_t h) {
 // samples per chunk from the activation budget
 int64_t choose_chunk(smc_t h) {
   int64_t budget = h->cfg.act_budget_bytes > 0 ? h->cfg.act_budget_bytes : ((int64_t)8 << 30);
+  if (h->cnn) {
+    // images per chunk from the bytes one image occupies across all particles
+    const CnnDims& d = h->cb.d;
+    const int64_t J = h->J, e = (int64_t)h->esz;
+    const int64_t per_image = J * d.HW * (int64_t)(2 * d.C1 + (d.K2 + 1) + 3 * d.C2) * e +
+                              J * (int64_t)(2 * d.F3 + 16) * e + J * d.ncls * 4 +
+                              (int64_t)d.HW * (d.K1p + d.K1 + 1) * e;
+    int64_t mc = std::max<int64_t>(1, budget / per_image);
+    return std::min<int64_t>(std::min<int64_t>(mc, 1024), h->n_data);
+  }
   int64_t per_sample = 0;  // bytes of activation buffers per sample
   for (int l = 0; l < h->L - 1; ++l) {
     const int64_t u = (int64_t)h->J * h->net.nout[l];
@@ -338,12 +404,41 @@ int64_t choose_chunk(smc_t h) {
   return std::min(mc, cap);
 }
 
+void alloc_cnn(smc_t h) {
+  CnnBufs& b = h->cb;
+  const CnnDims& d = b.d;
+  const int64_t J = h->J, mc = h->mc, e = (int64_t)h->esz;
+  b.RP = mc * d.HW;
+  b.s_act1 = b.RP * d.C1;
+  b.s_big = b.RP * (d.K2 + 1);
+  b.s_act2 = b.RP * d.C2;
+  b.s_pool = mc * d.F3;
+  b.p1 = dalloc<char>(h->owned, b.RP * d.K1p * e);
+  b.p1t = dalloc<char>(h->owned, b.RP * (d.K1 + 1) * e);
+  b.act1 = dalloc<char>(h->owned, J * b.s_act1 * e);
+  b.big = dalloc<char>(h->owned, J * b.s_big * e);
+  b.act2 = dalloc<char>(h->owned, J * b.s_act2 * e);
+  b.pooled = dalloc<char>(h->owned, J * b.s_pool * e);
+  b.d3 = dalloc<char>(h->owned, J * mc * 16 * e);
+  b.dpool = dalloc<char>(h->owned, J * b.s_pool * e);
+  b.d2 = dalloc<char>(h->owned, J * b.s_act2 * e);
+  b.d2t = dalloc<char>(h->owned, J * b.s_act2 * e);
+  b.d1t = dalloc<char>(h->owned, J * b.s_act1 * e);
+  b.logits = dalloc<float>(h->owned, J * mc * d.ncls);
+  for (int l = 1; l < 3; ++l) {
+    b.ldwT[l] = (int)round_up(h->net.nout[l], 8);
+    const int64_t n = J * h->net.nin[l] * b.ldwT[l] * e;
+    b.wT[l] = dalloc<char>(h->owned, n);
+    HIPCHECK(hipMemsetAsync(b.wT[l], 0, (size_t)n, h->stream));  // padded output columns stay zero
+  }
+}
+
 void alloc_all(smc_t h) {
   const int J = h->J;
   const int64_t D = h->D;
   h->n_pad = round_up(h->n_data, 256);
   h->X = dalloc<char>(h->owned, h->n_pad * h->xld * (int64_t)h->esz);
-  h->XT = dalloc<char>(h->owned, (int64_t)(h->F + 1) * h->n_pad * (int64_t)h->esz);
+  if (!h->cnn) h->XT = dalloc<char>(h->owned, (int64_t)(h->F + 1) * h->n_pad * (int64_t)h->esz);
   if (h->cfg.likelihood == SMC_LIK_GAUSSIAN) h->yreal = dalloc<float>(h->owned, h->n_pad);
   else h->ylab = dalloc<int32_t>(h->owned, h->n_pad);
   h->theta = dalloc<float>(h->owned, (int64_t)J * D);
@@ -369,6 +464,10 @@ void alloc_all(smc_t h) {
   }
   h->mc = choose_chunk(h);
   const int64_t mc = h->mc;
+  if (h->cnn) {
+    alloc_cnn(h);
+    return;
+  }
   for (int l = 0; l < h->L - 1; ++l) {
     const int64_t u = (int64_t)J * h->net.nout[l];
     LayerBufs& b = h->lb[l];
@@ -408,13 +507,15 @@ void upload_data(smc_t h, const float* x, const void* y) {
   if (h->bf16) {
     hipLaunchKernelGGL(pack_x_kernel<__bf16>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream, x,
                        h->n_data, h->F, h->ldx, h->split ? 2 : 1, h->n_pad, (__bf16*)h->X);
-    hipLaunchKernelGGL(pack_xt_kernel<__bf16>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, h->stream, x,
-                       h->n_data, h->F, h->n_pad, (__bf16*)h->XT);
+    if (h->XT)
+      hipLaunchKernelGGL(pack_xt_kernel<__bf16>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, h->stream, x,
+                         h->n_data, h->F, h->n_pad, (__bf16*)h->XT);
   } else {
     hipLaunchKernelGGL(pack_x_kernel<float>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream, x,
                        h->n_data, h->F, h->ldx, 1, h->n_pad, (float*)h->X);
-    hipLaunchKernelGGL(pack_xt_kernel<float>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, h->stream, x,
-                       h->n_data, h->F, h->n_pad, (float*)h->XT);
+    if (h->XT)
+      hipLaunchKernelGGL(pack_xt_kernel<float>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, h->stream, x,
+                         h->n_data, h->F, h->n_pad, (float*)h->XT);
   }
   HIPCHECK(hipGetLastError());
   hipLaunchKernelGGL(pack_labels_kernel, dim3((unsigned)((h->n_pad + 255) / 256)), dim3(256), 0, h->stream, y,
@@ -423,8 +524,14 @@ void upload_data(smc_t h, const float* x, const void* y) {
 }
 
 void transpose_weights(smc_t h, const float* theta) {
-  for (int l = 1; l < h->L - 1; ++l) {
-    const LayerBufs& b = h->lb[l];
+  const int l0 = 1, l1 = h->cnn ? 3 : h->L - 1;
+  for (int l = l0; l < l1; ++l) {
+    LayerBufs cbuf;
+    if (h->cnn) {
+      cbuf.wT = h->cb.wT[l];
+      cbuf.ldwT = h->cb.ldwT[l];
+    }
+    const LayerBufs& b = h->cnn ? cbuf : h->lb[l];
     const int nout = h->net.nout[l], nin = h->net.nin[l];
     dim3 grid((nin + 31) / 32, (nout + 31) / 32, h->J);
     if (h->bf16)
@@ -547,11 +654,222 @@ void set_splits(smc_t h, HeadArgs& a, int m_valid) {
   a.nsplit = (ntiles + a.tiles_per_split - 1) / a.tiles_per_split;
 }
 
+// ------------------------------------------------------------------ convolutional network
+// Forward of images [c0, c0 + mcv) of the operand Xop (xld-strided rows) up to the
+// linear layer's outputs (logits before the bias) in cb.logits.  The GEMM copies must be current.
+void cnn_forward_chunk(smc_t h, const void* Xop, int64_t c0, int mcv) {
+  CnnBufs& b = h->cb;
+  const CnnDims& d = b.d;
+  const int J = h->J, bf = h->bf16;
+  const int64_t R = (int64_t)mcv * d.HW;
+  timed(h, SMC_K_OTHER, 0.0, (double)R * d.K1p * h->esz,
+        [&]() { HIPCHECK(cnn_im2col_x_run(Xop, h->xld, c0, mcv, d, b.p1, bf, h->stream)); });
+  {
+    // conv1 of every particle as one GEMM over the J*C1 concatenated filters
+    GemmParams p;
+    p.epi = EPI_FWD;
+    p.act = ACT_RELU;
+    p.A = b.p1;
+    p.lda = d.K1p;
+    p.M = (int)R;
+    p.K = d.K1p;
+    p.B = h->net.w[0];
+    p.ldb = h->net.ldw[0];
+    p.N = J * d.C1;
+    p.bias = h->net.bias[0];
+    p.out0.ptr = b.act1;
+    p.out0.cs = d.C1;
+    p.out0.sC = b.s_act1;
+    p.out0.rstr = d.C1;
+    gemm(h, p, SMC_K_GEMM_FWD1, 2.0 * R * J * d.C1 * d.K1);
+  }
+  timed(h, SMC_K_OTHER, 0.0, (double)J * R * d.K2 * h->esz,
+        [&]() { HIPCHECK(cnn_im2col_a_run(b.act1, b.s_act1, mcv, d, J, b.big, b.s_big, bf, h->stream)); });
+  {
+    // conv2, batched over particles
+    GemmParams p;
+    p.epi = EPI_FWD;
+    p.act = ACT_RELU;
+    p.A = b.big;
+    p.lda = d.K2;
+    p.sAb = b.s_big;
+    p.M = (int)R;
+    p.K = d.K2;
+    p.B = h->net.w[1];
+    p.ldb = h->net.ldw[1];
+    p.sBb = (int64_t)d.C2 * h->net.ldw[1];
+    p.N = d.C2;
+    p.batch = J;
+    p.bias = h->net.bias[1];
+    p.sbias = d.C2;
+    p.out0.ptr = b.act2;
+    p.out0.sb = b.s_act2;
+    p.out0.rstr = d.C2;
+    gemm(h, p, SMC_K_GEMM_FWD1, 2.0 * R * J * d.C2 * d.K2);
+  }
+  timed(h, SMC_K_OTHER, 0.0, (double)J * R * d.C2 * h->esz * 1.25,
+        [&]() { HIPCHECK(cnn_pool_run(b.act2, b.s_act2, mcv, d, J, b.pooled, b.s_pool, bf, h->stream)); });
+  {
+    // linear layer, batched over particles; FP32 outputs (the bias is added with the softmax)
+    GemmParams p;
+    p.epi = EPI_GRAD;
+    p.A = b.pooled;
+    p.lda = d.F3;
+    p.sAb = b.s_pool;
+    p.M = mcv;
+    p.K = d.F3;
+    p.B = h->net.w[2];
+    p.ldb = h->net.ldw[2];
+    p.sBb = (int64_t)d.ncls * h->net.ldw[2];
+    p.N = d.ncls;
+    p.batch = J;
+    p.out0.ptr = b.logits;
+    p.out0.sb = h->mc * d.ncls;
+    p.out0.rstr = d.ncls;
+    gemm(h, p, SMC_K_GEMM_OTHER, 2.0 * mcv * J * d.ncls * d.F3);
+  }
+}
+
+CnnLLArgs cnn_ll_args(smc_t h, int mode, int mcv, int64_t c0) {
+  CnnLLArgs a;
+  a.logits = h->cb.logits;
+  a.bias = h->net.bias[2];
+  a.ylab = h->ylab;
+  a.c0 = c0;
+  a.mc = (int)h->mc;
+  a.mcv = mcv;
+  a.ncls = h->cb.d.ncls;
+  a.mode = mode;
+  a.d3 = h->cb.d3;
+  return a;
+}
+
+// the convolutional network's pass over the subset [0, m); same contract as grad_pass
+void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const double* scale, double* ll_out,
+              float* g_out) {
+  CnnBufs& b = h->cb;
+  const CnnDims& d = b.d;
+  const int J = h->J, bf = h->bf16;
+  const bool train = g_out != nullptr;
+  if (train) transpose_weights(h, theta);
+  for (int64_t c0 = 0; c0 < m; c0 += h->mc) {
+    const int mcv = (int)std::min<int64_t>(h->mc, m - c0);
+    const int64_t R = (int64_t)mcv * d.HW;
+    const int beta = c0 > 0 ? 1 : 0;
+    cnn_forward_chunk(h, h->X, c0, mcv);
+    CnnLLArgs la = cnn_ll_args(h, train ? HEAD_TRAIN : HEAD_FORWARD, mcv, c0);
+    la.lambda = lambda;
+    la.scale = scale;
+    la.ll_acc = ll_out;
+    la.beta = beta;
+    timed(h, SMC_K_HEAD, 0.0, 0.0, [&]() { HIPCHECK(cnn_ll_run(la, J, bf, h->stream)); });
+    if (!train) continue;
+    timed(h, SMC_K_OTHER, 2.0 * J * (double)mcv * d.ncls * (d.F3 + 1), 0.0, [&]() {
+      HIPCHECK(cnn_dw3_run(b.d3, b.pooled, b.s_pool, (int)h->mc, mcv, d.F3, d.ncls, J, g_out, h->D, h->net.off[2],
+                           beta, bf, h->stream));
+    });
+    {
+      // error at the pooled features: d3 [n x 16] . W3^T [F3 x 16]^T
+      GemmParams p;
+      p.epi = EPI_FWD;
+      p.act = -1;
+      p.A = b.d3;
+      p.lda = 16;
+      p.sAb = h->mc * 16;
+      p.M = mcv;
+      p.K = 16;
+      p.B = b.wT[2];
+      p.ldb = b.ldwT[2];
+      p.sBb = (int64_t)d.F3 * b.ldwT[2];
+      p.N = d.F3;
+      p.batch = J;
+      p.out0.ptr = b.dpool;
+      p.out0.sb = b.s_pool;
+      p.out0.rstr = d.F3;
+      gemm(h, p, SMC_K_GEMM_OTHER, 2.0 * mcv * J * d.ncls * d.F3);
+    }
+    timed(h, SMC_K_OTHER, 0.0, (double)J * R * d.C2 * h->esz * 3.25, [&]() {
+      HIPCHECK(cnn_unpool_run(b.dpool, b.s_pool, b.act2, b.s_act2, mcv, d, J, b.RP, b.d2, b.d2t, bf, h->stream));
+    });
+    timed(h, SMC_K_OTHER, 0.0, (double)J * R * (d.K2 + 1) * h->esz, [&]() {
+      HIPCHECK(cnn_im2col_at_run(b.act1, b.s_act1, mcv, d, J, b.RP, b.big, b.s_big, bf, h->stream));
+    });
+    {
+      // conv2 weight gradient [W2 | b2] = d2^T [patches | 1], reduced over the chunk's pixels
+      GemmParams p;
+      p.epi = EPI_GRAD;
+      p.beta = beta;
+      p.A = b.d2t;
+      p.lda = b.RP;
+      p.sAb = (int64_t)d.C2 * b.RP;
+      p.M = d.C2;
+      p.K = (int)R;
+      p.B = b.big;
+      p.ldb = b.RP;
+      p.sBb = b.s_big;
+      p.N = d.K2 + 1;
+      p.batch = J;
+      p.out0.ptr = g_out + h->net.off[1];
+      p.out0.sb = h->D;
+      p.out0.rstr = d.K2 + 1;
+      gemm(h, p, SMC_K_GEMM_DW1, 2.0 * R * J * d.C2 * (d.K2 + 1));
+    }
+    {
+      // patch errors d2 [R x C2] . W2 [C2 x K2] (B operand: W2^T rows)
+      GemmParams p;
+      p.epi = EPI_FWD;
+      p.act = -1;
+      p.A = b.d2;
+      p.lda = d.C2;
+      p.sAb = b.s_act2;
+      p.M = (int)R;
+      p.K = d.C2;
+      p.B = b.wT[1];
+      p.ldb = b.ldwT[1];
+      p.sBb = (int64_t)d.K2 * b.ldwT[1];
+      p.N = d.K2;
+      p.batch = J;
+      p.out0.ptr = b.big;
+      p.out0.sb = b.s_big;
+      p.out0.rstr = d.K2;
+      gemm(h, p, SMC_K_GEMM_OTHER, 2.0 * R * J * d.C2 * d.K2);
+    }
+    timed(h, SMC_K_OTHER, 0.0, (double)J * R * (d.K2 + 2 * d.C1) * h->esz, [&]() {
+      HIPCHECK(cnn_col2im_run(b.big, b.s_big, b.act1, b.s_act1, mcv, d, J, b.RP, b.d1t, bf, h->stream));
+    });
+    timed(h, SMC_K_OTHER, 0.0, (double)R * (d.K1 + 1) * h->esz,
+          [&]() { HIPCHECK(cnn_im2col_xt_run(h->X, h->xld, c0, mcv, d, b.RP, b.p1t, bf, h->stream)); });
+    {
+      // conv1 weight gradient of every particle: d1^T [J*C1 x R] . [patches | 1]
+      GemmParams p;
+      p.epi = EPI_GRAD;
+      p.beta = beta;
+      p.A = b.d1t;
+      p.lda = b.RP;
+      p.M = J * d.C1;
+      p.K = (int)R;
+      p.B = b.p1t;
+      p.ldb = b.RP;
+      p.N = d.K1 + 1;
+      p.out0.ptr = g_out;
+      p.out0.rs = d.C1;
+      p.out0.sR = h->D;
+      p.out0.rstr = d.K1 + 1;
+      gemm(h, p, SMC_K_GEMM_DW1, 2.0 * R * J * d.C1 * (d.K1 + 1));
+    }
+  }
+  if (train) h->grad_evals += (int64_t)J * m;
+}
+
 // One pass over the subset [0, m): log-likelihoods ll_out[j] (FP64) and, when
 // g_out is given, g_out[j] = scale_j * d LL_j / d theta_j (the lambda-scaled
 // likelihood gradient).  The GEMM copies of `theta` must be current.
 void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const double* scale, double* ll_out,
                float* g_out) {
+  if (h->cnn) {
+    cnn_pass(h, theta, m, lambda, scale, ll_out, g_out);
+    return;
+  }
   const int J = h->J, L = h->L;
   const bool train = g_out != nullptr;
   if (train && L >= 3) transpose_weights(h, theta);
@@ -1053,6 +1371,14 @@ smc_status smc_posterior_predict(smc_t h, const float* x_dev, const int32_t* y_d
     HIPCHECK(hipGetLastError());
     for (int64_t c0 = 0; c0 < n; c0 += h->mc) {
       const int mcv = (int)std::min<int64_t>(h->mc, n - c0);
+      if (h->cnn) {
+        cnn_forward_chunk(h, h->tx, c0, mcv);
+        CnnLLArgs la = cnn_ll_args(h, HEAD_PREDICT, mcv, c0);
+        la.logp = h->logp;
+        la.ld_logp = n;
+        HIPCHECK(cnn_ll_run(la, h->J, h->bf16, h->stream));
+        continue;
+      }
       const int rows = (int)round_up(mcv, 64);
       forward_hidden(h, h->tx, c0, rows, mcv);
       HeadArgs a = head_args(h, h->theta);

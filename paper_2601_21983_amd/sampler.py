@@ -31,7 +31,13 @@ def _dev(t: torch.Tensor, dtype, name: str) -> int:
     return t.data_ptr()
 
 
-def n_params(widths: Sequence[int]) -> int:
+def n_params(widths: Sequence[int], model: str = "mlp") -> int:
+    """Parameters per particle: dense layers [n_0, ..., n_L], or for the convolutional network
+    widths = [H, W, Cin, C1, C2, n_cls] (blocks [C1 x (9 Cin + 1)], [C2 x (9 C1 + 1)],
+    [n_cls x ((H/2)(W/2) C2 + 1)])."""
+    if model == "cnn":
+        H, W, Cin, C1, C2, n = widths
+        return C1 * (9 * Cin + 1) + C2 * (9 * C1 + 1) + n * ((H // 2) * (W // 2) * C2 + 1)
     return sum(widths[i + 1] * (widths[i] + 1) for i in range(len(widths) - 1))
 
 
@@ -51,15 +57,21 @@ class SMCConfig:
     seed: int = 0
     act_budget_bytes: int = 0
     n_iterations: int = 0
+    model: str = "mlp"  # "mlp" or "cnn" (widths = [H, W, Cin, C1, C2, n_cls])
 
     def to_c(self) -> L.smc_config:
         c = L.smc_config()
         c.n_particles = self.n_particles
-        c.n_layers = len(self.widths) - 1
+        if self.model == "cnn":
+            if len(self.widths) != 6:
+                raise ValueError("the convolutional network takes widths [H, W, Cin, C1, C2, n_cls]")
+            c.n_layers = 3
+        else:
+            c.n_layers = len(self.widths) - 1
         for i, w in enumerate(self.widths):
             c.widths[i] = int(w)
         c.activation = _ACT[self.activation]
-        c.model_kind = L.SMC_MODEL_MLP
+        c.model_kind = L.SMC_MODEL_CNN if self.model == "cnn" else L.SMC_MODEL_MLP
         c.likelihood = _LIK[self.likelihood]
         c.precision = _PREC[self.precision]
         c.proposal = _PROP[self.proposal]
@@ -81,7 +93,7 @@ class SMCSampler:
                  theta0: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None):
         self.cfg = cfg
         self.J = cfg.n_particles
-        self.D = n_params(cfg.widths)
+        self.D = n_params(cfg.widths, cfg.model)
         self.C = cfg.widths[-1]
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         xp = _dev(X, torch.float32, "X")
@@ -91,7 +103,8 @@ class SMCSampler:
             tp = _dev(theta0, torch.float32, "theta0")
             if tuple(theta0.shape) != (self.J, self.D):
                 raise ValueError("theta0 must be [J x D]")
-        if X.shape[1] != cfg.widths[0]:
+        F = cfg.widths[0] * cfg.widths[1] * cfg.widths[2] if cfg.model == "cnn" else cfg.widths[0]
+        if X.dim() != 2 or X.shape[1] != F:
             raise ValueError("X has the wrong number of features")
         self.N = X.shape[0]
         self._h = None
@@ -184,7 +197,7 @@ class SMCSampler:
     # ---------------------------------------------------------------- learned proposal
     @property
     def n_groups(self) -> int:
-        return 2 * (len(self.cfg.widths) - 1)
+        return 2 * (3 if self.cfg.model == "cnn" else len(self.cfg.widths) - 1)
 
     def set_proposal_net(self, params: torch.Tensor, h0: float) -> None:
         L.smc_set_proposal_net(self.handle, _dev(params, torch.float32, "params"), params.numel(), float(h0))
