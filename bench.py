@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy runs")
     ap.add_argument("--legs", default="bf16x3-learned,fp32,bf16x3,bf16",
                     help="comma list of precision[-learned]; the first is the headline")
+    ap.add_argument("--no-cnn", action="store_true", help="skip the convolutional-network workload")
+    ap.add_argument("--cnn-steps", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -227,6 +229,61 @@ def roofline(prof, prec, steps, with_traffic):
             "frac": round(ach / ALU_PEAK, 4), "traffic": traffic, "avg_launch_us": round(1e3 * ms / n, 3)}
 
 
+CNN_DIMS = [32, 32, 3, 16, 32, 10]
+CNN_J, CNN_N, CNN_NTEST, CNN_KAPPA, CNN_TOL = 128, 50000, 2000, 1000, 1e-2
+CNN_PRIOR = 0.05  # prior sd of every CNN weight: with sd 1 the 8192-input linear layer gives logits ~1e4
+
+
+def run_cnn(P, steps, seed):
+    """CIFAR-shaped workload: conv3x3(16) -> conv3x3(32) -> avgpool -> linear(10), J = 128, BF16,
+    subset grown by kappa = 1000 when the posterior mean's relative change is below 1e-2."""
+    import torch
+    import smc_inputs
+    from paper_2601_21983_amd.schedules import PosteriorMeanSchedule
+    t = time.perf_counter()
+    X, y = smc_inputs.textures32(CNN_N, seed=0)
+    Xt, yt = smc_inputs.textures32(CNN_NTEST, seed=1)
+    perm = smc_inputs.annealing_permutation(CNN_N, seed=2)
+    X, y = X.reshape(CNN_N, -1)[perm], y[perm].astype(np.int32)
+    log(f"cnn data generated in {time.perf_counter() - t:.1f} s")
+    cuda = torch.device("cuda")
+    Xd, yd = torch.from_numpy(np.ascontiguousarray(X)).to(cuda), torch.from_numpy(y).to(cuda)
+    Xtd = torch.from_numpy(np.ascontiguousarray(Xt.reshape(CNN_NTEST, -1))).to(cuda)
+    ytd = torch.from_numpy(yt.astype(np.int32)).to(cuda)
+    cfg = P.SMCConfig(widths=CNN_DIMS, n_particles=CNN_J, model="cnn", precision="bf16", step_size=STEP,
+                      prior_std=CNN_PRIOR, seed=seed)
+    s = P.SMCSampler(cfg, Xd, yd, m0=CNN_KAPPA, lambda0=CNN_N / CNN_KAPPA)
+    s.resample()
+    sched = PosteriorMeanSchedule(CNN_KAPPA, CNN_KAPPA, CNN_TOL, CNN_N)
+    sched.start(s)
+    s.profile(True)
+    s.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m, evals, sizes, ess = CNN_KAPPA, 0, [], []
+    for k in range(1, steps + 1):
+        info = s.step(m, CNN_N / m)
+        evals += info["grad_evals"]
+        ess.append(info["ess"])
+        s.resample()
+        sizes.append(m)
+        m = sched.next(s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = s.profile_read()
+    r = s.predict(Xtd, ytd)
+    s.close()
+    return {"value": round(evals / dt, 1), "unit": "grad-evals/s", "ms_per_step": round(1e3 * dt / steps, 3),
+            "steps": steps, "subset_sizes": sizes, "mean_ess": round(float(np.mean(ess)), 2),
+            "test_accuracy": round(r["accuracy"], 4), "test_mean_log_pred": round(r["mean_log_pred"], 5),
+            "config": {"workload": "CIFAR-shaped synthetic textures 50000/2000 (32x32x3), CNN conv3x3(16)-"
+                                   "conv3x3(32)-avgpool2-FC10 ReLU, J=128, BF16 operands, prior N(0, 0.05^2), Langevin h=0.002, "
+                                   "subset grown by 1000 when the posterior mean changes by < 1e-2",
+                       "particles": CNN_J, "precision": "bf16"},
+            "roofline": roofline(prof, "bf16", steps, False), "kernels": kernel_table(prof, "bf16"),
+            "host_seconds_incl_schedule": round(dt, 3)}
+
+
 def cpu_baseline(X, y, sizes, budget_s=12.0, J_s=8):
     """The FP64 oracle on the host cores: iterations k = 1, 2, ... of the same schedule
     with J_s particles until about budget_s seconds of work; rate in grad evals/s."""
@@ -317,6 +374,11 @@ def main():
             tta[l] = e
         log("time-to-accuracy: " + json.dumps(tta))
 
+    cnn = None
+    if not args.no_cnn:
+        cnn = run_cnn(P, max(1, args.cnn_steps), args.seed)
+        log(f"cnn: {json.dumps(cnn)}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(X, y, sizes)
@@ -345,6 +407,7 @@ def main():
         "cpu_baseline": cpu,
         "time_to_accuracy": tta,
         "proposal_network": training,
+        "cnn_config2": cnn,
         "kernels": {l: kernel_table(res[l]["prof"], leg_parts(l)[0]) for l in legs},
     }
     for l in legs[1:]:
