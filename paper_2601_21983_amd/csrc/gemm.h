@@ -41,9 +41,9 @@ struct GemmParams {
   int64_t sbias = 0;
   int act = -1;                 // -1: identity
   int beta = 0;
-  // EPI_FWD with BF16 operands: when nonzero, out0 + lo_off (elements) receives the
-  // split-BF16 residual bf16(v - bf16(v)) of every value stored at out0
-  int64_t lo_off = 0;
+  // EPI_FWD with BF16 operands: store FP32 outputs (for a consumer that splits them into
+  // BF16 hi/lo pairs) instead of rounding them to BF16
+  int out_f32 = 0;
 };
 
 hipError_t gemm_run(const GemmParams& p, int type, hipStream_t stream);

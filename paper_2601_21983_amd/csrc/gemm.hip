@@ -80,9 +80,16 @@ __device__ __forceinline__ float act_deriv(float a) {
 }
 
 // ACT: activation of the FWD epilogue / derivative of the DELTA epilogue (-1: none)
-// LO:  the FWD epilogue also stores the split-BF16 residual plane at out0 + lo_off
-template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT, bool LO>
-__global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
+// F32O: the FWD epilogue stores FP32 values (BF16 operands only)
+// The BF16 256x128 tile keeps one LDS stage so that two workgroups share a CU (one's
+// prologue and epilogue overlap the other's matrix-core loop; measured 1.3-1.6x on the
+// layer-1 GEMMs).  Other tiles, and FP32 (whose weight-gradient GEMM lost 15% that way),
+// double-buffer with one workgroup per CU.
+constexpr int tile_nbuf(int bm, int bn, int esz) { return (bm == 256 && bn == 128 && esz == 2) ? 1 : 2; }
+constexpr int tile_minb(int bm, int bn, int esz) { return tile_nbuf(bm, bn, esz) == 1 ? 2 : 1; }
+
+template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT, bool F32O>
+__global__ __launch_bounds__(THREADS, tile_minb(BM, BN, (int)sizeof(T))) void gemm_nt(const GemmParams p) {
   constexpr int VEC = Mf<T>::VEC;
   constexpr int BKE = ROW_BYTES / (int)sizeof(T);
   constexpr int NWN = BN / WN;
@@ -93,7 +100,8 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
   static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
   static_assert(AV >= 1 && BV >= 1, "tile too small");
 
-  __shared__ __attribute__((aligned(16))) char smem[2 * STAGE];
+  constexpr int NBUF = tile_nbuf(BM, BN, (int)sizeof(T));
+  __shared__ __attribute__((aligned(16))) char smem[NBUF * STAGE];
 
   const int b = blockIdx.y;
   // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
@@ -182,7 +190,7 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
   const int frow = lane & 31;
   const int fhalf = (lane >> 5) * 16;
   for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
+    const int buf = NBUF == 2 ? (kt & 1) : 0;
     if (kt + 1 < nk) gload(kt + 1);
     const char* base = smem + buf * STAGE;
 #pragma unroll
@@ -199,7 +207,12 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = Mf<T>::mma(fa[i], fb[j], acc[i][j]);
     }
-    if (kt + 1 < nk) sstore(buf ^ 1);
+    if (NBUF == 2) {
+      if (kt + 1 < nk) sstore(buf ^ 1);
+    } else if (kt + 1 < nk) {
+      __syncthreads();  // every wave is done reading the stage
+      sstore(0);
+    }
     __syncthreads();
   }
 
@@ -208,22 +221,19 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
   // segment goes through LDS, so each output row piece is written by consecutive
   // lanes with the widest aligned vector stores (16, 8 or 4/2 bytes).
   if (p.out0.cstr == 1 && (EPI == EPI_GRAD || (EPI == EPI_FWD && !p.out1.ptr))) {
-    typedef typename std::conditional<EPI == EPI_GRAD, float, T>::type O;
+    typedef typename std::conditional<EPI == EPI_GRAD || (EPI == EPI_FWD && F32O), float, T>::type O;
     constexpr int OS = (int)sizeof(O);
     constexpr int SROW = BN + 16 / OS;  // padded LDS row, in elements
     O* slab = (O*)smem;                 // [NWM*32][SROW]
     constexpr int NWM = BM / WM;
     constexpr int SLAB_BYTES = NWM * 32 * SROW * OS;
-    // the split-BF16 residual goes through a second slab right after the first
-    static_assert(2 * SLAB_BYTES + (NWM * 32 + BN) * 8 <= 2 * STAGE, "slab does not fit in LDS");
-    O* slab_lo = (O*)(smem + SLAB_BYTES);
-    int64_t* rowaddr = (int64_t*)(smem + 2 * SLAB_BYTES);
+    static_assert(SLAB_BYTES + (NWM * 32 + BN) * 8 <= NBUF * STAGE, "slab does not fit in LDS");
+    int64_t* rowaddr = (int64_t*)(smem + SLAB_BYTES);
     int64_t* colpart = rowaddr + NWM * 32;
     const OutDesc& d = p.out0;
-    constexpr bool lo = LO && EPI == EPI_FWD && sizeof(O) == 2;
     auto aligned = [&](int ve) {
       return ((uintptr_t)d.ptr % (uintptr_t)(ve * OS)) == 0 && d.rstr % ve == 0 && d.sR % ve == 0 &&
-             d.sb % ve == 0 && d.sC % ve == 0 && d.cs % ve == 0 && (!lo || p.lo_off % ve == 0);
+             d.sb % ve == 0 && d.sC % ve == 0 && d.cs % ve == 0;
     };
     const int vw = aligned(16 / OS) ? 16 / OS : (aligned(8 / OS) ? 8 / OS : 1);
     for (int lc = tid; lc < BN; lc += THREADS) {
@@ -244,9 +254,7 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
           const int lr = wm * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
           float v = acc[i][j][q];
           if (EPI == EPI_FWD) v = act_apply<ACT>(v + bias);
-          const O vo = cvt_out<O>(v);
-          slab[lr * SROW + lc] = vo;
-          if (lo) slab_lo[lr * SROW + lc] = cvt_out<O>(v - cvt_in<O>(vo));
+          slab[lr * SROW + lc] = cvt_out<O>(v);
         }
       }
       if (tid < NWM * 32) {
@@ -263,22 +271,6 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
         if (ra < 0 || col >= N) continue;
         O* dst = (O*)d.ptr + ra + colpart[lc];
         const O* src = slab + lr * SROW + lc;
-        if (lo) {
-          // forward epilogue with BF16 output: plain copies of both planes
-          O* dlo = dst + p.lo_off;
-          const O* slo = slab_lo + lr * SROW + lc;
-          if (col + vw <= N && vw * OS == 16) {
-            *(u32x4*)dst = *(const u32x4*)src;
-            *(u32x4*)dlo = *(const u32x4*)slo;
-          } else {
-            const int n = min(vw, N - col);
-            for (int q = 0; q < n; ++q) {
-              dst[q] = src[q];
-              dlo[q] = slo[q];
-            }
-          }
-          continue;
-        }
         if (col + vw <= N && vw * OS == 16) {
           u32x4 v = *(const u32x4*)src;
           if (EPI == EPI_GRAD && p.beta) {
@@ -335,8 +327,11 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
         } else {
           if (EPI == EPI_FWD) {
             v = act_apply<ACT>(v + bias);
-            if (LO && sizeof(T) == 2)
-              *((T*)p.out0.ptr + p.lo_off + split_at(p.out0, s0, dr)) = cvt_out<T>(v - cvt_in<T>(cvt_out<T>(v)));
+            if (F32O) {
+              *((float*)p.out0.ptr + split_at(p.out0, s0, dr)) = v;
+              if (p.out1.ptr) *((float*)p.out1.ptr + split_at(p.out1, s1, dr)) = v;
+              continue;
+            }
           } else {
             const float a = cvt_in<T>(*((const T*)p.aux.ptr + split_at(p.aux, sa, dr)));
             v *= act_deriv<ACT>(a);
@@ -352,12 +347,12 @@ __global__ __launch_bounds__(THREADS) void gemm_nt(const GemmParams p) {
 template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT>
 hipError_t launch_one(const GemmParams& p, dim3 grid, hipStream_t s) {
   if constexpr (EPI == EPI_FWD && std::is_same<T, __bf16>::value) {
-    if (p.lo_off) {
+    if (p.out_f32) {
       hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI, ACT, true>), grid, dim3(THREADS), 0, s, p);
       return hipGetLastError();
     }
-  } else {
-    if (p.lo_off) return hipErrorInvalidValue;
+  } else if (EPI != EPI_FWD) {
+    if (p.out_f32) return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI, ACT, false>), grid, dim3(THREADS), 0, s, p);
   return hipGetLastError();
@@ -391,9 +386,8 @@ hipError_t gemm_run(const GemmParams& p, int type, hipStream_t stream) {
   if (p.K % vec || p.lda % vec || p.ldb % vec) return hipErrorInvalidValue;
   if (((uintptr_t)p.A | (uintptr_t)p.B) & 15) return hipErrorInvalidValue;
   // the 256x128 tile keeps its 128 accumulators in registers only with the lean
-  // epilogues (identity/ReLU forward without residual plane, gradient); tanh, residual
-  // and delta epilogues use 128x128
-  const bool lean = p.epi == EPI_GRAD || (p.epi == EPI_FWD && p.act != ACT_TANH && !p.lo_off);
+  // epilogues (identity/ReLU forward, gradient); tanh and delta epilogues use 128x128
+  const bool lean = p.epi == EPI_GRAD || (p.epi == EPI_FWD && p.act != ACT_TANH);
   const bool big = lean && (int64_t)p.M * p.N >= (int64_t)256 * 128 * 512;
   // narrow outputs (convolution channels, small weight-gradient blocks): 256x32 tiles for
   // N <= 32 and 32x128 tiles for M <= 32, so the matrix cores do not multiply padding

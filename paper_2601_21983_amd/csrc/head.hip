@@ -23,7 +23,9 @@
 // Split-BF16 form (SPL): every operand value v that differs between particles or
 // states is carried as hi = bf16(v) and lo = bf16(v - hi); the products use
 // hi*hi + hi*lo + lo*hi (lo*lo is below FP32 resolution), so logits and errors
-// carry about 16 mantissa bits although every MFMA input is BF16.  Data X stays
+// carry about 16 mantissa bits although every MFMA input is BF16.  The hidden
+// activations arrive in FP32 and are split while they are staged in LDS; the
+// weights are split when loaded.  Data X (a network without hidden layer) stays
 // single BF16: its rounding is the same at every state and cancels in the
 // log-likelihood differences that enter the importance weights.
 // MFMA forms: bf16 v_mfma_f32_16x16x16_bf16 (a lane supplies 4 consecutive K
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
   T* WcLo = Wc + 16 * Lo.AS;     // lo planes (SPL only)
   T* WtLo = Wt + Lo.Hp * Lo.WT;
   T* AsLo = As + HT * Lo.AS;
-  const bool alo = SPL && a.Alo != nullptr;  // activations carry a lo plane
+  const bool alo = SPL && a.a_f32;  // activations arrive in FP32 and get a lo plane
   T* Dt = (T*)(hsm + Lo.offDt);
   T* St = (T*)(hsm + Lo.offSt);
   double* red = (double*)(hsm + Lo.offRed);
@@ -182,19 +184,59 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
 
   const float lam = a.scale ? (float)a.scale[j] : (float)a.lambda;
   const T* Aj = (const T*)a.A + (int64_t)j * a.sAj;
-  const T* Alj = alo ? (const T*)a.Alo + (int64_t)j * a.sAj : nullptr;
+  const float* Afj = (const float*)a.A + (int64_t)j * a.sAj;  // FP32 activations (alo)
   const int ntiles = (a.m_valid + HT - 1) / HT;
   const int t0 = split * a.tiles_per_split;
   const int t1 = min(ntiles, t0 + a.tiles_per_split);
 
   // activation tile loader: 8-byte chunks when rows allow it, else single elements
   constexpr int CE = 8 / (int)sizeof(T);  // elements per chunk
-  const bool vec = (H % CE) == 0 && (a.sAm % CE) == 0 && (a.sAj % CE) == 0 && ((uintptr_t)a.A % 8) == 0 &&
-                   (!alo || ((uintptr_t)a.Alo % 8) == 0);
-  const int cpr = vec ? H / CE : H;       // chunks per row
+  const int ce = alo ? 4 : CE;             // FP32 activations: four per (16-byte) chunk
+  const bool vec = (H % ce) == 0 && (a.sAm % ce) == 0 && (a.sAj % ce) == 0 && ((uintptr_t)a.A % (alo ? 16 : 8)) == 0;
+  const int cpr = vec ? H / ce : H;       // chunks per row
   const int nch = HT * cpr;
   const float rcpr = 1.0f / (float)cpr;
-  u32x2 pre[PF], prelo[SPL ? PF : 1];
+  // chunk (s, c) of the activation tile.  BF16: 8 raw bytes (CE values).  FP32 (split): four
+  // values read as one 16-byte vector and kept as {hi 0-1, hi 2-3, lo 0-1, lo 2-3}, pairs of
+  // packed BF16 values.
+  typedef typename std::conditional<SPL, u32x4, u32x2>::type PreT;
+  PreT pre[PF];
+  auto pack2 = [](__bf16 x, __bf16 y) -> uint32_t {
+    return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+  };
+  auto ld_chunk = [&](int tile, int s, int c) -> PreT {
+    PreT v{};
+    if constexpr (SPL) {
+      if (alo) {
+        const f32x4 f = *(const f32x4*)(Afj + (int64_t)(tile * HT + s) * a.sAm + c * 4);
+        __bf16 hi[4], lo[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          hi[t] = to_bf16(f[t]);
+          lo[t] = to_bf16(f[t] - from_bf16(hi[t]));
+        }
+        v[0] = pack2(hi[0], hi[1]);
+        v[1] = pack2(hi[2], hi[3]);
+        v[2] = pack2(lo[0], lo[1]);
+        v[3] = pack2(lo[2], lo[3]);
+        return v;
+      }
+    }
+    const u32x2 r = *(const u32x2*)(Aj + (int64_t)(tile * HT + s) * a.sAm + c * CE);
+    v[0] = r[0];
+    v[1] = r[1];
+    return v;
+  };
+  auto put_chunk = [&](int s, int c, PreT v) {
+    if constexpr (SPL) {
+      if (alo) {
+        *(u32x2*)(As + s * AS + 4 * c) = u32x2{v[0], v[1]};
+        *(u32x2*)(AsLo + s * AS + 4 * c) = u32x2{v[2], v[3]};
+        return;
+      }
+    }
+    *(u32x2*)(As + s * AS + c * CE) = u32x2{v[0], v[1]};
+  };
   auto chunk_rc = [&](int e, int& s, int& c) {
     s = (int)(((float)e + 0.5f) * rcpr);
     c = e - s * cpr;
@@ -208,8 +250,7 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
       if (e < nch) {
         int s, c;
         chunk_rc(e, s, c);
-        pre[q] = *(const u32x2*)(Aj + (int64_t)(tile * HT + s) * a.sAm + c * CE);
-        if (alo) prelo[SPL ? q : 0] = *(const u32x2*)(Alj + (int64_t)(tile * HT + s) * a.sAm + c * CE);
+        pre[q] = ld_chunk(tile, s, c);
       }
     }
   };
@@ -221,23 +262,26 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
         if (e < nch) {
           int s, c;
           chunk_rc(e, s, c);
-          *(u32x2*)(As + s * AS + c * CE) = pre[q];
-          if (alo) *(u32x2*)(AsLo + s * AS + c * CE) = prelo[SPL ? q : 0];
+          put_chunk(s, c, pre[q]);
         }
       }
       for (int e = tid + PF * HTHREADS; e < nch; e += HTHREADS) {
         int s, c;
         chunk_rc(e, s, c);
-        *(u32x2*)(As + s * AS + c * CE) = *(const u32x2*)(Aj + (int64_t)(tile * HT + s) * a.sAm + c * CE);
-        if (alo)
-          *(u32x2*)(AsLo + s * AS + c * CE) = *(const u32x2*)(Alj + (int64_t)(tile * HT + s) * a.sAm + c * CE);
+        put_chunk(s, c, ld_chunk(tile, s, c));
       }
     } else {
       for (int e = tid; e < nch; e += HTHREADS) {
         int s, c;
         chunk_rc(e, s, c);
-        As[s * AS + c] = Aj[(int64_t)(tile * HT + s) * a.sAm + c];
-        if (alo) AsLo[s * AS + c] = Alj[(int64_t)(tile * HT + s) * a.sAm + c];
+        if (SPL && alo) {
+          const float f = Afj[(int64_t)(tile * HT + s) * a.sAm + c];
+          const T hv = cvt_out<T>(f);
+          As[s * AS + c] = hv;
+          AsLo[s * AS + c] = cvt_out<T>(f - cvt_in<T>(hv));
+        } else {
+          As[s * AS + c] = Aj[(int64_t)(tile * HT + s) * a.sAm + c];
+        }
       }
     }
   };
@@ -436,7 +480,7 @@ hipError_t head_run(const HeadArgs& a, int mode, int type, hipStream_t s) {
   const int ntiles = (a.m_valid + HT - 1) / HT;
   if (ntiles <= 0) return hipSuccess;
   if (!head_supported(a.H, a.C, type)) return hipErrorInvalidValue;
-  if (a.Alo && type != HEAD_BF16_SPLIT) return hipErrorInvalidValue;
+  if (a.a_f32 && type != HEAD_BF16_SPLIT) return hipErrorInvalidValue;
   dim3 grid(a.nsplit, a.J);
 #define HEAD_LAUNCH(T, MODE, SPL)                                                                        \
   do {                                                                                                   \

@@ -16,7 +16,7 @@ enum { TAG_MOMENTUM = 1, TAG_RESAMPLE_U = 2, TAG_PRIOR = 3 };
 
 struct HeadArgs {
   const void* A = nullptr;          // activation (j, m, h) at A + j*sAj + m*sAm + h
-  const void* Alo = nullptr;        // split-BF16 residual plane of A (same strides), or null
+  int a_f32 = 0;                    // split BF16: A holds FP32 values, split into hi/lo when staged
   int64_t sAj = 0, sAm = 0;
   const float* theta = nullptr;     // master parameters [J x D]
   int64_t D = 0, offL = 0;          // output-layer block offset

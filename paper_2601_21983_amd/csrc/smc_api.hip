@@ -15,7 +15,7 @@
 //                          is added where it is used) and momenta
 //   w_l  [J*n_l x ldw_l]   GEMM copy of each layer's weights (operand type), b_l [J*n_l]
 //   act_l [J x mc x n_l]   hidden activations of one chunk of samples, particle-major
-//                          (split BF16: followed by the residual plane of the same shape)
+//                          (split BF16: FP32 values, split into hi/lo by the output-layer kernel)
 //                          (one contiguous [samples x units] block per particle); layer 1
 //                          is still a single dense GEMM over the J*n_1 concatenated units,
 //                          whose epilogue scatters each particle's columns to its block
@@ -571,7 +571,7 @@ void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows, int m_valid)
       p.ldb = h->net.ldw[0] * (h->split ? 2 : 1);
       if (h->split) {
         p.K = 2 * h->net.ldw[0];  // [x | x] . [w_hi | w_lo]
-        p.lo_off = h->mc * U;     // residual plane of act_0
+        p.out_f32 = 1;            // FP32 activations for the output layer's hi/lo split
       }
       p.N = (int)U;
       p.batch = 1;
@@ -636,7 +636,7 @@ HeadArgs head_args(smc_t h, const float* theta) {
     a.A = h->lb[L - 2].act;
     a.sAj = h->mc * a.H;
     a.sAm = a.H;
-    if (h->split) a.Alo = (const char*)a.A + h->mc * (int64_t)h->J * a.H * (int64_t)h->esz;
+    a.a_f32 = h->split;
   } else {
     a.A = h->X;
     a.sAj = 0;
