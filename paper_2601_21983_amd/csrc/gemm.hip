@@ -1,21 +1,7 @@
-// MFMA GEMM kernels for gfx950 (CDNA4).
-//
-// Tiling: a 256-thread workgroup (4 wave64s) computes a BM x BN tile; each wave
-// owns a WM x WN sub-tile made of 32x32 MFMA blocks.  Every K step stages a
-// 128-byte-deep slice of A and B (64 bf16 or 32 fp32) in LDS with a 16-byte row
-// pad (row stride 144 B, so the 16-byte fragment reads of 16 consecutive rows hit
-// distinct banks) and double-buffers it, prefetching the next slice into
-// registers while the current one feeds the matrix cores.
-//
-// MFMA forms:
-//   bf16: v_mfma_f32_32x32x16_bf16 - each lane supplies 8 consecutive K values
-//   fp32: v_mfma_f32_32x32x2_f32   - each lane reads 4 consecutive K values and
-//         issues 4 MFMAs, instruction c taking component c (lane halves cover
-//         k and k+4), so one 16-byte LDS read feeds 4 instructions.
-// Both operands use the same lane->k assignment, so any such assignment yields
-// the same sum; only the row/column lane mapping (row = lane % 32) and the
-// accumulator layout (row = 8*(q/4) + 4*(lane/32) + q%4, col = lane % 32) matter.
+// Batched MFMA GEMM kernels for gfx950 (CDNA4) with fused epilogues; the tile
+// main loop (LDS staging, MFMA forms, XCD-aware tile order) is in gemm_core.h.
 #include "gemm.h"
+#include "gemm_core.h"
 
 #include <type_traits>
 
@@ -23,31 +9,7 @@ namespace smc {
 
 namespace {
 
-constexpr int THREADS = 256;
-constexpr int ROW_BYTES = 128;          // K slice per stage, in bytes
-constexpr int LDS_ROW = ROW_BYTES + 16; // padded LDS row stride
-constexpr int ROWV = ROW_BYTES / 16;    // 16-byte vectors per row
-
-template <typename T> struct Mf;
-template <> struct Mf<__bf16> {
-  static constexpr int VEC = 8;
-  __device__ static __forceinline__ f32x16 mma(const u32x4& a, const u32x4& b, f32x16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
-                                                    0, 0, 0);
-  }
-};
-template <> struct Mf<float> {
-  static constexpr int VEC = 4;
-  __device__ static __forceinline__ f32x16 mma(const u32x4& a, const u32x4& b, f32x16 c) {
-    const f32x4 av = __builtin_bit_cast(f32x4, a);
-    const f32x4 bv = __builtin_bit_cast(f32x4, b);
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bv[0], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[1], bv[1], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[2], bv[2], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[3], bv[3], c, 0, 0, 0);
-    return c;
-  }
-};
+using namespace gcore;
 
 struct SplitIdx {
   int64_t colpart;  // (col / cs) * sC + (col % cs) * cstr + b * sb
@@ -81,140 +43,24 @@ __device__ __forceinline__ float act_deriv(float a) {
 
 // ACT: activation of the FWD epilogue / derivative of the DELTA epilogue (-1: none)
 // F32O: the FWD epilogue stores FP32 values (BF16 operands only)
-// The BF16 256x128 tile keeps one LDS stage so that two workgroups share a CU (one's
-// prologue and epilogue overlap the other's matrix-core loop; measured 1.3-1.6x on the
-// layer-1 GEMMs).  Other tiles, and FP32 (whose weight-gradient GEMM lost 15% that way),
-// double-buffer with one workgroup per CU.
-constexpr int tile_nbuf(int bm, int bn, int esz) { return (bm == 256 && bn == 128 && esz == 2) ? 1 : 2; }
-constexpr int tile_minb(int bm, int bn, int esz) { return tile_nbuf(bm, bn, esz) == 1 ? 2 : 1; }
-
 template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT, bool F32O>
 __global__ __launch_bounds__(THREADS, tile_minb(BM, BN, (int)sizeof(T))) void gemm_nt(const GemmParams p) {
-  constexpr int VEC = Mf<T>::VEC;
-  constexpr int BKE = ROW_BYTES / (int)sizeof(T);
   constexpr int NWN = BN / WN;
   constexpr int FM = WM / 32, FN = WN / 32;
-  constexpr int AV = BM * ROWV / THREADS;
-  constexpr int BV = BN * ROWV / THREADS;
   constexpr int STAGE = (BM + BN) * LDS_ROW;
-  static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
-  static_assert(AV >= 1 && BV >= 1, "tile too small");
-
   constexpr int NBUF = tile_nbuf(BM, BN, (int)sizeof(T));
   __shared__ __attribute__((aligned(16))) char smem[NBUF * STAGE];
 
   const int b = blockIdx.y;
-  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
-  // renumber them so that each XCD receives a contiguous range of tiles, and walk
-  // that range in groups of GROUP_M row-tiles per column-tile (the group's A panels
-  // stay in the XCD's L2 while the B panel streams once per group).
   int tm, tn;
-  {
-    const int nM = (p.M + BM - 1) / BM, nN = (p.N + BN - 1) / BN;
-    const int ntiles = nM * nN;
-    const int pid = blockIdx.x;
-    int t = pid;
-    if (ntiles % 8 == 0) t = (pid % 8) * (ntiles / 8) + pid / 8;
-    constexpr int GROUP_M = 8;
-    const int group = t / (GROUP_M * nN);
-    const int first_m = group * GROUP_M;
-    const int gm = min(nM - first_m, GROUP_M);
-    const int r = t - group * GROUP_M * nN;
-    tm = first_m + r % gm;
-    tn = r / gm;
-  }
+  tile_order((p.M + BM - 1) / BM, (p.N + BN - 1) / BN, blockIdx.x, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / NWN, wn = wave % NWN;
-  const T* __restrict__ A = (const T*)p.A + (int64_t)b * p.sAb;
-  const T* __restrict__ B = (const T*)p.B + (int64_t)b * p.sBb;
-  const int M = p.M, N = p.N, K = p.K;
-
-  // per-thread global source rows (clamped into range; results outside are not stored)
-  const T* arow[AV];
-  const T* brow[BV];
-#pragma unroll
-  for (int i = 0; i < AV; ++i) {
-    const int r = (tid + i * THREADS) / ROWV;
-    const int gr = min(m0 + r, M - 1);
-    arow[i] = A + (int64_t)gr * p.lda + ((tid + i * THREADS) % ROWV) * VEC;
-  }
-#pragma unroll
-  for (int i = 0; i < BV; ++i) {
-    const int r = (tid + i * THREADS) / ROWV;
-    const int gr = min(n0 + r, N - 1);
-    brow[i] = B + (int64_t)gr * p.ldb + ((tid + i * THREADS) % ROWV) * VEC;
-  }
-  const int kvec = (tid % ROWV) * VEC;  // same for every i since THREADS % ROWV == 0
-
-  u32x4 ra[AV], rb[BV];
-  auto gload = [&](int kt) {
-    const int k = kt * BKE + kvec;
-    const bool ok = k < K;
-#pragma unroll
-    for (int i = 0; i < AV; ++i) {
-      ra[i] = ok ? *(const u32x4*)(arow[i] + (int64_t)kt * BKE) : u32x4{0u, 0u, 0u, 0u};
-    }
-#pragma unroll
-    for (int i = 0; i < BV; ++i) {
-      rb[i] = ok ? *(const u32x4*)(brow[i] + (int64_t)kt * BKE) : u32x4{0u, 0u, 0u, 0u};
-    }
-  };
-  auto sstore = [&](int buf) {
-    char* base = smem + buf * STAGE;
-#pragma unroll
-    for (int i = 0; i < AV; ++i) {
-      const int v = tid + i * THREADS;
-      *(u32x4*)(base + (v / ROWV) * LDS_ROW + (v % ROWV) * 16) = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < BV; ++i) {
-      const int v = tid + i * THREADS;
-      *(u32x4*)(base + (BM + v / ROWV) * LDS_ROW + (v % ROWV) * 16) = rb[i];
-    }
-  };
-
+  const int M = p.M, N = p.N;
   f32x16 acc[FM][FN];
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
-
-  const int nk = (K + BKE - 1) / BKE;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-
-  const int frow = lane & 31;
-  const int fhalf = (lane >> 5) * 16;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = NBUF == 2 ? (kt & 1) : 0;
-    if (kt + 1 < nk) gload(kt + 1);
-    const char* base = smem + buf * STAGE;
-#pragma unroll
-    for (int ks = 0; ks < ROW_BYTES / 32; ++ks) {
-      u32x4 fa[FM], fb[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-        fa[i] = *(const u32x4*)(base + (wm * WM + i * 32 + frow) * LDS_ROW + ks * 32 + fhalf);
-#pragma unroll
-      for (int j = 0; j < FN; ++j)
-        fb[j] = *(const u32x4*)(base + (BM + wn * WN + j * 32 + frow) * LDS_ROW + ks * 32 + fhalf);
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = Mf<T>::mma(fa[i], fb[j], acc[i][j]);
-    }
-    if (NBUF == 2) {
-      if (kt + 1 < nk) sstore(buf ^ 1);
-    } else if (kt + 1 < nk) {
-      __syncthreads();  // every wave is done reading the stage
-      sstore(0);
-    }
-    __syncthreads();
-  }
+  mainloop<T, BM, BN, WM, WN, NBUF>((const T*)p.A + (int64_t)b * p.sAb, (const T*)p.B + (int64_t)b * p.sBb, p.lda,
+                                    p.ldb, M, N, p.K, m0, n0, smem, acc);
 
   // ------------------------------------------------------------------ epilogue
   // Staged path: one output whose columns are contiguous inside each column-split
