@@ -34,7 +34,10 @@
 // precisions read 4 consecutive K values per lane.  Accumulator layout: lane l
 // holds rows 4(l/16) + i, column l % 16.
 // Log-likelihoods are summed in FP64 in a fixed order.
+#include "gemm_core.h"
 #include "kernels.h"
+
+#include <algorithm>
 
 namespace smc {
 
@@ -137,27 +140,35 @@ __host__ __device__ inline HeadLayout head_layout(int H, bool stage, bool spl) {
 
 typedef __attribute__((__vector_size__(2 * sizeof(uint32_t)))) uint32_t u32x2;
 
-template <typename T, int MODE, int NQ, bool SPL>
-__global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const HeadLayout Lo) {
-  extern __shared__ __attribute__((aligned(16))) char hsm[];
-  T* Wc = (T*)hsm;
-  T* Wt = (T*)(hsm + Lo.offWt);
-  T* As = (T*)(hsm + Lo.offAs);
-  T* WcLo = Wc + 16 * Lo.AS;     // lo planes (SPL only)
-  T* WtLo = Wt + Lo.Hp * Lo.WT;
-  T* AsLo = As + HT * Lo.AS;
-  const bool alo = SPL && a.a_f32;  // activations arrive in FP32 and get a lo plane
-  T* Dt = (T*)(hsm + Lo.offDt);
-  T* St = (T*)(hsm + Lo.offSt);
-  double* red = (double*)(hsm + Lo.offRed);
-  float* bred = (float*)(red + 64);
-  const int H = a.H, C = a.C, Hp = Lo.Hp, AS = Lo.AS, WT = Lo.WT, DS = Lo.DS, SS = Lo.SS;
-  const int NHB = Hp / 16;
-  const int j = blockIdx.y, split = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int g = lane >> 4, cl = lane & 15;
+// LDS regions of the output-layer work (offsets from head_layout).
+template <typename T>
+struct HeadSmem {
+  T *Wc, *Wt, *As, *WcLo, *WtLo, *AsLo, *Dt, *St;
+  double* red;
+};
 
-  // weights of the output layer: Wc[c][h] = [W | b], Wt[h][c] = W^T (zero padded)
+template <typename T>
+__device__ __forceinline__ HeadSmem<T> head_smem(char* base, const HeadLayout& Lo) {
+  HeadSmem<T> S;
+  S.Wc = (T*)base;
+  S.Wt = (T*)(base + Lo.offWt);
+  S.As = (T*)(base + Lo.offAs);
+  S.WcLo = S.Wc + 16 * Lo.AS;  // lo planes (split operands only)
+  S.WtLo = S.Wt + Lo.Hp * Lo.WT;
+  S.AsLo = S.As + HT * Lo.AS;
+  S.Dt = (T*)(base + Lo.offDt);
+  S.St = (T*)(base + Lo.offSt);
+  S.red = (double*)(base + Lo.offRed);
+  return S;
+}
+
+// Output-layer weights of particle j into LDS: Wc[c][h] = [W | b], Wt[h][c] = W^T (zero
+// padded), with their lo planes for split operands.
+template <typename T, int MODE, bool SPL>
+__device__ __forceinline__ void head_weights(const HeadArgs& a, const HeadLayout& Lo, const HeadSmem<T>& S, int j) {
+  T *Wc = S.Wc, *Wt = S.Wt, *WcLo = S.WcLo, *WtLo = S.WtLo;
+  const int H = a.H, C = a.C, Hp = Lo.Hp, AS = Lo.AS, WT = Lo.WT;
+  const int tid = threadIdx.x;
   const float* wsrc = a.theta + (int64_t)j * a.D + a.offL;
   for (int e = tid; e < 16 * AS; e += HTHREADS) {
     const int c = e / AS, h = e - c * AS;
@@ -175,6 +186,178 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
       if (SPL) WtLo[e] = cvt_out<T>(v - cvt_in<T>(hi));
     }
   }
+}
+
+// Steps 1-4 on the 64-sample activation tile staged in As (and AsLo) whose first sample
+// (within the chunk) is s0.  Every thread of the workgroup calls it (it synchronises).
+template <typename T, int MODE, int NQ, bool SPL>
+__device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& Lo, const HeadSmem<T>& S, int j, int s0,
+                                          float lam, bool alo, double& llacc, f32x4 (&dacc)[NQ]) {
+  T *Wc = S.Wc, *Wt = S.Wt, *As = S.As, *WcLo = S.WcLo, *WtLo = S.WtLo, *AsLo = S.AsLo, *Dt = S.Dt, *St = S.St;
+  const int H = a.H, C = a.C, Hp = Lo.Hp, AS = Lo.AS, WT = Lo.WT, DS = Lo.DS, SS = Lo.SS;
+  const int NHB = Hp / 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, cl = lane & 15;
+  // ---- 1. logits^T for this wave's 16 samples
+  const T* arow = As + (w * 16 + cl) * AS + 4 * g;
+  const T* wrow = Wc + cl * AS + 4 * g;
+  f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (SPL) {
+    const T* wrowlo = WcLo + cl * AS + 4 * g;
+    const T* arowlo = AsLo + (w * 16 + cl) * AS + 4 * g;
+    for (int kb = 0; kb < NHB; ++kb) {
+      const typename V4<T>::type wv = ld4(wrow + kb * 16), av = ld4(arow + kb * 16);
+      z = mma16(ld4(wrowlo + kb * 16), av, z);
+      if (alo) z = mma16(wv, ld4(arowlo + kb * 16), z);
+      z = mma16(wv, av, z);
+    }
+  } else {
+    for (int kb = 0; kb < NHB; ++kb) z = mma16(ld4(wrow + kb * 16), ld4(arow + kb * 16), z);
+  }
+
+  // ---- 2. likelihood and output error (sample cl, classes 4g + i)
+  const int sl = w * 16 + cl;           // sample within the tile
+  const int sg = s0 + sl;               // sample within the chunk
+  const bool valid = sg < a.m_valid;
+  float d[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (a.likelihood == 0) {
+    float zz[4];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      zz[i] = (4 * g + i < C) ? z[i] : -INFINITY;
+      mx = fmaxf(mx, zz[i]);
+    }
+    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    float se = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) se += (4 * g + i < C) ? expf(zz[i] - mx) : 0.0f;
+    se += __shfl_xor(se, 16, 64);
+    se += __shfl_xor(se, 32, 64);
+    const float lse = mx + logf(se);
+    if (MODE == HEAD_PREDICT) {
+      if (valid) {
+        float* lp = a.logp + ((int64_t)j * a.ld_logp + a.c0 + sg) * C;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (4 * g + i < C) lp[4 * g + i] = zz[i] - lse;
+      }
+    } else {
+      const int y = valid ? a.ylab[a.c0 + sg] : -1;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 4 * g + i;
+        if (c == y) llacc += (double)(zz[i] - lse);
+        if (MODE == HEAD_TRAIN && valid && c < C) d[i] = lam * ((c == y ? 1.0f : 0.0f) - expf(zz[i] - lse));
+      }
+    }
+  } else {
+    // one output: the value sits in lane group 0, register 0
+    const float yv = valid ? a.yreal[a.c0 + sg] : 0.0f;
+    const float r = yv - z[0];
+    if (MODE == HEAD_PREDICT) {
+      if (valid && g == 0) a.logp[(int64_t)j * a.ld_logp + a.c0 + sg] = z[0];
+    } else if (g == 0 && valid) {
+      llacc += (double)(a.gauss_c - 0.5f * r * r * a.inv_var);
+      if (MODE == HEAD_TRAIN) d[0] = lam * r * a.inv_var;
+    }
+  }
+
+  if (MODE == HEAD_TRAIN) {
+    // ---- 3. delta_{L-1}^T = W^T delta^T (times act'), staged for sample-contiguous stores
+    if (a.dT) {
+      const typename V4<T>::type bd = pack4<T>(d);
+      for (int hb = 0; hb < NHB; ++hb) {
+        f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (SPL) v = mma16(ld4(WtLo + (hb * 16 + cl) * WT + 4 * g), bd, v);
+        v = mma16(ld4(Wt + (hb * 16 + cl) * WT + 4 * g), bd, v);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int h = hb * 16 + 4 * g + i;
+          if (h < H) {
+            const float av = cvt_in<T>(As[sl * AS + h]) + (alo ? cvt_in<T>(AsLo[sl * AS + h]) : 0.0f);
+            const float dv = v[i] * act_grad_from_out(av, a.act);
+            if (Lo.stage) St[h * SS + sl] = cvt_out<T>(dv);
+            else ((T*)a.dT)[(int64_t)j * a.sdTj + (int64_t)h * a.sdTh + sg] = cvt_out<T>(dv);
+            if (a.dR) ((T*)a.dR)[(int64_t)j * a.sdRj + (int64_t)sg * a.sdRm + h] = cvt_out<T>(dv);
+          }
+        }
+      }
+    }
+    // delta^T to LDS for the dW_L product
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Dt[(4 * g + i) * DS + sl] = cvt_out<T>(d[i]);
+    __syncthreads();
+    if (a.dT && Lo.stage) {
+      // rows h < H of 64 samples each, 16-byte vectors
+      constexpr int VPR = HT * (int)sizeof(T) / 16;  // vectors per row
+      for (int e = tid; e < H * VPR; e += HTHREADS) {
+        const int h = e / VPR, v = e - h * VPR;
+        const u32x4 val = *(const u32x4*)(St + h * SS + v * (16 / (int)sizeof(T)));
+        *(u32x4*)((T*)a.dT + (int64_t)j * a.sdTj + (int64_t)h * a.sdTh + s0 + v * (16 / (int)sizeof(T))) = val;
+      }
+    }
+    // ---- 4. dW_L += delta^T [A | 1]: this wave owns h-blocks w, w+4, ...
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int hb = w + 4 * q;
+      if (hb >= NHB) break;
+#pragma unroll
+      for (int kb = 0; kb < HT / 16; ++kb) {
+        const typename V4<T>::type av = ld4(Dt + cl * DS + kb * 16 + 4 * g);
+        const typename V4<T>::type bv = gather4(As + (kb * 16 + 4 * g) * AS + hb * 16 + cl, AS);
+        if (alo) dacc[q] = mma16(av, gather4(AsLo + (kb * 16 + 4 * g) * AS + hb * 16 + cl, AS), dacc[q]);
+        dacc[q] = mma16(av, bv, dacc[q]);
+      }
+    }
+  }
+}
+
+// The workgroup's log-likelihood partial and output-layer gradient partial (slot `split`).
+template <typename T, int MODE, int NQ>
+__device__ __forceinline__ void head_finish(const HeadArgs& a, const HeadLayout& Lo, const HeadSmem<T>& S, int j,
+                                            int split, double llacc, const f32x4 (&dacc)[NQ]) {
+  double* red = S.red;
+  const int H = a.H, C = a.C;
+  const int NHB = Lo.Hp / 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, cl = lane & 15;
+  if (MODE != HEAD_PREDICT) {
+    const double v = wave_sum(llacc);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (tid == 0) a.llpart[(int64_t)j * a.nsplit + split] = red[0] + red[1] + red[2] + red[3];
+  }
+  if (MODE == HEAD_TRAIN) {
+    const int npair = C * (H + 1);
+    float* dst = a.dWpart + ((int64_t)j * a.nsplit + split) * npair;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int hb = w + 4 * q;
+      if (hb >= NHB) break;
+      const int h = hb * 16 + cl;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 4 * g + i;
+        if (c < C && h <= H) dst[c * (H + 1) + h] = dacc[q][i];
+      }
+    }
+  }
+}
+
+template <typename T, int MODE, int NQ, bool SPL>
+__global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const HeadLayout Lo) {
+  extern __shared__ __attribute__((aligned(16))) char hsm[];
+  const HeadSmem<T> S = head_smem<T>(hsm, Lo);
+  T* As = S.As;
+  T* AsLo = S.AsLo;
+  const bool alo = SPL && a.a_f32;  // activations arrive in FP32 and get a lo plane
+  const int H = a.H, AS = Lo.AS;
+  const int j = blockIdx.y, split = blockIdx.x;
+  const int tid = threadIdx.x;
+  head_weights<T, MODE, SPL>(a, Lo, S, j);
   // activation tile: columns >= H are constant (1 at H, 0 beyond) for the whole kernel
   for (int e = tid; e < HT * (AS - H); e += HTHREADS) {
     const int s = e / (AS - H), h = H + (e - s * (AS - H));
@@ -293,150 +476,82 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
 
   if (t0 < t1) prefetch(t0);
   for (int t = t0; t < t1; ++t) {
-    const int s0 = t * HT;
     __syncthreads();  // previous tile's LDS reads are done
     stage(t);
     __syncthreads();
     if (t + 1 < t1) prefetch(t + 1);
+    head_tile<T, MODE, NQ, SPL>(a, Lo, S, j, t * HT, lam, alo, llacc, dacc);
+  }
+  head_finish<T, MODE, NQ>(a, Lo, S, j, split, llacc, dacc);
+}
 
-    // ---- 1. logits^T for this wave's 16 samples
-    const T* arow = As + (w * 16 + cl) * AS + 4 * g;
-    const T* wrow = Wc + cl * AS + 4 * g;
-    f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (SPL) {
-      const T* wrowlo = WcLo + cl * AS + 4 * g;
-      const T* arowlo = AsLo + (w * 16 + cl) * AS + 4 * g;
-      for (int kb = 0; kb < NHB; ++kb) {
-        const typename V4<T>::type wv = ld4(wrow + kb * 16), av = ld4(arow + kb * 16);
-        z = mma16(ld4(wrowlo + kb * 16), av, z);
-        if (alo) z = mma16(wv, ld4(arowlo + kb * 16), z);
-        z = mma16(wv, av, z);
-      }
-    } else {
-      for (int kb = 0; kb < NHB; ++kb) z = mma16(ld4(wrow + kb * 16), ld4(arow + kb * 16), z);
-    }
+// ------------------------------------------------------------------ fused layer 1 + output layer
+// For networks with one hidden layer of H <= 127 units: one workgroup computes, for 256
+// samples and one particle j, z1 = X W1_j^T on the matrix cores (gemm_core.h; the weight
+// copy holds 128 rows per particle, rows >= H zero), then applies bias and activation in
+// registers and runs the output-layer steps (head_tile) on four 64-sample passes straight
+// from the accumulators.  The hidden activations never reach HBM, and there is one launch
+// per chunk instead of two.  Split operands: X . [w_hi | w_lo] over K = 2 ldw, and the
+// activations are split into hi/lo when they are written to LDS.
+template <int ACT>
+__device__ __forceinline__ float fused_act(float v) {
+  if constexpr (ACT == ACT_RELU) return fmaxf(v, 0.0f);
+  else return tanhf(v);
+}
 
-    // ---- 2. likelihood and output error (sample cl, classes 4g + i)
-    const int sl = w * 16 + cl;           // sample within the tile
-    const int sg = s0 + sl;               // sample within the chunk
-    const bool valid = sg < a.m_valid;
-    float d[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (a.likelihood == 0) {
-      float zz[4];
-      float mx = -INFINITY;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        zz[i] = (4 * g + i < C) ? z[i] : -INFINITY;
-        mx = fmaxf(mx, zz[i]);
-      }
-      mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-      float se = 0.0f;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) se += (4 * g + i < C) ? expf(zz[i] - mx) : 0.0f;
-      se += __shfl_xor(se, 16, 64);
-      se += __shfl_xor(se, 32, 64);
-      const float lse = mx + logf(se);
-      if (MODE == HEAD_PREDICT) {
-        if (valid) {
-          float* lp = a.logp + ((int64_t)j * a.ld_logp + a.c0 + sg) * C;
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (4 * g + i < C) lp[4 * g + i] = zz[i] - lse;
-        }
-      } else {
-        const int y = valid ? a.ylab[a.c0 + sg] : -1;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int c = 4 * g + i;
-          if (c == y) llacc += (double)(zz[i] - lse);
-          if (MODE == HEAD_TRAIN && valid && c < C) d[i] = lam * ((c == y ? 1.0f : 0.0f) - expf(zz[i] - lse));
-        }
-      }
-    } else {
-      // one output: the value sits in lane group 0, register 0
-      const float yv = valid ? a.yreal[a.c0 + sg] : 0.0f;
-      const float r = yv - z[0];
-      if (MODE == HEAD_PREDICT) {
-        if (valid && g == 0) a.logp[(int64_t)j * a.ld_logp + a.c0 + sg] = z[0];
-      } else if (g == 0 && valid) {
-        llacc += (double)(a.gauss_c - 0.5f * r * r * a.inv_var);
-        if (MODE == HEAD_TRAIN) d[0] = lam * r * a.inv_var;
-      }
-    }
+constexpr int FBM = 256, FBN = 128;  // tile: samples x (one particle's padded units)
+constexpr int FSTAGE = (FBM + FBN) * gcore::LDS_ROW;
 
-    if (MODE == HEAD_TRAIN) {
-      // ---- 3. delta_{L-1}^T = W^T delta^T (times act'), staged for sample-contiguous stores
-      if (a.dT) {
-        const typename V4<T>::type bd = pack4<T>(d);
-        for (int hb = 0; hb < NHB; ++hb) {
-          f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
-          if (SPL) v = mma16(ld4(WtLo + (hb * 16 + cl) * WT + 4 * g), bd, v);
-          v = mma16(ld4(Wt + (hb * 16 + cl) * WT + 4 * g), bd, v);
+template <int MODE, bool SPL, int ACT>
+__global__ __launch_bounds__(HTHREADS, 2) void fwd_head_kernel(const GemmParams p, const HeadArgs a,
+                                                                const HeadLayout Lo) {
+  typedef __bf16 T;
+  constexpr int WM = 128, WN = 64, FM = WM / 32, FN = WN / 32, NQ = 2;
+  extern __shared__ __attribute__((aligned(16))) char fsm[];
+  int tm, jp;
+  gcore::tile_order((p.M + FBM - 1) / FBM, a.J, blockIdx.x, tm, jp);
+  const int m0 = tm * FBM;
+  f32x16 acc[FM][FN];
+  gcore::mainloop<T, FBM, FBN, WM, WN, 1>((const T*)p.A, (const T*)p.B, p.lda, p.ldb, p.M, a.J * FBN, p.K, m0,
+                                          jp * FBN, fsm, acc);
+
+  // the main loop ended with a barrier: its LDS stage is free for the output-layer work
+  const HeadSmem<T> S = head_smem<T>(fsm, Lo);
+  head_weights<T, MODE, SPL>(a, Lo, S, jp);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  const int H = a.H, Hp = Lo.Hp, AS = Lo.AS;
+  const float lam = a.scale ? (float)a.scale[jp] : (float)a.lambda;
+  const float* b1 = p.bias + (int64_t)jp * H;
+  double llacc = 0.0;
+  f32x4 dacc[NQ];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int h = hb * 16 + 4 * g + i;
-            if (h < H) {
-              const float av = cvt_in<T>(As[sl * AS + h]) + (alo ? cvt_in<T>(AsLo[sl * AS + h]) : 0.0f);
-              const float dv = v[i] * act_grad_from_out(av, a.act);
-              if (Lo.stage) St[h * SS + sl] = cvt_out<T>(dv);
-              else ((T*)a.dT)[(int64_t)j * a.sdTj + (int64_t)h * a.sdTh + sg] = cvt_out<T>(dv);
-              if (a.dR) ((T*)a.dR)[(int64_t)j * a.sdRj + (int64_t)sg * a.sdRm + h] = cvt_out<T>(dv);
-            }
+  for (int q = 0; q < NQ; ++q) dacc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    // samples m0 + 64q .. +63 sit in accumulator blocks 2(q&1), 2(q&1)+1 of the waves with wm = q/2
+    if (wm == (q >> 1)) {
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < FN; ++jj) {
+          const int u = wn * WN + jj * 32 + (lane & 31);
+          if (u >= Hp) continue;
+          const float bias = u < H ? b1[u] : 0.0f;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const int r = ii * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+            const float v = u < H ? fused_act<ACT>(acc[2 * (q & 1) + ii][jj][e] + bias) : (u == H ? 1.0f : 0.0f);
+            const T hi = to_bf16(v);
+            S.As[r * AS + u] = hi;
+            if (SPL) S.AsLo[r * AS + u] = to_bf16(v - from_bf16(hi));
           }
         }
-      }
-      // delta^T to LDS for the dW_L product
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Dt[(4 * g + i) * DS + sl] = cvt_out<T>(d[i]);
-      __syncthreads();
-      if (a.dT && Lo.stage) {
-        // rows h < H of 64 samples each, 16-byte vectors
-        constexpr int VPR = HT * (int)sizeof(T) / 16;  // vectors per row
-        for (int e = tid; e < H * VPR; e += HTHREADS) {
-          const int h = e / VPR, v = e - h * VPR;
-          const u32x4 val = *(const u32x4*)(St + h * SS + v * (16 / (int)sizeof(T)));
-          *(u32x4*)((T*)a.dT + (int64_t)j * a.sdTj + (int64_t)h * a.sdTh + s0 + v * (16 / (int)sizeof(T))) = val;
-        }
-      }
-      // ---- 4. dW_L += delta^T [A | 1]: this wave owns h-blocks w, w+4, ...
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int hb = w + 4 * q;
-        if (hb >= NHB) break;
-#pragma unroll
-        for (int kb = 0; kb < HT / 16; ++kb) {
-          const typename V4<T>::type av = ld4(Dt + cl * DS + kb * 16 + 4 * g);
-          const typename V4<T>::type bv = gather4(As + (kb * 16 + 4 * g) * AS + hb * 16 + cl, AS);
-          if (alo) dacc[q] = mma16(av, gather4(AsLo + (kb * 16 + 4 * g) * AS + hb * 16 + cl, AS), dacc[q]);
-          dacc[q] = mma16(av, bv, dacc[q]);
-        }
-      }
     }
-  }
-
-  if (MODE != HEAD_PREDICT) {
-    const double v = wave_sum(llacc);
     __syncthreads();
-    if (lane == 0) red[w] = v;
+    head_tile<T, MODE, NQ, SPL>(a, Lo, S, jp, m0 + 64 * q, lam, SPL, llacc, dacc);
     __syncthreads();
-    if (tid == 0) a.llpart[(int64_t)j * a.nsplit + split] = red[0] + red[1] + red[2] + red[3];
   }
-  if (MODE == HEAD_TRAIN) {
-    const int npair = C * (H + 1);
-    float* dst = a.dWpart + ((int64_t)j * a.nsplit + split) * npair;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int hb = w + 4 * q;
-      if (hb >= NHB) break;
-      const int h = hb * 16 + cl;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int c = 4 * g + i;
-        if (c < C && h <= H) dst[c * (H + 1) + h] = dacc[q][i];
-      }
-    }
-  }
+  head_finish<T, MODE, NQ>(a, Lo, S, jp, tm, llacc, dacc);
 }
 
 // Sum the per-split partials of one chunk in a fixed order and fold them into the
@@ -513,6 +628,42 @@ hipError_t head_run(const HeadArgs& a, int mode, int type, hipStream_t s) {
   return hipGetLastError();
 }
 
+bool fwd_head_supported(int H, int C) {
+  return H >= 1 && H < FBN && C >= 1 && C <= 16 && pick_layout<__bf16>(H, true).total <= LDS_LIMIT;
+}
+
+hipError_t fwd_head_run(const GemmParams& p, const HeadArgs& a, int mode, int split, int act, hipStream_t s) {
+  if (p.M <= 0) return hipSuccess;
+  if (!fwd_head_supported(a.H, a.C) || (act != ACT_RELU && act != ACT_TANH)) return hipErrorInvalidValue;
+  if (p.K % 8 || p.lda % 8 || p.ldb % 8 || ((uintptr_t)p.A | (uintptr_t)p.B) & 15) return hipErrorInvalidValue;
+  const int nM = (p.M + FBM - 1) / FBM;
+  if (a.nsplit != nM) return hipErrorInvalidValue;  // one partial per 256-sample tile
+  const HeadLayout L = pick_layout<__bf16>(a.H, split != 0);
+  const size_t smem = (size_t)std::max(FSTAGE, L.total);
+  const dim3 grid((unsigned)(nM * a.J));
+#define FH_LAUNCH(MODE, SPL, ACT) hipLaunchKernelGGL((fwd_head_kernel<MODE, SPL, ACT>), grid, dim3(HTHREADS), smem, s, p, a, L)
+#define FH_ACT(MODE, SPL)                                      \
+  do {                                                         \
+    if (act == ACT_RELU) FH_LAUNCH(MODE, SPL, ACT_RELU);       \
+    else FH_LAUNCH(MODE, SPL, ACT_TANH);                       \
+  } while (0)
+#define FH_MODE(SPL)                                           \
+  do {                                                         \
+    if (mode == HEAD_TRAIN) FH_ACT(HEAD_TRAIN, SPL);           \
+    else if (mode == HEAD_FORWARD) FH_ACT(HEAD_FORWARD, SPL);  \
+    else FH_ACT(HEAD_PREDICT, SPL);                            \
+  } while (0)
+  if (split) FH_MODE(true);
+  else FH_MODE(false);
+#undef FH_MODE
+#undef FH_ACT
+#undef FH_LAUNCH
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || mode == HEAD_PREDICT) return e;
+  hipLaunchKernelGGL(head_reduce_kernel, dim3(a.J), dim3(256), 0, s, a, a.beta, mode == HEAD_TRAIN ? 1 : 0);
+  return hipGetLastError();
+}
+
 hipError_t head_set_smem_limits() {
 #define HEAD_ATTR(T, MODE, NQ, SPL)                                                                       \
   hipFuncSetAttribute((const void*)head_kernel<T, MODE, NQ, SPL>, hipFuncAttributeMaxDynamicSharedMemorySize, \
@@ -532,6 +683,21 @@ hipError_t head_set_smem_limits() {
   HEAD_ATTR3(__bf16, HEAD_PREDICT, true);
 #undef HEAD_ATTR3
 #undef HEAD_ATTR
+#define FH_ATTR(MODE, SPL, ACT)                                                                        \
+  if ((e = hipFuncSetAttribute((const void*)fwd_head_kernel<MODE, SPL, ACT>,                             \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, LDS_LIMIT)) != hipSuccess) \
+  return e
+#define FH_ATTR2(MODE, SPL) \
+  FH_ATTR(MODE, SPL, ACT_RELU); \
+  FH_ATTR(MODE, SPL, ACT_TANH)
+  FH_ATTR2(HEAD_TRAIN, false);
+  FH_ATTR2(HEAD_FORWARD, false);
+  FH_ATTR2(HEAD_PREDICT, false);
+  FH_ATTR2(HEAD_TRAIN, true);
+  FH_ATTR2(HEAD_FORWARD, true);
+  FH_ATTR2(HEAD_PREDICT, true);
+#undef FH_ATTR2
+#undef FH_ATTR
   return e;
 }
 

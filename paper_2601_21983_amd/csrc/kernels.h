@@ -48,6 +48,11 @@ struct HeadArgs {
 enum HeadType { HEAD_F32 = 0, HEAD_BF16 = 1, HEAD_BF16_SPLIT = 2 };
 bool head_supported(int H, int C, int type);
 hipError_t head_run(const HeadArgs& a, int mode, int type, hipStream_t s);
+// Fused layer-1 GEMM + output layer for networks with one hidden layer (BF16 or split-BF16
+// operands): p describes z1 = X W1^T for the chunk (A = X rows, B = the weight copy with 128
+// rows per particle, bias = b1); a.nsplit must equal ceil(p.M / 256).
+bool fwd_head_supported(int H, int C);
+hipError_t fwd_head_run(const GemmParams& p, const HeadArgs& a, int mode, int split, int act, hipStream_t s);
 hipError_t head_set_smem_limits();
 
 // Convolutional network dimensions (conv3x3 C1 -> conv3x3 C2 -> 2x2 avgpool -> linear ncls).
@@ -97,8 +102,9 @@ struct NetShape {
   int nin[MAX_LAYERS] = {0}, nout[MAX_LAYERS] = {0};
   int64_t off[MAX_LAYERS + 1] = {0};  // parameter offsets of each layer block; off[L] = D
   int ldw[MAX_LAYERS] = {0};          // padded row length of the GEMM weight copy
+  int rowpad[MAX_LAYERS] = {0};       // rows per particle in the GEMM weight copy (>= nout, extra rows zero)
   float rinv[MAX_LAYERS] = {0};       // 1 / (nin + 1)
-  void* w[MAX_LAYERS] = {nullptr};    // GEMM weight copy [J*nout x ldw] (operand type)
+  void* w[MAX_LAYERS] = {nullptr};    // GEMM weight copy [J*rowpad x ldw] (operand type)
   float* bias[MAX_LAYERS] = {nullptr};// [J*nout]
   int64_t D = 0;
   int J = 0;
@@ -109,11 +115,11 @@ struct NetShape {
 // Store parameter v of particle j (layer l, output unit o, input i; i == nin is the
 // bias) into the GEMM copy of that layer.
 __device__ __forceinline__ void weight_copy_store(const NetShape& n, int j, int l, int o, int i, float v) {
-  const int64_t r = (int64_t)j * n.nout[l] + o;
   if (i >= n.nin[l]) {
-    n.bias[l][r] = v;
+    n.bias[l][(int64_t)j * n.nout[l] + o] = v;
     return;
   }
+  const int64_t r = (int64_t)j * n.rowpad[l] + o;
   if (!n.bf16) {
     ((float*)n.w[l])[r * n.ldw[l] + i] = v;
     return;

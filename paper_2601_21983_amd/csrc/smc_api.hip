@@ -170,6 +170,7 @@ struct smc_handle {
   hipStream_t stream = nullptr;
   std::vector<void*> owned;
   int J = 0, L = 0, F = 0, C = 0, bf16 = 0, split = 0, cnn = 0;
+  int fused = 0;  // one hidden layer, BF16 operands: layer 1 and the output layer in one kernel
   CnnBufs cb;
   int64_t D = 0;
   int64_t n_data = 0, n_pad = 0;
@@ -364,6 +365,7 @@ void setup_shapes(smc_t h) {
     n.nout[l] = h->cnn ? cnn_out[l] : c.widths[l + 1];
     n.off[l] = off;
     n.ldw[l] = (int)round_up(n.nin[l], 8);
+    n.rowpad[l] = n.nout[l];
     n.rinv[l] = 1.0f / (float)(n.nin[l] + 1);
     off += (int64_t)n.nout[l] * (n.nin[l] + 1);
   }
@@ -373,6 +375,8 @@ void setup_shapes(smc_t h) {
   if (h->D > (1 << 24)) fail(SMC_ERR_UNSUPPORTED, "more than 2^24 parameters per particle");
   h->ldx = (int)round_up(h->F, 8);
   h->xld = h->split ? 2 * h->ldx : h->ldx;
+  h->fused = !h->cnn && h->L == 2 && h->bf16 && fwd_head_supported(n.nin[1], h->C);
+  if (h->fused) n.rowpad[0] = 128;  // one 128-row tile per particle
   h->nblk = (int)((h->D + MOVE_ELEMS - 1) / MOVE_ELEMS);
 }
 
@@ -392,7 +396,7 @@ int64_t choose_chunk(smc_t h) {
   int64_t per_sample = 0;  // bytes of activation buffers per sample
   for (int l = 0; l < h->L - 1; ++l) {
     const int64_t u = (int64_t)h->J * h->net.nout[l];
-    per_sample += u * h->esz * (h->split ? 3 : 2);                 // act (+ lo plane) + dT
+    per_sample += u * h->esz * (h->fused ? 1 : (h->split ? 3 : 2));  // dT (+ act: FP32 for split)
     if (l >= 1) per_sample += u * h->esz;                          // dR
     if (l + 1 < h->L - 1) per_sample += (int64_t)h->J * (h->net.nout[l] + 1) * h->esz;  // actT
   }
@@ -457,7 +461,7 @@ void alloc_all(smc_t h) {
   HIPCHECK(hipMemsetAsync(h->stats, 0, 16 * sizeof(double), h->stream));
   HIPCHECK(hipMemsetAsync(h->part, 0, (size_t)3 * J * h->nblk * sizeof(double), h->stream));
   for (int l = 0; l < h->L; ++l) {
-    const int64_t n = (int64_t)J * h->net.nout[l] * h->net.ldw[l] * (int64_t)h->esz * (h->split ? 2 : 1);
+    const int64_t n = (int64_t)J * h->net.rowpad[l] * h->net.ldw[l] * (int64_t)h->esz * (h->split ? 2 : 1);
     h->net.w[l] = dalloc<char>(h->owned, n);
     HIPCHECK(hipMemsetAsync(h->net.w[l], 0, (size_t)n, h->stream));  // row padding stays zero
     h->net.bias[l] = dalloc<float>(h->owned, (int64_t)J * h->net.nout[l]);
@@ -471,7 +475,7 @@ void alloc_all(smc_t h) {
   for (int l = 0; l < h->L - 1; ++l) {
     const int64_t u = (int64_t)J * h->net.nout[l];
     LayerBufs& b = h->lb[l];
-    b.act = dalloc<char>(h->owned, mc * u * (int64_t)h->esz * (h->split ? 2 : 1));
+    if (!h->fused) b.act = dalloc<char>(h->owned, mc * u * (int64_t)h->esz * (h->split ? 2 : 1));
     b.dT = dalloc<char>(h->owned, mc * u * (int64_t)h->esz);
     if (l >= 1) b.dR = dalloc<char>(h->owned, mc * u * (int64_t)h->esz);
     if (l + 1 < h->L - 1) {
@@ -496,6 +500,7 @@ void alloc_all(smc_t h) {
   }
   const int ntiles = (int)(mc / 64);
   h->nsplit_max = std::max(1, std::min(ntiles, (2048 + J - 1) / J));
+  if (h->fused) h->nsplit_max = std::max(h->nsplit_max, (int)((mc + 255) / 256));  // one partial per 256 samples
   const int H = h->net.nin[h->L - 1];
   h->llpart = dalloc<double>(h->owned, (int64_t)J * h->nsplit_max);
   h->dWpart = dalloc<float>(h->owned, (int64_t)J * h->nsplit_max * h->C * (H + 1));
@@ -861,6 +866,29 @@ void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const doubl
   if (train) h->grad_evals += (int64_t)J * m;
 }
 
+// Layer 1 and the output layer of samples [c0, c0 + mcv) of the operand Xop in one fused
+// kernel (networks with one hidden layer, BF16 or split-BF16 operands); a carries the
+// output-layer arguments (mode, targets, dT).  Timed as the layer-1 forward class with the
+// algorithmic FLOPs of both layers.
+void fused_chunk(smc_t h, const void* Xop, int64_t c0, int mcv, int mode, HeadArgs& a) {
+  const int rows = (int)round_up(mcv, 64);
+  GemmParams p;
+  p.A = (const char*)Xop + c0 * h->xld * (int64_t)h->esz;
+  p.lda = h->xld;
+  p.M = rows;
+  p.K = h->net.ldw[0] * (h->split ? 2 : 1);  // split: [x | x] . [w_hi | w_lo]
+  p.B = h->net.w[0];
+  p.ldb = p.K;
+  p.bias = h->net.bias[0];
+  a.m_valid = mcv;
+  a.c0 = c0;
+  a.nsplit = (rows + 255) / 256;
+  const double H = h->net.nout[0], flops = 2.0 * mcv * (double)h->J * H * h->F +
+                                           (mode == HEAD_TRAIN ? 6.0 : 2.0) * a.C * H * h->J * mcv;
+  timed(h, SMC_K_GEMM_FWD1, flops, 0.0,
+        [&]() { HIPCHECK(fwd_head_run(p, a, mode, h->split, h->cfg.activation, h->stream)); });
+}
+
 // One pass over the subset [0, m): log-likelihoods ll_out[j] (FP64) and, when
 // g_out is given, g_out[j] = scale_j * d LL_j / d theta_j (the lambda-scaled
 // likelihood gradient).  The GEMM copies of `theta` must be current.
@@ -877,7 +905,7 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
     const int mcv = (int)std::min<int64_t>(h->mc, m - c0);
     const int rows = (int)round_up(mcv, 64);
     const int beta = c0 > 0 ? 1 : 0;
-    forward_hidden(h, h->X, c0, rows, mcv);
+    if (!h->fused) forward_hidden(h, h->X, c0, rows, mcv);
     HeadArgs a = head_args(h, theta);
     if (L == 1) a.A = (const char*)h->X + c0 * h->xld * (int64_t)h->esz;
     a.m_valid = mcv;
@@ -898,8 +926,12 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
         a.sdRm = a.H;
       }
     }
-    timed(h, SMC_K_HEAD, (train ? 6.0 : 2.0) * a.C * (double)a.H * J * mcv, 0.0,
-          [&]() { HIPCHECK(head_run(a, train ? HEAD_TRAIN : HEAD_FORWARD, head_type(h->cfg.precision), h->stream)); });
+    if (h->fused)
+      fused_chunk(h, h->X, c0, mcv, train ? HEAD_TRAIN : HEAD_FORWARD, a);
+    else
+      timed(h, SMC_K_HEAD, (train ? 6.0 : 2.0) * a.C * (double)a.H * J * mcv, 0.0, [&]() {
+        HIPCHECK(head_run(a, train ? HEAD_TRAIN : HEAD_FORWARD, head_type(h->cfg.precision), h->stream));
+      });
     if (!train) continue;
     // backward through the hidden layers, top down
     for (int l = L - 2; l >= 0; --l) {
@@ -1377,6 +1409,13 @@ smc_status smc_posterior_predict(smc_t h, const float* x_dev, const int32_t* y_d
         la.logp = h->logp;
         la.ld_logp = n;
         HIPCHECK(cnn_ll_run(la, h->J, h->bf16, h->stream));
+        continue;
+      }
+      if (h->fused) {
+        HeadArgs a = head_args(h, h->theta);
+        a.logp = h->logp;
+        a.ld_logp = n;
+        fused_chunk(h, h->tx, c0, mcv, HEAD_PREDICT, a);
         continue;
       }
       const int rows = (int)round_up(mcv, 64);
