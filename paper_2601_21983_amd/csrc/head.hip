@@ -113,7 +113,10 @@ __host__ __device__ inline HeadLayout head_layout(int H, bool stage, bool spl) {
   const int e = (int)sizeof(T);
   L.planes = spl ? 2 : 1;
   L.Hp = rup(H + 1, 16);
-  L.AS = L.Hp + 16 / e * 2;  // pad: keeps 16 consecutive rows on distinct banks
+  // activation / weight row stride: BF16 rows are an odd multiple of 16 elements (8 * odd
+  // dwords), so the 16 rows a wave reads at once (fragment rows and activation columns) fall
+  // on distinct banks; FP32 rows are padded by 32 bytes
+  L.AS = e == 2 ? ((L.Hp / 16) % 2 ? L.Hp : L.Hp + 16) : L.Hp + 16 / e * 2;
   L.WT = 16 + 8 / e * 2;
   L.DS = HT + 16 / e;
   L.SS = HT + 16 / e;
