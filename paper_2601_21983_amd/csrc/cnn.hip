@@ -91,27 +91,39 @@ __global__ void im2col_a_kernel(const T* __restrict__ act1, int64_t sA, int mcv,
   *(u32x4*)(big + (int64_t)j * sB + r * d.K2 + k) = v;
 }
 
-// bigT[j][k][r] (row stride ld) = act1 patch transposed, ones row at k = K2
+// bigT[j][k][r] (row stride ld) = act1 patch transposed, ones row at k = K2.  One thread per
+// (j, tap, 8-channel vector, pixel r), pixels fastest: a 16-byte read of 8 channels of the
+// source pixel, eight 2-byte writes that are contiguous across the wave's pixels.
 template <typename T>
 __global__ void im2col_at_kernel(const T* __restrict__ act1, int64_t sA, int mcv, CnnDims d, int J, int64_t ld,
                                  T* __restrict__ bigT, int64_t sB) {
+  constexpr int VEC = 16 / (int)sizeof(T);
   const int64_t i = gtid();
   const int64_t R = (int64_t)mcv * d.HW;
-  const int64_t per = (int64_t)(d.K2 + 1) * R;
-  if (i >= (int64_t)J * per) return;
+  const int nv = d.C1 / VEC;
+  const int64_t per = (int64_t)9 * nv * R;
+  if (i >= (int64_t)J * per + (int64_t)J * R) return;
+  if (i >= (int64_t)J * per) {
+    // the ones row (bias gradient)
+    const int64_t e = i - (int64_t)J * per;
+    const int j = (int)(e / R);
+    bigT[(int64_t)j * sB + (int64_t)d.K2 * ld + (e - (int64_t)j * R)] = cvt_out<T>(1.0f);
+    return;
+  }
   const int j = (int)(i / per);
   const int64_t e = i - (int64_t)j * per;
-  const int k = (int)(e / R);
-  const int64_t r = e - (int64_t)k * R;
-  float v = 1.0f;
-  if (k < d.K2) {
-    const int64_t n = r / d.HW;
-    const int pix = (int)(r - n * d.HW);
-    const int tap = k / d.C1, c = k - tap * d.C1;
-    const int s = tap_src(d, pix, tap);
-    v = s >= 0 ? cvt_in<T>(act1[(int64_t)j * sA + (n * d.HW + s) * d.C1 + c]) : 0.0f;
-  }
-  bigT[(int64_t)j * sB + (int64_t)k * ld + r] = cvt_out<T>(v);
+  const int tv = (int)(e / R);
+  const int64_t r = e - (int64_t)tv * R;
+  const int tap = tv / nv, c = (tv - tap * nv) * VEC;
+  const int64_t n = r / d.HW;
+  const int pix = (int)(r - n * d.HW);
+  const int s = tap_src(d, pix, tap);
+  u32x4 v = {0u, 0u, 0u, 0u};
+  if (s >= 0) v = *(const u32x4*)(act1 + (int64_t)j * sA + (n * d.HW + s) * d.C1 + c);
+  const T* vv = (const T*)&v;
+  T* dst = bigT + (int64_t)j * sB + (int64_t)(tap * d.C1 + c) * ld + r;
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) dst[(int64_t)t * ld] = vv[t];
 }
 
 // pooled[j][n][(py Wp + px) C2 + c] = mean of the 2x2 block of act2
@@ -215,57 +227,81 @@ __global__ __launch_bounds__(256) void cnn_dw3_kernel(const T* __restrict__ d3, 
 }
 
 // error at the conv2 output: d2 = (unpooled dpool / 4) * 1{act2 > 0}, written as rows
-// d2[j][r][c] and transposed d2t[j][c][r] (row stride ld)
+// d2[j][r][c] and transposed d2t[j][c][r] (row stride ld).  One thread per (j, 8-channel
+// vector, pixel r), pixels fastest: 16-byte reads of act2 and dpool, a 16-byte row write and
+// eight 2-byte transposed writes contiguous across the wave's pixels.
 template <typename T>
 __global__ void unpool_kernel(const T* __restrict__ dpool, int64_t sP, const T* __restrict__ act2, int64_t sA,
                               int mcv, CnnDims d, int J, int64_t ld, T* __restrict__ d2, T* __restrict__ d2t) {
+  constexpr int VEC = 16 / (int)sizeof(T);
   const int64_t i = gtid();
   const int64_t R = (int64_t)mcv * d.HW;
-  const int64_t per = (int64_t)d.C2 * R;
+  const int nv = d.C2 / VEC;
+  const int64_t per = (int64_t)nv * R;
   if (i >= (int64_t)J * per) return;
   const int j = (int)(i / per);
   const int64_t e = i - (int64_t)j * per;
-  const int c = (int)(e / R);
-  const int64_t r = e - (int64_t)c * R;
+  const int cvi = (int)(e / R);
+  const int64_t r = e - (int64_t)cvi * R;
+  const int c = cvi * VEC;
   const int64_t n = r / d.HW;
   const int pix = (int)(r - n * d.HW);
   const int y = pix / d.W, x = pix - y * d.W;
   const int64_t ai = (int64_t)j * sA + r * d.C2 + c;
-  float v = 0.0f;
-  if (cvt_in<T>(act2[ai]) > 0.0f)
-    v = 0.25f * cvt_in<T>(dpool[(int64_t)j * sP + n * d.F3 + ((y >> 1) * d.Wp + (x >> 1)) * d.C2 + c]);
-  const T o = cvt_out<T>(v);
-  d2[ai] = o;
-  d2t[((int64_t)j * d.C2 + c) * ld + r] = o;
+  const u32x4 av = *(const u32x4*)(act2 + ai);
+  const u32x4 pv =
+      *(const u32x4*)(dpool + (int64_t)j * sP + n * d.F3 + ((y >> 1) * d.Wp + (x >> 1)) * d.C2 + c);
+  const T* a = (const T*)&av;
+  const T* pp = (const T*)&pv;
+  u32x4 ov;
+  T* o = (T*)&ov;
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) o[t] = cvt_out<T>(cvt_in<T>(a[t]) > 0.0f ? 0.25f * cvt_in<T>(pp[t]) : 0.0f);
+  *(u32x4*)(d2 + ai) = ov;
+  T* dt = d2t + ((int64_t)j * d.C2 + c) * ld + r;
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) dt[(int64_t)t * ld] = o[t];
 }
 
 // error at the conv1 output: sum over taps of the patch errors that read pixel r, times
-// 1{act1 > 0}; written transposed as d1t[j C1 + c][r] (row stride ld)
+// 1{act1 > 0}; written transposed as d1t[j C1 + c][r] (row stride ld).  One thread per
+// (j, 8-channel vector, pixel r), pixels fastest: nine 16-byte patch-error reads, one
+// 16-byte activation read, eight 2-byte writes contiguous across the wave's pixels.
 template <typename T>
 __global__ void col2im_kernel(const T* __restrict__ dp2, int64_t sB, const T* __restrict__ act1, int64_t sA,
                               int mcv, CnnDims d, int J, int64_t ld, T* __restrict__ d1t) {
+  constexpr int VEC = 16 / (int)sizeof(T);
   const int64_t i = gtid();
   const int64_t R = (int64_t)mcv * d.HW;
-  const int64_t per = (int64_t)d.C1 * R;
+  const int nv = d.C1 / VEC;
+  const int64_t per = (int64_t)nv * R;
   if (i >= (int64_t)J * per) return;
   const int j = (int)(i / per);
   const int64_t e = i - (int64_t)j * per;
-  const int c = (int)(e / R);
-  const int64_t r = e - (int64_t)c * R;
+  const int cvi = (int)(e / R);
+  const int64_t r = e - (int64_t)cvi * R;
+  const int c = cvi * VEC;
   const int64_t n = r / d.HW;
   const int pix = (int)(r - n * d.HW);
   const int y = pix / d.W, x = pix - y * d.W;
-  float v = 0.0f;
-  if (cvt_in<T>(act1[(int64_t)j * sA + r * d.C1 + c]) > 0.0f) {
-    const T* pj = dp2 + (int64_t)j * sB;
-    for (int tap = 0; tap < 9; ++tap) {
-      // output pixel (y - ky + 1, x - kx + 1) reads this pixel through tap (ky, kx)
-      const int yo = y - tap / 3 + 1, xo = x - tap % 3 + 1;
-      if (yo >= 0 && yo < d.H && xo >= 0 && xo < d.W)
-        v += cvt_in<T>(pj[(n * d.HW + yo * d.W + xo) * d.K2 + tap * d.C1 + c]);
-    }
+  float acc[VEC];
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) acc[t] = 0.0f;
+  const T* pj = dp2 + (int64_t)j * sB;
+  for (int tap = 0; tap < 9; ++tap) {
+    // output pixel (y - ky + 1, x - kx + 1) reads this pixel through tap (ky, kx)
+    const int yo = y - tap / 3 + 1, xo = x - tap % 3 + 1;
+    if (yo < 0 || yo >= d.H || xo < 0 || xo >= d.W) continue;
+    const u32x4 v = *(const u32x4*)(pj + (n * d.HW + yo * d.W + xo) * d.K2 + tap * d.C1 + c);
+    const T* vv = (const T*)&v;
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) acc[t] += cvt_in<T>(vv[t]);
   }
-  d1t[((int64_t)j * d.C1 + c) * ld + r] = cvt_out<T>(v);
+  const u32x4 av = *(const u32x4*)(act1 + (int64_t)j * sA + r * d.C1 + c);
+  const T* a = (const T*)&av;
+  T* dt = d1t + ((int64_t)j * d.C1 + c) * ld + r;
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) dt[(int64_t)t * ld] = cvt_out<T>(cvt_in<T>(a[t]) > 0.0f ? acc[t] : 0.0f);
 }
 
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -300,7 +336,9 @@ hipError_t cnn_im2col_a_run(const void* act1, int64_t sA, int mcv, const CnnDims
 
 hipError_t cnn_im2col_at_run(const void* act1, int64_t sA, int mcv, const CnnDims& d, int J, int64_t ld, void* bigT,
                              int64_t sB, int bf16, hipStream_t s) {
-  const int64_t n = (int64_t)J * (d.K2 + 1) * mcv * d.HW;
+  const int vec = bf16 ? 8 : 4;
+  if (d.C1 % vec) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)J * (9 * (d.C1 / vec) + 1) * mcv * d.HW;
   if (bf16) hipLaunchKernelGGL(im2col_at_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)act1, sA, mcv, d, J, ld, (__bf16*)bigT, sB);
   else hipLaunchKernelGGL(im2col_at_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)act1, sA, mcv, d, J, ld, (float*)bigT, sB);
   return hipGetLastError();
@@ -333,7 +371,9 @@ hipError_t cnn_dw3_run(const void* d3, const void* pooled, int64_t sP, int mc, i
 
 hipError_t cnn_unpool_run(const void* dpool, int64_t sP, const void* act2, int64_t sA, int mcv, const CnnDims& d,
                           int J, int64_t ld, void* d2, void* d2t, int bf16, hipStream_t s) {
-  const int64_t n = (int64_t)J * d.C2 * mcv * d.HW;
+  const int vec = bf16 ? 8 : 4;
+  if (d.C2 % vec) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)J * (d.C2 / vec) * mcv * d.HW;
   if (bf16) hipLaunchKernelGGL(unpool_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)dpool, sP, (const __bf16*)act2, sA, mcv, d, J, ld, (__bf16*)d2, (__bf16*)d2t);
   else hipLaunchKernelGGL(unpool_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)dpool, sP, (const float*)act2, sA, mcv, d, J, ld, (float*)d2, (float*)d2t);
   return hipGetLastError();
@@ -341,7 +381,9 @@ hipError_t cnn_unpool_run(const void* dpool, int64_t sP, const void* act2, int64
 
 hipError_t cnn_col2im_run(const void* dp2, int64_t sB, const void* act1, int64_t sA, int mcv, const CnnDims& d, int J,
                           int64_t ld, void* d1t, int bf16, hipStream_t s) {
-  const int64_t n = (int64_t)J * d.C1 * mcv * d.HW;
+  const int vec = bf16 ? 8 : 4;
+  if (d.C1 % vec) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)J * (d.C1 / vec) * mcv * d.HW;
   if (bf16) hipLaunchKernelGGL(col2im_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)dp2, sB, (const __bf16*)act1, sA, mcv, d, J, ld, (__bf16*)d1t);
   else hipLaunchKernelGGL(col2im_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)dp2, sB, (const float*)act1, sA, mcv, d, J, ld, (float*)d1t);
   return hipGetLastError();
