@@ -231,6 +231,7 @@ hipError_t gemm_run(const GemmParams& p, int type, hipStream_t stream) {
   const int vec = type == GEMM_BF16 ? 8 : 4;
   if (p.K % vec || p.lda % vec || p.ldb % vec) return hipErrorInvalidValue;
   if (((uintptr_t)p.A | (uintptr_t)p.B) & 15) return hipErrorInvalidValue;
+  if (!gcore::tile_offsets_fit(p.lda, p.ldb, vec == 8 ? 2 : 4)) return hipErrorInvalidValue;
   // the 256x128 tile keeps its 128 accumulators in registers only with the lean
   // epilogues (identity/ReLU forward, gradient); tanh and delta epilogues use 128x128
   const bool lean = p.epi == EPI_GRAD || (p.epi == EPI_FWD && p.act != ACT_TANH);

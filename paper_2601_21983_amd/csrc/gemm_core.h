@@ -17,6 +17,7 @@
 // the same sum; only the row/column lane mapping (row = lane % 32) and the
 // accumulator layout (row = 8*(q/4) + 4*(lane/32) + q%4, col = lane % 32) matter.
 #pragma once
+#include <algorithm>
 
 #include "common.h"
 
@@ -56,6 +57,12 @@ template <> struct Mf<float> {
 constexpr int tile_nbuf(int bm, int bn, int esz) { return (bm == 256 && bn == 128 && esz == 2) ? 1 : 2; }
 constexpr int tile_minb(int bm, int bn, int esz) { return tile_nbuf(bm, bn, esz) == 1 ? 2 : 1; }
 
+// Host check: the main loop addresses a tile's rows by 32-bit byte offsets from its first
+// row, so 256 rows of the larger leading dimension must span less than 4 GiB.
+inline bool tile_offsets_fit(int64_t lda, int64_t ldb, int esz) {
+  return 256 * std::max(lda, ldb) * esz < ((int64_t)1 << 32);
+}
+
 // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
 // renumber them so that each XCD receives a contiguous range of tiles, and walk
 // that range in groups of GROUP_M row-tiles per column-tile (the group's A panels
@@ -73,53 +80,66 @@ __device__ __forceinline__ void tile_order(int nM, int nN, int pid, int& tm, int
   tn = r / gm;
 }
 
+// LDS bytes of one stage: A rows, B rows (and the B lo rows of the split form)
+template <int BM, int BN, bool SB>
+constexpr int stage_bytes() { return (BM + (SB ? 2 : 1) * BN) * LDS_ROW; }
+
 // acc[i][j] (+)= the BM x BN tile at (m0, n0) of A[M x K] . B[N x K]^T (rows lda / ldb
-// apart).  Rows beyond M or N are clamped (their results are garbage and must not be
-// stored).  Ends with a barrier, after which smem may be reused.
-template <typename T, int BM, int BN, int WM, int WN, int NBUF>
+// apart).  Split form (SB): B has a second plane at b_lo elements after each row (the lo
+// parts of split-BF16 weights), and acc accumulates A.B_hi^T + A.B_lo^T: each A fragment
+// feeds two MFMAs, so A is loaded and staged once.  Rows beyond M or N are clamped (their
+// results are garbage and must not be stored).  Ends with a barrier, after which smem may
+// be reused.
+template <typename T, int BM, int BN, int WM, int WN, int NBUF, bool SB = false>
 __device__ __forceinline__ void mainloop(const T* __restrict__ A, const T* __restrict__ B, int64_t lda, int64_t ldb,
                                          int M, int N, int K, int m0, int n0, char* smem,
-                                         f32x16 (&acc)[WM / 32][WN / 32]) {
+                                         f32x16 (&acc)[WM / 32][WN / 32], int64_t b_lo = 0) {
   constexpr int VEC = Mf<T>::VEC;
   constexpr int BKE = ROW_BYTES / (int)sizeof(T);
   constexpr int NWN = BN / WN;
   constexpr int FM = WM / 32, FN = WN / 32;
   constexpr int AV = BM * ROWV / THREADS;
   constexpr int BV = BN * ROWV / THREADS;
-  constexpr int STAGE = (BM + BN) * LDS_ROW;
+  constexpr int STAGE = stage_bytes<BM, BN, SB>();
+  constexpr int NBV = SB ? 2 * BV : BV;  // B vectors per thread per stage (both planes)
   static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
   static_assert(AV >= 1 && BV >= 1, "tile too small");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / NWN, wn = wave % NWN;
 
-  // per-thread global source rows (clamped into range)
-  const T* arow[AV];
-  const T* brow[BV];
+  // per-thread source rows (clamped into range) as 32-bit byte offsets from the tile's first
+  // row, so that the loads take a uniform 64-bit base plus one VGPR each
+  const char* At = (const char*)(A + (int64_t)m0 * lda);
+  const char* Bt = (const char*)(B + (int64_t)n0 * ldb);
+  const char* Blo = Bt + b_lo * (int64_t)sizeof(T);
+  uint32_t aoff[AV], boff[BV];
 #pragma unroll
   for (int i = 0; i < AV; ++i) {
     const int r = (tid + i * THREADS) / ROWV;
-    const int gr = min(m0 + r, M - 1);
-    arow[i] = A + (int64_t)gr * lda + ((tid + i * THREADS) % ROWV) * VEC;
+    const int gr = min(m0 + r, M - 1) - m0;
+    aoff[i] = (uint32_t)((gr * (int64_t)lda + ((tid + i * THREADS) % ROWV) * VEC) * (int64_t)sizeof(T));
   }
 #pragma unroll
   for (int i = 0; i < BV; ++i) {
     const int r = (tid + i * THREADS) / ROWV;
-    const int gr = min(n0 + r, N - 1);
-    brow[i] = B + (int64_t)gr * ldb + ((tid + i * THREADS) % ROWV) * VEC;
+    const int gr = min(n0 + r, N - 1) - n0;
+    boff[i] = (uint32_t)((gr * (int64_t)ldb + ((tid + i * THREADS) % ROWV) * VEC) * (int64_t)sizeof(T));
   }
   const int kvec = (tid % ROWV) * VEC;  // same for every i since THREADS % ROWV == 0
 
-  u32x4 ra[AV], rb[BV];
+  u32x4 ra[AV], rb[NBV];
   auto gload = [&](int kt) {
     const int k = kt * BKE + kvec;
     const bool ok = k < K;
+    const uint32_t ko = (uint32_t)kt * ROW_BYTES;  // kept 32-bit: base + zext(offset) loads
 #pragma unroll
     for (int i = 0; i < AV; ++i) {
-      ra[i] = ok ? *(const u32x4*)(arow[i] + (int64_t)kt * BKE) : u32x4{0u, 0u, 0u, 0u};
+      ra[i] = ok ? *(const u32x4*)(At + (aoff[i] + ko)) : u32x4{0u, 0u, 0u, 0u};
     }
 #pragma unroll
-    for (int i = 0; i < BV; ++i) {
-      rb[i] = ok ? *(const u32x4*)(brow[i] + (int64_t)kt * BKE) : u32x4{0u, 0u, 0u, 0u};
+    for (int i = 0; i < NBV; ++i) {
+      const char* Bp = i >= BV ? Blo : Bt;
+      rb[i] = ok ? *(const u32x4*)(Bp + (boff[i % BV] + ko)) : u32x4{0u, 0u, 0u, 0u};
     }
   };
   auto sstore = [&](int buf) {
@@ -130,9 +150,10 @@ __device__ __forceinline__ void mainloop(const T* __restrict__ A, const T* __res
       *(u32x4*)(base + (v / ROWV) * LDS_ROW + (v % ROWV) * 16) = ra[i];
     }
 #pragma unroll
-    for (int i = 0; i < BV; ++i) {
-      const int v = tid + i * THREADS;
-      *(u32x4*)(base + (BM + v / ROWV) * LDS_ROW + (v % ROWV) * 16) = rb[i];
+    for (int i = 0; i < NBV; ++i) {
+      // lo plane rows follow the BN hi rows
+      const int v = tid + (i % BV) * THREADS;
+      *(u32x4*)(base + (BM + (i / BV) * BN + v / ROWV) * LDS_ROW + (v % ROWV) * 16) = rb[i];
     }
   };
 
@@ -167,6 +188,15 @@ __device__ __forceinline__ void mainloop(const T* __restrict__ A, const T* __res
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = Mf<T>::mma(fa[i], fb[j], acc[i][j]);
+      if (SB) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          fb[j] = *(const u32x4*)(base + (BM + BN + wn * WN + j * 32 + frow) * LDS_ROW + ks * 32 + fhalf);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[i][j] = Mf<T>::mma(fa[i], fb[j], acc[i][j]);
+      }
     }
     if (NBUF == 2) {
       if (kt + 1 < nk) sstore(buf ^ 1);

@@ -494,8 +494,9 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
 // copy holds 128 rows per particle, rows >= H zero), then applies bias and activation in
 // registers and runs the output-layer steps (head_tile) on four 64-sample passes straight
 // from the accumulators.  The hidden activations never reach HBM, and there is one launch
-// per chunk instead of two.  Split operands: X . [w_hi | w_lo] over K = 2 ldw, and the
-// activations are split into hi/lo when they are written to LDS.
+// per chunk instead of two.  Split operands: each staged X slice feeds one MFMA against
+// the w_hi tile and one against the w_lo tile (the weight copy holds rows [w_hi | w_lo]),
+// and the activations are split into hi/lo when they are written to LDS.
 template <int ACT>
 __device__ __forceinline__ float fused_act(float v) {
   if constexpr (ACT == ACT_RELU) return fmaxf(v, 0.0f);
@@ -503,7 +504,6 @@ __device__ __forceinline__ float fused_act(float v) {
 }
 
 constexpr int FBM = 256, FBN = 128;  // tile: samples x (one particle's padded units)
-constexpr int FSTAGE = (FBM + FBN) * gcore::LDS_ROW;
 
 template <int MODE, bool SPL, int ACT>
 __global__ __launch_bounds__(HTHREADS, 2) void fwd_head_kernel(const GemmParams p, const HeadArgs a,
@@ -515,8 +515,9 @@ __global__ __launch_bounds__(HTHREADS, 2) void fwd_head_kernel(const GemmParams 
   gcore::tile_order((p.M + FBM - 1) / FBM, a.J, blockIdx.x, tm, jp);
   const int m0 = tm * FBM;
   f32x16 acc[FM][FN];
-  gcore::mainloop<T, FBM, FBN, WM, WN, 1>((const T*)p.A, (const T*)p.B, p.lda, p.ldb, p.M, a.J * FBN, p.K, m0,
-                                          jp * FBN, fsm, acc);
+  // split: K = ldw over X (first half of its rows), B lo plane ldw elements after each row
+  gcore::mainloop<T, FBM, FBN, WM, WN, 1, SPL>((const T*)p.A, (const T*)p.B, p.lda, p.ldb, p.M, a.J * FBN, p.K, m0,
+                                               jp * FBN, fsm, acc, SPL ? (int64_t)p.K : 0);
 
   // the main loop ended with a barrier: its LDS stage is free for the output-layer work
   const HeadSmem<T> S = head_smem<T>(fsm, Lo);
@@ -639,10 +640,13 @@ hipError_t fwd_head_run(const GemmParams& p, const HeadArgs& a, int mode, int sp
   if (p.M <= 0) return hipSuccess;
   if (!fwd_head_supported(a.H, a.C) || (act != ACT_RELU && act != ACT_TANH)) return hipErrorInvalidValue;
   if (p.K % 8 || p.lda % 8 || p.ldb % 8 || ((uintptr_t)p.A | (uintptr_t)p.B) & 15) return hipErrorInvalidValue;
+  if (split && p.ldb < 2 * p.K) return hipErrorInvalidValue;  // rows [w_hi | w_lo]
+  if (!gcore::tile_offsets_fit(p.lda, p.ldb, 2)) return hipErrorInvalidValue;
   const int nM = (p.M + FBM - 1) / FBM;
   if (a.nsplit != nM) return hipErrorInvalidValue;  // one partial per 256-sample tile
   const HeadLayout L = pick_layout<__bf16>(a.H, split != 0);
-  const size_t smem = (size_t)std::max(FSTAGE, L.total);
+  const int stage = split ? gcore::stage_bytes<FBM, FBN, true>() : gcore::stage_bytes<FBM, FBN, false>();
+  const size_t smem = (size_t)std::max(stage, L.total);
   const dim3 grid((unsigned)(nM * a.J));
 #define FH_LAUNCH(MODE, SPL, ACT) hipLaunchKernelGGL((fwd_head_kernel<MODE, SPL, ACT>), grid, dim3(HTHREADS), smem, s, p, a, L)
 #define FH_ACT(MODE, SPL)                                      \

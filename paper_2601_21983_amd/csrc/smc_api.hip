@@ -876,9 +876,9 @@ void fused_chunk(smc_t h, const void* Xop, int64_t c0, int mcv, int mode, HeadAr
   p.A = (const char*)Xop + c0 * h->xld * (int64_t)h->esz;
   p.lda = h->xld;
   p.M = rows;
-  p.K = h->net.ldw[0] * (h->split ? 2 : 1);  // split: [x | x] . [w_hi | w_lo]
+  p.K = h->net.ldw[0];  // split: the kernel adds the w_lo plane (second half of each weight row)
   p.B = h->net.w[0];
-  p.ldb = p.K;
+  p.ldb = h->net.ldw[0] * (h->split ? 2 : 1);
   p.bias = h->net.bias[0];
   a.m_valid = mcv;
   a.c0 = c0;
