@@ -85,6 +85,15 @@ __device__ __forceinline__ typename V4<T>::type gather4(const T* p, int stride) 
   }
   return v;
 }
+// two BF16 values as one 32-bit word, x in the low half
+__device__ __forceinline__ uint32_t pack2(__bf16 x, __bf16 y) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+}
+template <typename T>
+__device__ __forceinline__ float v4_at(const typename V4<T>::type& v, int t) {
+  if constexpr (sizeof(T) == 2) return from_bf16(__builtin_bit_cast(__bf16, (short)v[t]));
+  else return v[t];
+}
 template <typename T>
 __device__ __forceinline__ typename V4<T>::type pack4(const float* x) {
   typename V4<T>::type v;
@@ -275,11 +284,17 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
         f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
         if (SPL) v = mma16(ld4(WtLo + (hb * 16 + cl) * WT + 4 * g), bd, v);
         v = mma16(ld4(Wt + (hb * 16 + cl) * WT + 4 * g), bd, v);
+        // activations of sample sl at units hb*16 + 4g .. +3, one vector read per plane; the
+        // ReLU derivative needs only the hi plane (a value and its BF16 rounding share a sign)
+        const typename V4<T>::type ah = ld4(As + sl * AS + hb * 16 + 4 * g);
+        const bool need_lo = alo && a.act != ACT_RELU;
+        typename V4<T>::type al = ah;
+        if (need_lo) al = ld4(AsLo + sl * AS + hb * 16 + 4 * g);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int h = hb * 16 + 4 * g + i;
           if (h < H) {
-            const float av = cvt_in<T>(As[sl * AS + h]) + (alo ? cvt_in<T>(AsLo[sl * AS + h]) : 0.0f);
+            const float av = v4_at<T>(ah, i) + (need_lo ? v4_at<T>(al, i) : 0.0f);
             const float dv = v[i] * act_grad_from_out(av, a.act);
             if (Lo.stage) St[h * SS + sl] = cvt_out<T>(dv);
             else ((T*)a.dT)[(int64_t)j * a.sdTj + (int64_t)h * a.sdTh + sg] = cvt_out<T>(dv);
@@ -387,9 +402,6 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
   // packed BF16 values.
   typedef typename std::conditional<SPL, u32x4, u32x2>::type PreT;
   PreT pre[PF];
-  auto pack2 = [](__bf16 x, __bf16 y) -> uint32_t {
-    return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
-  };
   auto ld_chunk = [&](int tile, int s, int c) -> PreT {
     PreT v{};
     if constexpr (SPL) {
@@ -534,20 +546,30 @@ __global__ __launch_bounds__(HTHREADS, 2) void fwd_head_kernel(const GemmParams 
   for (int q = 0; q < 4; ++q) {
     // samples m0 + 64q .. +63 sit in accumulator blocks 2(q&1), 2(q&1)+1 of the waves with wm = q/2
     if (wm == (q >> 1)) {
+      // lane pairs (units u, u+1) trade one value per row pair (r, r+1) over DPP, so that
+      // the even lane writes row r and the odd lane row r+1, each as one 4-byte store
+      const bool odd = lane & 1;
 #pragma unroll
       for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
         for (int jj = 0; jj < FN; ++jj) {
           const int u = wn * WN + jj * 32 + (lane & 31);
-          if (u >= Hp) continue;
+          if (u >= Hp) continue;  // Hp is a multiple of 16: pairs agree
           const float bias = u < H ? b1[u] : 0.0f;
 #pragma unroll
-          for (int e = 0; e < 16; ++e) {
+          for (int e = 0; e < 16; e += 2) {
             const int r = ii * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-            const float v = u < H ? fused_act<ACT>(acc[2 * (q & 1) + ii][jj][e] + bias) : (u == H ? 1.0f : 0.0f);
-            const T hi = to_bf16(v);
-            S.As[r * AS + u] = hi;
-            if (SPL) S.AsLo[r * AS + u] = to_bf16(v - from_bf16(hi));
+            const f32x16& ac = acc[2 * (q & 1) + ii][jj];
+            const float v0 = u < H ? fused_act<ACT>(ac[e] + bias) : (u == H ? 1.0f : 0.0f);      // row r
+            const float v1 = u < H ? fused_act<ACT>(ac[e + 1] + bias) : (u == H ? 1.0f : 0.0f);  // row r + 1
+            const float recv = __builtin_bit_cast(
+                float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, odd ? v0 : v1), 0xB1, 0xF, 0xF, false));
+            const float c0 = odd ? recv : v0;  // unit u & ~1
+            const float c1 = odd ? v1 : recv;  // unit u | 1
+            const int off = (odd ? r + 1 : r) * AS + (u & ~1);
+            const __bf16 h0 = to_bf16(c0), h1 = to_bf16(c1);
+            *(uint32_t*)(S.As + off) = pack2(h0, h1);
+            if (SPL) *(uint32_t*)(S.AsLo + off) = pack2(to_bf16(c0 - from_bf16(h0)), to_bf16(c1 - from_bf16(h1)));
           }
         }
     }

@@ -105,6 +105,8 @@ NET_CASES = [
     ([784, 100, 10], "relu", "categorical", 24, 1000, "bf16x3", 24 * 100 * 2 * 3 * 256),
     ([2, 16, 2], "tanh", "categorical", 64, 1000, "bf16x3", 0),
     ([5, 1], "relu", "gaussian", 33, 999, "bf16x3", 0),
+    ([784, 100, 10], "tanh", "categorical", 24, 1000, "bf16", 0),
+    ([784, 100, 10], "tanh", "categorical", 24, 1000, "bf16x3", 24 * 100 * 2 * 3 * 256),
 ]
 
 
