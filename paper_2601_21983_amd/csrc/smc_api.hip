@@ -1152,6 +1152,9 @@ smc_status guard(void (*body)(void*), void* ctx) {
   } catch (const std::bad_alloc&) {
     g_last_error = "host allocation failed";
     return SMC_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = std::string("C++ exception: ") + e.what();
+    return SMC_ERR_DEVICE;
   } catch (...) {
     g_last_error = "unexpected C++ exception";
     return SMC_ERR_DEVICE;
