@@ -9,8 +9,11 @@ and the lines before it).
 Readings: the update without new data is Eq. beta_initial_data_k and the
 update after a mini-batch was appended is Eq. beta_annealed_k; if an update
 would not increase beta the sign of dS is flipped (equivalently the magnitude
-of the step is used); beta is clipped to 1, and after it reaches 1 a new
-mini-batch is appended and beta restarts at 0.1.
+of the step is used); beta is clipped to 1, and after an iteration whose
+target had beta = 1 a new mini-batch is appended and beta restarts at 0.1.
+The initial phase tempers the first C samples (Eq. sda_initial_target): it is
+the two-segment target with nothing fully annealed in (Omega = 0).  Once every
+sample is annealed in and beta = 1 the target stays the full posterior.
 """
 from __future__ import annotations
 
@@ -37,3 +40,22 @@ def next_beta(beta, w, omega, omega_hat, annealed: bool, dS: float = 1.0):
     if not np.isfinite(step) or step <= 0.0:
         step = abs(dS / denom) if np.isfinite(denom) and denom != 0.0 else 1.0
     return min(1.0, beta + step)
+
+
+def next_target(state, w, ll, ll_b, N, kappa, beta0=0.1, dS=1.0):
+    """The SDA target after the iteration run at state = (m, split, beta).
+
+    The target is p(y[0:split] | theta) p(y[split:m] | theta)^beta q0(theta); ll and
+    ll_b are the particles' log-likelihoods on [0, m) and [split, m) at the current
+    state and w their normalised weights.  Returns the next (m, split, beta).
+    """
+    m, split, beta = int(state[0]), int(state[1]), float(state[2])
+    if beta >= 1.0:
+        if m >= N:
+            return m, split, 1.0
+        return min(m + int(kappa), int(N)), m, float(beta0)
+    ll = np.asarray(ll, dtype=np.float64)
+    ll_b = np.asarray(ll_b, dtype=np.float64)
+    omega_hat = -ll_b
+    omega = -(ll - ll_b)
+    return m, split, next_beta(beta, w, omega, omega_hat, annealed=split > 0, dS=dS)

@@ -172,10 +172,34 @@ class Sampler:
     def log_target(self, ll, theta, lam):
         return lam * ll - np.sum(theta * theta, axis=1) / (2.0 * self.prior_std ** 2)
 
+    # ---- two-segment target (smooth data annealing, Section 3.1):
+    #      log pi(theta) = lam_a LL[0, split) + lam_b LL[split, m) + log q0(theta)
+    def _segment(self, theta, lo, hi, lam):
+        """(LL on samples [lo, hi) [J], lam * its gradient [J x D]); zeros when the range is empty."""
+        J = theta.shape[0]
+        if hi <= lo:
+            return np.zeros(J), np.zeros_like(theta)
+        sc = np.full(J, lam)
+        if self.model is not None:
+            return self.model.loglik_grad(theta, self.X[lo:hi], self.y[lo:hi], sc)
+        return mlp.loglik_grad(theta, self.X[lo:hi], self.y[lo:hi], self.widths, self.act,
+                               self.likelihood, self.noise_std, scale=sc)
+
+    def segment_loglik_grad(self, theta, m, split, lam_a, lam_b):
+        """(LL on the first m samples [J], LL on samples [split, m) [J], grad log pi(theta) [J x D])."""
+        split = min(int(split), int(m))
+        ll_a, g_a = self._segment(theta, 0, split, lam_a)
+        ll_b, g_b = self._segment(theta, split, int(m), lam_b)
+        return ll_a + ll_b, ll_b, g_a + g_b - theta / self.prior_std ** 2
+
+    def segment_log_target(self, ll, ll_b, theta, lam_a, lam_b):
+        return lam_a * (ll - ll_b) + lam_b * ll_b - np.sum(theta * theta, axis=1) / (2.0 * self.prior_std ** 2)
+
     # ---- Eq. init_weight
     def init(self, theta0, m0, lam0):
         self.theta = np.asarray(theta0, dtype=np.float64).copy()
         self.m, self.lam = int(m0), float(lam0)
+        self.tgt = None
         ll, g = self.loglik_grad(self.theta, self.m, self.lam)
         self.ll, self.g = ll, g
         self.lp = self.log_target(ll, self.theta, self.lam)
@@ -209,8 +233,8 @@ class Sampler:
         m, lam = int(m), float(lam)
         if m < self.m:
             raise ValueError("the annealed subset only grows")
-        if (m, lam) != (self.m, self.lam):
-            self.m, self.lam = m, lam
+        if (m, lam) != (self.m, self.lam) or self.tgt is not None:
+            self.m, self.lam, self.tgt = m, lam, None
             _, self.g = self.loglik_grad(self.theta, m, lam)
         P = np.asarray(xi, dtype=np.float64).copy()
         kinetic0 = 0.5 * np.sum(P * P, axis=1)
@@ -222,6 +246,39 @@ class Sampler:
         logw = self.logw + incr
         logw = np.where(np.isfinite(incr) & np.isfinite(ll), logw, -np.inf)
         self.theta, self.g, self.ll, self.lp = theta, g, ll, lp_new
+        self.kinetic = (kinetic0, kinetic1)
+        self._finish_reweight(logw, self.logw)
+        return self
+
+    def step_tempered(self, m, split, lam_a, lam_b, xi):
+        """step() for the two-segment target: samples [0, split) weigh lam_a, samples
+        [split, m) weigh lam_b (a split at or beyond m is the one-segment target with lam_a).
+        Keeps the second segment's log-likelihood at the new state in ll_b."""
+        m = int(m)
+        split = min(int(split), m)
+        lam_a = float(lam_a)
+        lam_b = float(lam_b) if split < m else lam_a
+        if m < self.m:
+            raise ValueError("the annealed subset only grows")
+        tgt = (m, split, lam_a, lam_b)
+        if tgt != self.tgt:
+            self.m, self.lam, self.tgt = m, None, tgt
+            _, _, self.g = self.segment_loglik_grad(self.theta, *tgt)
+        P = np.asarray(xi, dtype=np.float64).copy()
+        kinetic0 = 0.5 * np.sum(P * P, axis=1)
+        theta, g = self.theta, self.g
+        for _ in range(self.S):
+            P = P + 0.5 * self.h * g
+            theta = theta + self.h * P
+            ll, ll_b, g = self.segment_loglik_grad(theta, *tgt)
+            P = P + 0.5 * self.h * g
+        kinetic1 = 0.5 * np.sum(P * P, axis=1)
+        lp_new = self.segment_log_target(ll, ll_b, theta, lam_a, lam_b)
+        incr = lp_new - self.lp - kinetic1 + kinetic0
+        self.last_increment = incr
+        logw = self.logw + incr
+        logw = np.where(np.isfinite(incr) & np.isfinite(ll), logw, -np.inf)
+        self.theta, self.g, self.ll, self.ll_b, self.lp = theta, g, ll, ll_b, lp_new
         self.kinetic = (kinetic0, kinetic1)
         self._finish_reweight(logw, self.logw)
         return self
@@ -239,6 +296,8 @@ class Sampler:
         self.theta = self.theta[p]
         self.g = self.g[p]
         self.ll = self.ll[p]
+        if getattr(self, "ll_b", None) is not None:
+            self.ll_b = self.ll_b[p]
         self.lp = self.lp[p]
         self.logw = np.full(J, -math.log(J))
         self.ess = float(J)
