@@ -158,6 +158,33 @@ SMC_API void smc_destroy(smc_t h);
 SMC_API smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info);
 
 /*
+ * smc_step for a two-segment target (smooth data annealing, Section 3.1, Eq.
+ * sda_initial_target and the annealed target after a mini-batch was appended):
+ *   log pi(theta) = lambda_a LL[0, m_split) + lambda_b LL[m_split, m_k) + log q0(theta),
+ * where LL[a, b) is the unscaled log-likelihood of samples a..b-1.  SDA's
+ * initial phase is m_split = 0, lambda_b = beta; after an append it is
+ * m_split = M_{k-1}, lambda_a = 1, lambda_b = beta.  m_split >= m_k is the
+ * one-segment target of smc_step (lambda_b ignored).  The move, weight
+ * update (against the cached target of the previous iteration) and ESS are
+ * those of smc_step; the second segment's log-likelihood at the new particles
+ * is kept for smc_segment_moments.  Errors as smc_step, plus SMC_ERR_ARG for
+ * m_split < 0 or lambda_b not finite and > 0.
+ */
+SMC_API smc_status smc_step_tempered(smc_t h, int64_t m_k, int64_t m_split, double lambda_a, double lambda_b,
+                                     smc_step_info* info);
+
+/*
+ * Weighted moments of the segment log-likelihoods of the last target at the
+ * current particles (Section 3.1, the moment equations ending in Eq. E{XY}):
+ * with Omega^ = -LL[m_split, m) and Omega = -LL[0, m_split), under the
+ * normalised weights, out4 (host, 4 doubles) receives
+ *   { E[Omega^], Var(Omega^), E[Omega], Cov(Omega, Omega^) },
+ * variance and covariance as E[XY] - E[X]E[Y] in FP64; particles of zero weight
+ * do not enter.  With a one-segment target Omega^ is 0.  Synchronises the stream.
+ */
+SMC_API smc_status smc_segment_moments(smc_t h, double* out4);
+
+/*
  * Systematic resampling (Section 2 resamples when J_eff < J/2).
  *   mode      SMC_RESAMPLE_IF_NEEDED (decided on the device: ESS < ess_frac*J),
  *             SMC_RESAMPLE_ALWAYS or SMC_RESAMPLE_NEVER.

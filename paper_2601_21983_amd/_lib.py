@@ -78,6 +78,8 @@ _SIGS = {
     "smc_init": (_i32, [C.POINTER(smc_config), _vp, _vp, _i64, _vp, _i64, _d, _vp, C.POINTER(_handle)]),
     "smc_destroy": (None, [_handle]),
     "smc_step": (_i32, [_handle, _i64, _d, C.POINTER(smc_step_info)]),
+    "smc_step_tempered": (_i32, [_handle, _i64, _i64, _d, _d, C.POINTER(smc_step_info)]),
+    "smc_segment_moments": (_i32, [_handle, C.POINTER(_d)]),
     "smc_resample": (_i32, [_handle, _i32, C.POINTER(_d), C.POINTER(_i32), C.POINTER(_i32)]),
     "smc_posterior_predict": (_i32, [_handle, _vp, _vp, _i64, _vp, C.POINTER(_d), C.POINTER(_d)]),
     "smc_posterior_mean": (_i32, [_handle, _vp]),
@@ -148,6 +150,20 @@ def smc_step(h, m_k: int, lambda_k: float, want_info: bool = True):
     info = smc_step_info()
     _check(lib.smc_step(h, m_k, lambda_k, C.byref(info) if want_info else None), "smc_step")
     return info if want_info else None
+
+
+def smc_step_tempered(h, m_k: int, m_split: int, lambda_a: float, lambda_b: float, want_info: bool = True):
+    info = smc_step_info()
+    _check(lib.smc_step_tempered(h, m_k, m_split, lambda_a, lambda_b, C.byref(info) if want_info else None),
+           "smc_step_tempered")
+    return info if want_info else None
+
+
+def smc_segment_moments(h):
+    """(E[Omega^], Var(Omega^), E[Omega], Cov(Omega, Omega^))."""
+    out = (C.c_double * 4)()
+    _check(lib.smc_segment_moments(h, out), "smc_segment_moments")
+    return tuple(out)
 
 
 def smc_resample(h, mode: int, u=None, want_result: bool = False, want_ancestors: bool = False, J: int = 0):

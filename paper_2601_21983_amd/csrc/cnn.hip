@@ -150,11 +150,12 @@ __global__ void pool_kernel(const T* __restrict__ act2, int64_t sA, int mcv, Cnn
 // (zero for ncls <= c < 16); PREDICT writes log-probabilities instead.
 template <typename T>
 __global__ __launch_bounds__(256) void cnn_ll_kernel(const CnnLLArgs a) {
-  __shared__ double red[4];
+  __shared__ double red[8];
   const int j = blockIdx.x;
   const float lam = a.scale ? (float)a.scale[j] : (float)a.lambda;
+  const float lam_b = a.scale ? lam : (float)a.lambda_b;
   const float* b3 = a.bias + (int64_t)j * a.ncls;
-  double acc = 0.0;
+  double acc = 0.0, acc_b = 0.0;
   for (int n = threadIdx.x; n < a.mcv; n += blockDim.x) {
     const float* z = a.logits + ((int64_t)j * a.mc + n) * a.ncls;
     float zz[16];
@@ -180,22 +181,33 @@ __global__ __launch_bounds__(256) void cnn_ll_kernel(const CnnLLArgs a) {
 #pragma unroll
     for (int c = 0; c < 16; ++c)
       if (c == y) zy = zz[c];
+    const bool segb = a.c0 + n >= a.m_split;  // second segment of a two-segment target
     acc += (double)(zy - lse);
+    if (segb) acc_b += (double)(zy - lse);
+    const float lm = segb ? lam_b : lam;
     if (a.mode == HEAD_TRAIN) {
       T* d = (T*)a.d3 + ((int64_t)j * a.mc + n) * 16;
 #pragma unroll
       for (int c = 0; c < 16; ++c)
-        d[c] = cvt_out<T>(c < a.ncls ? lam * ((c == y ? 1.0f : 0.0f) - expf(zz[c] - lse)) : 0.0f);
+        d[c] = cvt_out<T>(c < a.ncls ? lm * ((c == y ? 1.0f : 0.0f) - expf(zz[c] - lse)) : 0.0f);
     }
   }
   if (a.mode == HEAD_PREDICT) return;
   const double v = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  const double vb = wave_sum(acc_b);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = v;
+    red[4 + (threadIdx.x >> 6)] = vb;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
+    double s = 0.0, sb = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+      s += red[q];
+      sb += red[4 + q];
+    }
     a.ll_acc[j] = a.beta ? a.ll_acc[j] + s : s;
+    if (a.ll_acc_b) a.ll_acc_b[j] = a.beta ? a.ll_acc_b[j] + sb : sb;
   }
 }
 

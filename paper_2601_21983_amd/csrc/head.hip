@@ -204,7 +204,8 @@ __device__ __forceinline__ void head_weights(const HeadArgs& a, const HeadLayout
 // (within the chunk) is s0.  Every thread of the workgroup calls it (it synchronises).
 template <typename T, int MODE, int NQ, bool SPL>
 __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& Lo, const HeadSmem<T>& S, int j, int s0,
-                                          float lam, bool alo, double& llacc, f32x4 (&dacc)[NQ]) {
+                                          float lam, float lam_b, bool alo, double& llacc, double& llacc_b,
+                                          f32x4 (&dacc)[NQ]) {
   T *Wc = S.Wc, *Wt = S.Wt, *As = S.As, *WcLo = S.WcLo, *WtLo = S.WtLo, *AsLo = S.AsLo, *Dt = S.Dt, *St = S.St;
   const int H = a.H, C = a.C, Hp = Lo.Hp, AS = Lo.AS, WT = Lo.WT, DS = Lo.DS, SS = Lo.SS;
   const int NHB = Hp / 16;
@@ -231,6 +232,8 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
   const int sl = w * 16 + cl;           // sample within the tile
   const int sg = s0 + sl;               // sample within the chunk
   const bool valid = sg < a.m_valid;
+  const bool segb = a.c0 + sg >= a.m_split;  // second segment of a two-segment target
+  const float lm = segb ? lam_b : lam;
   float d[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   if (a.likelihood == 0) {
     float zz[4];
@@ -260,8 +263,11 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int c = 4 * g + i;
-        if (c == y) llacc += (double)(zz[i] - lse);
-        if (MODE == HEAD_TRAIN && valid && c < C) d[i] = lam * ((c == y ? 1.0f : 0.0f) - expf(zz[i] - lse));
+        if (c == y) {
+          llacc += (double)(zz[i] - lse);
+          if (segb) llacc_b += (double)(zz[i] - lse);
+        }
+        if (MODE == HEAD_TRAIN && valid && c < C) d[i] = lm * ((c == y ? 1.0f : 0.0f) - expf(zz[i] - lse));
       }
     }
   } else {
@@ -271,8 +277,10 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
     if (MODE == HEAD_PREDICT) {
       if (valid && g == 0) a.logp[(int64_t)j * a.ld_logp + a.c0 + sg] = z[0];
     } else if (g == 0 && valid) {
-      llacc += (double)(a.gauss_c - 0.5f * r * r * a.inv_var);
-      if (MODE == HEAD_TRAIN) d[0] = lam * r * a.inv_var;
+      const double l = (double)(a.gauss_c - 0.5f * r * r * a.inv_var);
+      llacc += l;
+      if (segb) llacc_b += l;
+      if (MODE == HEAD_TRAIN) d[0] = lm * r * a.inv_var;
     }
   }
 
@@ -335,7 +343,7 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
 // The workgroup's log-likelihood partial and output-layer gradient partial (slot `split`).
 template <typename T, int MODE, int NQ>
 __device__ __forceinline__ void head_finish(const HeadArgs& a, const HeadLayout& Lo, const HeadSmem<T>& S, int j,
-                                            int split, double llacc, const f32x4 (&dacc)[NQ]) {
+                                            int split, double llacc, double llacc_b, const f32x4 (&dacc)[NQ]) {
   double* red = S.red;
   const int H = a.H, C = a.C;
   const int NHB = Lo.Hp / 16;
@@ -343,10 +351,17 @@ __device__ __forceinline__ void head_finish(const HeadArgs& a, const HeadLayout&
   const int g = lane >> 4, cl = lane & 15;
   if (MODE != HEAD_PREDICT) {
     const double v = wave_sum(llacc);
+    const double vb = a.llpart_b ? wave_sum(llacc_b) : 0.0;
     __syncthreads();
-    if (lane == 0) red[w] = v;
+    if (lane == 0) {
+      red[w] = v;
+      red[4 + w] = vb;
+    }
     __syncthreads();
-    if (tid == 0) a.llpart[(int64_t)j * a.nsplit + split] = red[0] + red[1] + red[2] + red[3];
+    if (tid == 0) {
+      a.llpart[(int64_t)j * a.nsplit + split] = red[0] + red[1] + red[2] + red[3];
+      if (a.llpart_b) a.llpart_b[(int64_t)j * a.nsplit + split] = red[4] + red[5] + red[6] + red[7];
+    }
   }
   if (MODE == HEAD_TRAIN) {
     const int npair = C * (H + 1);
@@ -384,6 +399,7 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
   }
 
   const float lam = a.scale ? (float)a.scale[j] : (float)a.lambda;
+  const float lam_b = a.scale ? lam : (float)a.lambda_b;
   const T* Aj = (const T*)a.A + (int64_t)j * a.sAj;
   const float* Afj = (const float*)a.A + (int64_t)j * a.sAj;  // FP32 activations (alo)
   const int ntiles = (a.m_valid + HT - 1) / HT;
@@ -484,7 +500,7 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
     }
   };
 
-  double llacc = 0.0;
+  double llacc = 0.0, llacc_b = 0.0;
   f32x4 dacc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) dacc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -495,9 +511,9 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
     stage(t);
     __syncthreads();
     if (t + 1 < t1) prefetch(t + 1);
-    head_tile<T, MODE, NQ, SPL>(a, Lo, S, j, t * HT, lam, alo, llacc, dacc);
+    head_tile<T, MODE, NQ, SPL>(a, Lo, S, j, t * HT, lam, lam_b, alo, llacc, llacc_b, dacc);
   }
-  head_finish<T, MODE, NQ>(a, Lo, S, j, split, llacc, dacc);
+  head_finish<T, MODE, NQ>(a, Lo, S, j, split, llacc, llacc_b, dacc);
 }
 
 // ------------------------------------------------------------------ fused layer 1 + output layer
@@ -537,8 +553,9 @@ __global__ __launch_bounds__(HTHREADS, 2) void fwd_head_kernel(const GemmParams 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
   const int H = a.H, Hp = Lo.Hp, AS = Lo.AS;
   const float lam = a.scale ? (float)a.scale[jp] : (float)a.lambda;
+  const float lam_b = a.scale ? lam : (float)a.lambda_b;
   const float* b1 = p.bias + (int64_t)jp * H;
-  double llacc = 0.0;
+  double llacc = 0.0, llacc_b = 0.0;
   f32x4 dacc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) dacc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -574,10 +591,10 @@ __global__ __launch_bounds__(HTHREADS, 2) void fwd_head_kernel(const GemmParams 
         }
     }
     __syncthreads();
-    head_tile<T, MODE, NQ, SPL>(a, Lo, S, jp, m0 + 64 * q, lam, SPL, llacc, dacc);
+    head_tile<T, MODE, NQ, SPL>(a, Lo, S, jp, m0 + 64 * q, lam, lam_b, SPL, llacc, llacc_b, dacc);
     __syncthreads();
   }
-  head_finish<T, MODE, NQ>(a, Lo, S, jp, tm, llacc, dacc);
+  head_finish<T, MODE, NQ>(a, Lo, S, jp, tm, llacc, llacc_b, dacc);
 }
 
 // Sum the per-split partials of one chunk in a fixed order and fold them into the
@@ -589,6 +606,11 @@ __global__ void head_reduce_kernel(const HeadArgs a, int beta, int with_grad) {
     double s = 0.0;
     for (int k = 0; k < a.nsplit; ++k) s += a.llpart[(int64_t)j * a.nsplit + k];
     a.ll_acc[j] = beta ? a.ll_acc[j] + s : s;
+    if (a.ll_acc_b) {
+      double sb = 0.0;
+      for (int k = 0; k < a.nsplit; ++k) sb += a.llpart_b[(int64_t)j * a.nsplit + k];
+      a.ll_acc_b[j] = beta ? a.ll_acc_b[j] + sb : sb;
+    }
   }
   if (!with_grad) return;
   const float* src = a.dWpart + (int64_t)j * a.nsplit * npair;

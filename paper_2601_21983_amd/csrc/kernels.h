@@ -29,7 +29,13 @@ struct HeadArgs {
   int likelihood = 0;
   float inv_var = 1.0f, gauss_c = 0.0f;
   double lambda = 1.0;
-  const double* scale = nullptr;    // per-particle gradient scale (overrides lambda)
+  const double* scale = nullptr;    // per-particle gradient scale (overrides lambda and lambda_b)
+  // two-segment target: samples with global index >= m_split weigh lambda_b instead of lambda,
+  // and their log-likelihood is also summed on its own (ll_acc_b, through llpart_b)
+  int64_t m_split = INT64_MAX;
+  double lambda_b = 1.0;
+  double* llpart_b = nullptr;       // [J x nsplit]
+  double* ll_acc_b = nullptr;       // [J] or null
   int act = 0;
   void* dT = nullptr;               // delta_{L-1} transposed: dT + j*sdTj + h*sdTh + m
   int64_t sdTj = 0, sdTh = 0;
@@ -71,7 +77,10 @@ struct CnnLLArgs {
   int64_t c0 = 0;
   int mc = 0, mcv = 0, ncls = 0, mode = HEAD_TRAIN, beta = 0;
   double lambda = 1.0;
-  const double* scale = nullptr;  // per-particle gradient scale (overrides lambda)
+  const double* scale = nullptr;  // per-particle gradient scale (overrides lambda and lambda_b)
+  int64_t m_split = INT64_MAX;    // samples from m_split on weigh lambda_b (two-segment target)
+  double lambda_b = 1.0;
+  double* ll_acc_b = nullptr;     // [J] log-likelihood of samples >= m_split, or null
   void* d3 = nullptr;             // [J x mc x 16] operand type
   double* ll_acc = nullptr;       // [J]
   float* logp = nullptr;          // predict: logp[(j*ld_logp + c0 + n)*ncls + c]
@@ -162,6 +171,8 @@ struct WeightArgs {
   double inv_2prior_var = 0.5;
   double ess_frac = 0.5;
   const double* ll = nullptr;    // [J] subset log-likelihood at the new state
+  const double* ll_b = nullptr;  // [J] its second-segment part (two-segment target), or null
+  double lambda_b = 1.0;         // weight of the second segment
   const double* part = nullptr;  // [3][J][nblk]
   const double* extra = nullptr; // [J] extra log-weight term (learned proposal), or null
   const double* tsq = nullptr;   // [J] |theta|^2 when part is null (initial weighting)
@@ -196,6 +207,9 @@ hipError_t gather_rows_run(int J, int64_t D, const int32_t* placement, float* a0
 
 hipError_t normalise_run(const double* logw, int J, double* out, double* stats, hipStream_t s,
                          double* wout = nullptr);
+// {E[Omega^], Var(Omega^), E[Omega], Cov(Omega, Omega^)} with Omega^ = -ll_b, Omega = -(ll - ll_b)
+hipError_t segment_moments_run(const double* w, const double* ll, const double* ll_b, int J, double* out,
+                               hipStream_t s);
 hipError_t systematic_run(const double* w, int J, double u, int32_t* anc, int32_t* placement, hipStream_t s);
 hipError_t philox_run(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t* out,
                       hipStream_t s);

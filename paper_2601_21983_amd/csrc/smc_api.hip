@@ -198,6 +198,13 @@ struct smc_handle {
   bool w_dirty = true;
   int64_t m = 0;
   double lam = 1.0;
+  // two-segment target (smooth data annealing): samples from seg_split on weigh lam_b;
+  // INT64_MAX: one segment.  ll_b holds the second segment's log-likelihood at the
+  // current particles (zero with one segment).
+  int64_t seg_split = INT64_MAX;
+  double lam_b = 1.0;
+  double* ll_b = nullptr;
+  double* llpart_b = nullptr;
   uint64_t rng_iter = 0;
   int64_t grad_evals = 0;
   // learned proposal
@@ -449,6 +456,7 @@ void alloc_all(smc_t h) {
   h->g = dalloc<float>(h->owned, (int64_t)J * D);
   h->P = dalloc<float>(h->owned, (int64_t)J * D);
   h->ll = dalloc<double>(h->owned, J);
+  h->ll_b = dalloc<double>(h->owned, J);
   h->lp = dalloc<double>(h->owned, J);
   h->logw = dalloc<double>(h->owned, J);
   h->w = dalloc<double>(h->owned, J);
@@ -459,6 +467,7 @@ void alloc_all(smc_t h) {
   h->anc = dalloc<int32_t>(h->owned, J);
   h->place = dalloc<int32_t>(h->owned, J);
   HIPCHECK(hipMemsetAsync(h->stats, 0, 16 * sizeof(double), h->stream));
+  HIPCHECK(hipMemsetAsync(h->ll_b, 0, (size_t)J * sizeof(double), h->stream));
   HIPCHECK(hipMemsetAsync(h->part, 0, (size_t)3 * J * h->nblk * sizeof(double), h->stream));
   for (int l = 0; l < h->L; ++l) {
     const int64_t n = (int64_t)J * h->net.rowpad[l] * h->net.ldw[l] * (int64_t)h->esz * (h->split ? 2 : 1);
@@ -503,6 +512,7 @@ void alloc_all(smc_t h) {
   if (h->fused) h->nsplit_max = std::max(h->nsplit_max, (int)((mc + 255) / 256));  // one partial per 256 samples
   const int H = h->net.nin[h->L - 1];
   h->llpart = dalloc<double>(h->owned, (int64_t)J * h->nsplit_max);
+  h->llpart_b = dalloc<double>(h->owned, (int64_t)J * h->nsplit_max);
   h->dWpart = dalloc<float>(h->owned, (int64_t)J * h->nsplit_max * h->C * (H + 1));
 }
 
@@ -735,6 +745,25 @@ void cnn_forward_chunk(smc_t h, const void* Xop, int64_t c0, int mcv) {
   }
 }
 
+// The second segment of a two-segment target for one pass: samples from `split` on weigh
+// lam_b, and their log-likelihood goes to ll_b (when not null).
+struct Seg {
+  int64_t split = INT64_MAX;
+  double lam_b = 1.0;
+  double* ll_b = nullptr;
+};
+
+// the handle's current target (its second-segment log-likelihood into h->ll_b)
+Seg target_seg(smc_t h) { return Seg{h->seg_split, h->lam_b, h->ll_b}; }
+
+// the weight kernel's view of the current target (two segments only when split)
+void set_segment(smc_t h, WeightArgs& wa) {
+  if (h->seg_split != INT64_MAX) {
+    wa.ll_b = h->ll_b;
+    wa.lambda_b = h->lam_b;
+  }
+}
+
 CnnLLArgs cnn_ll_args(smc_t h, int mode, int mcv, int64_t c0) {
   CnnLLArgs a;
   a.logits = h->cb.logits;
@@ -751,7 +780,7 @@ CnnLLArgs cnn_ll_args(smc_t h, int mode, int mcv, int64_t c0) {
 
 // the convolutional network's pass over the subset [0, m); same contract as grad_pass
 void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const double* scale, double* ll_out,
-              float* g_out) {
+              float* g_out, const Seg& seg) {
   CnnBufs& b = h->cb;
   const CnnDims& d = b.d;
   const int J = h->J, bf = h->bf16;
@@ -765,6 +794,9 @@ void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const doubl
     CnnLLArgs la = cnn_ll_args(h, train ? HEAD_TRAIN : HEAD_FORWARD, mcv, c0);
     la.lambda = lambda;
     la.scale = scale;
+    la.m_split = seg.split;
+    la.lambda_b = seg.lam_b;
+    la.ll_acc_b = seg.ll_b;
     la.ll_acc = ll_out;
     la.beta = beta;
     timed(h, SMC_K_HEAD, 0.0, 0.0, [&]() { HIPCHECK(cnn_ll_run(la, J, bf, h->stream)); });
@@ -893,9 +925,9 @@ void fused_chunk(smc_t h, const void* Xop, int64_t c0, int mcv, int mode, HeadAr
 // g_out is given, g_out[j] = scale_j * d LL_j / d theta_j (the lambda-scaled
 // likelihood gradient).  The GEMM copies of `theta` must be current.
 void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const double* scale, double* ll_out,
-               float* g_out) {
+               float* g_out, const Seg& seg = Seg{}) {
   if (h->cnn) {
-    cnn_pass(h, theta, m, lambda, scale, ll_out, g_out);
+    cnn_pass(h, theta, m, lambda, scale, ll_out, g_out, seg);
     return;
   }
   const int J = h->J, L = h->L;
@@ -912,6 +944,12 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
     a.c0 = c0;
     a.lambda = lambda;
     a.scale = scale;
+    a.m_split = seg.split;
+    a.lambda_b = seg.lam_b;
+    if (seg.ll_b) {
+      a.ll_acc_b = seg.ll_b;
+      a.llpart_b = h->llpart_b;
+    }
     a.ll_acc = ll_out;
     a.grad = g_out;
     a.beta = beta;
@@ -1036,6 +1074,7 @@ void initial_weighting(smc_t h) {
   wa.J = h->J;
   wa.init = 1;
   wa.lambda = h->lam;
+  set_segment(h, wa);
   wa.inv_2prior_var = 0.5 / (h->cfg.prior_std * h->cfg.prior_std);
   wa.ess_frac = h->cfg.ess_frac;
   wa.ll = h->ll;
@@ -1218,7 +1257,7 @@ smc_status smc_init(const smc_config* cfg, const float* x_dev, const void* y_dev
     ensure_cast(h);
     h->m = m0;
     h->lam = lambda0;
-    grad_pass(h, h->theta, m0, lambda0, nullptr, h->ll, h->g);
+    grad_pass(h, h->theta, m0, lambda0, nullptr, h->ll, h->g, target_seg(h));
     initial_weighting(h);
     double st8[8];
     read_stats(h, st8);
@@ -1248,19 +1287,30 @@ void smc_destroy(smc_t h) {
 int64_t smc_n_params(smc_t h) { return h ? h->D : -1; }
 int64_t smc_chunk_samples(smc_t h) { return h ? h->mc : -1; }
 
-smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info) {
-  return run([&]() {
+namespace {
+
+// One iteration (move + reweight) targeting lambda_k LL[0, split) + lambda_b LL[split, m_k) + log q0.
+void step_impl(smc_t h, int64_t m_k, int64_t split, double lambda_k, double lambda_b, smc_step_info* info) {
     if (!h) fail(SMC_ERR_ARG, "null handle");
     if (m_k < h->m || m_k > h->n_data) fail(SMC_ERR_ARG, "m_k must satisfy previous m <= m_k <= n_data");
     if (!(lambda_k > 0) || !isfinite(lambda_k)) fail(SMC_ERR_ARG, "lambda_k must be finite and > 0");
+    if (split < 0) fail(SMC_ERR_ARG, "m_split must be >= 0");
+    if (split >= m_k) {
+      split = INT64_MAX;  // one segment
+      lambda_b = lambda_k;
+    } else if (!(lambda_b > 0) || !isfinite(lambda_b)) {
+      fail(SMC_ERR_ARG, "lambda_b must be finite and > 0");
+    }
     if (h->cfg.proposal == SMC_PROPOSAL_LEARNED && !h->pnet) fail(SMC_ERR_STATE, "no proposal network set");
     const int64_t ev0 = h->grad_evals;
     ensure_cast(h);
-    if (m_k != h->m || lambda_k != h->lam) {
-      // the target changed: gradient at the current particles on the new subset
-      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g);
+    if (m_k != h->m || lambda_k != h->lam || split != h->seg_split || lambda_b != h->lam_b) {
+      // the target changed: gradient at the current particles under the new target
       h->m = m_k;
       h->lam = lambda_k;
+      h->seg_split = split;
+      h->lam_b = lambda_b;
+      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g, target_seg(h));
     }
     h->rng_iter += 1;
     h->k_iter += 1;
@@ -1273,7 +1323,7 @@ smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info) 
       timed(h, SMC_K_MOVE, 0.0, nd * (16.0 + h->esz + (la.noise ? 4.0 : 0.0)),
             [&]() { HIPCHECK(learned_move_run(la, h->stream)); });
       h->noise_pending = false;
-      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g);
+      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g, target_seg(h));
       learned_scales(h, h->sc1);
       LearnedMoveArgs lb = learned_args(h, MOVE_LAST, h->sc1);
       timed(h, SMC_K_MOVE, 0.0, nd * 12.0, [&]() { HIPCHECK(learned_move_run(lb, h->stream)); });
@@ -1283,6 +1333,7 @@ smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info) 
       wa.J = h->J;
       wa.nblk = h->nblk;
       wa.lambda = lambda_k;
+      set_segment(h, wa);
       wa.inv_2prior_var = 0.5 / (h->cfg.prior_std * h->cfg.prior_std);
       wa.ess_frac = h->cfg.ess_frac;
       wa.ll = h->ll;
@@ -1306,7 +1357,7 @@ smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info) 
           [&]() { HIPCHECK(move_run(ma, h->stream)); });
     h->noise_pending = false;
     for (int s = 1; s <= S; ++s) {
-      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g);
+      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g, target_seg(h));
       MoveArgs mb = move_args(h, s < S ? MOVE_MID : MOVE_LAST);
       // MID: read theta, g, P; write P, theta, copy.  LAST: read P, g, theta
       timed(h, SMC_K_MOVE, 0.0, nd * (s < S ? 20.0 + h->esz : 12.0), [&]() { HIPCHECK(move_run(mb, h->stream)); });
@@ -1315,6 +1366,7 @@ smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info) 
     wa.J = h->J;
     wa.nblk = h->nblk;
     wa.lambda = lambda_k;
+    set_segment(h, wa);
     wa.inv_2prior_var = 0.5 / (h->cfg.prior_std * h->cfg.prior_std);
     wa.ess_frac = h->cfg.ess_frac;
     wa.ll = h->ll;
@@ -1325,6 +1377,28 @@ smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info) 
     wa.stats = h->stats;
     timed(h, SMC_K_WEIGHT, 0.0, 0.0, [&]() { HIPCHECK(weight_run(wa, h->stream)); });
     if (info) fill_info(h, info, h->grad_evals - ev0);
+}
+
+}  // namespace
+
+smc_status smc_step(smc_t h, int64_t m_k, double lambda_k, smc_step_info* info) {
+  return run([&]() { step_impl(h, m_k, INT64_MAX, lambda_k, lambda_k, info); });
+}
+
+smc_status smc_step_tempered(smc_t h, int64_t m_k, int64_t m_split, double lambda_a, double lambda_b,
+                             smc_step_info* info) {
+  return run([&]() { step_impl(h, m_k, m_split, lambda_a, lambda_b, info); });
+}
+
+smc_status smc_segment_moments(smc_t h, double* out4) {
+  return run([&]() {
+    if (!h || !out4) fail(SMC_ERR_ARG, "handle and out4 are required");
+    double* d = h->stats + 12;  // device slots 12..15
+    HIPCHECK(segment_moments_run(h->w, h->ll, h->ll_b, h->J, d, h->stream));
+    double host[4];
+    HIPCHECK(hipMemcpyAsync(host, d, sizeof(host), hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+    for (int i = 0; i < 4; ++i) out4[i] = host[i];
   });
 }
 
@@ -1354,6 +1428,7 @@ smc_status smc_resample(smc_t h, int32_t mode, const double* u, int32_t* resampl
     ra.placement = h->place;
     ra.sc[0] = h->ll;
     ra.sc[1] = h->lp;
+    ra.sc[2] = h->ll_b;
     timed(h, SMC_K_RESAMPLE, 0.0, 0.0, [&]() {
       HIPCHECK(resample_run(ra, h->stream));
       HIPCHECK(gather_rows_run(h->J, h->D, h->place, h->theta, h->g, h->stream));
@@ -1499,7 +1574,7 @@ smc_status smc_set_state(smc_t h, const float* theta_dev, const double* logw_dev
     h->w_dirty = true;
     h->pm_have = false;
     ensure_cast(h);
-    grad_pass(h, h->theta, h->m, h->lam, nullptr, h->ll, h->g);
+    grad_pass(h, h->theta, h->m, h->lam, nullptr, h->ll, h->g, target_seg(h));
     h->rng_iter = rng_counter;
     // log pi and the initial weights at the restored particles
     initial_weighting(h);
@@ -1578,10 +1653,13 @@ smc_status smc_proposal_targets(smc_t h, int64_t m_k, double lambda_k, const dou
       h->lp0 = dalloc<double>(h->owned, J);
     }
     ensure_cast(h);
-    if (m_k != h->m || lambda_k != h->lam) {
-      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g);
+    if (m_k != h->m || lambda_k != h->lam || h->seg_split != INT64_MAX) {
+      // the trace targets use the one-segment target
       h->m = m_k;
       h->lam = lambda_k;
+      h->seg_split = INT64_MAX;
+      h->lam_b = lambda_k;
+      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g, target_seg(h));
     }
     const float ipv = (float)(1.0 / (h->cfg.prior_std * h->cfg.prior_std));
     const double i2pv = 0.5 / (h->cfg.prior_std * h->cfg.prior_std);

@@ -151,11 +151,13 @@ __global__ __launch_bounds__(1024) void weight_kernel(const WeightArgs a) {
       if (a.no_kinetic) { k0 = 0.0; k1 = 0.0; }
     }
     const double ll = a.ll[j];
-    const double lpn = a.lambda * ll - kt * a.inv_2prior_var;
+    // log-likelihood term of the target: one segment (lambda LL) or two
+    const double llt = a.ll_b ? a.lambda * (ll - a.ll_b[j]) + a.lambda_b * a.ll_b[j] : a.lambda * ll;
+    const double lpn = llt - kt * a.inv_2prior_var;
     double incr;
     double prev;
     if (a.init) {
-      incr = a.lambda * ll;
+      incr = llt;
       prev = 0.0;
     } else {
       incr = lpn - a.lp[j] - 0.5 * k1 + 0.5 * k0 + (a.extra ? a.extra[j] : 0.0);
@@ -562,6 +564,36 @@ __global__ void f64_to_f32_kernel(const double* in, int64_t n, float* out) {
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Weighted moments of the two segments' negative log-likelihoods under the normalised
+// weights w (smooth data annealing, Section 3.1): with Omega^ = -ll_b and Omega = -(ll - ll_b),
+// out = {E[Omega^], Var(Omega^), E[Omega], Cov(Omega, Omega^)}, variance and covariance as
+// E[XY] - E[X] E[Y].  Particles of zero weight do not enter the sums.
+__global__ __launch_bounds__(1024) void segment_moments_kernel(const double* __restrict__ w,
+                                                               const double* __restrict__ ll,
+                                                               const double* __restrict__ ll_b, int J, double* out) {
+  __shared__ double red[16];
+  double eb = 0.0, ebb = 0.0, ea = 0.0, eab = 0.0;
+  for (int j = threadIdx.x; j < J; j += blockDim.x) {
+    const double wj = w[j];
+    if (!(wj > 0.0)) continue;
+    const double b = -ll_b[j], a = -(ll[j] - ll_b[j]);
+    eb += wj * b;
+    ebb += wj * b * b;
+    ea += wj * a;
+    eab += wj * a * b;
+  }
+  eb = block_sum(eb, red);
+  ebb = block_sum(ebb, red);
+  ea = block_sum(ea, red);
+  eab = block_sum(eab, red);
+  if (threadIdx.x == 0) {
+    out[0] = eb;
+    out[1] = ebb - eb * eb;
+    out[2] = ea;
+    out[3] = eab - ea * eb;
+  }
+}
+
 }  // namespace
 
 hipError_t kernels_set_smem_limits() {
@@ -586,6 +618,13 @@ hipError_t move_run(const MoveArgs& a, hipStream_t s) {
 hipError_t weight_run(const WeightArgs& a, hipStream_t s) {
   if (a.J > MAX_J) return hipErrorInvalidValue;
   hipLaunchKernelGGL(weight_kernel, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t segment_moments_run(const double* w, const double* ll, const double* ll_b, int J, double* out,
+                               hipStream_t s) {
+  if (J > MAX_J || J < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(segment_moments_kernel, dim3(1), dim3(1024), 0, s, w, ll, ll_b, J, out);
   return hipGetLastError();
 }
 

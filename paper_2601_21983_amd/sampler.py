@@ -139,6 +139,22 @@ class SMCSampler:
                 "max_loglik": r.max_loglik, "n_nonfinite": r.n_nonfinite,
                 "resample_recommended": bool(r.resample_recommended), "grad_evals": r.grad_evals}
 
+    def step_tempered(self, m: int, m_split: int, lam_a: float, lam_b: float, info: bool = True) -> Optional[dict]:
+        """One iteration targeting lam_a LL[0, m_split) + lam_b LL[m_split, m) + log q0 (smooth data
+        annealing: lam_a = 1, lam_b = beta)."""
+        r = L.smc_step_tempered(self.handle, int(m), int(m_split), float(lam_a), float(lam_b), want_info=info)
+        self.m = int(m)
+        if r is None:
+            return None
+        return {"ess": r.ess, "log_z_increment": r.log_z_increment, "mean_loglik": r.mean_loglik,
+                "max_loglik": r.max_loglik, "n_nonfinite": r.n_nonfinite,
+                "resample_recommended": bool(r.resample_recommended), "grad_evals": r.grad_evals}
+
+    def segment_moments(self) -> dict:
+        """Weighted moments of Omega^ = -LL[m_split, m) and Omega = -LL[0, m_split) at the current particles."""
+        e_b, var_b, e_a, cov = L.smc_segment_moments(self.handle)
+        return {"mean_hat": e_b, "var_hat": var_b, "mean": e_a, "cov": cov}
+
     def resample(self, mode: str = "if_needed", u: Optional[float] = None, want: bool = False):
         res, anc = L.smc_resample(self.handle, _RES[mode], u, want_result=want, want_ancestors=want, J=self.J)
         return (res, anc) if want else None
