@@ -16,7 +16,8 @@ the timed steps) of the headline leg, the split-BF16 sampler (BF16 matrix-core
 operands carried as hi/lo pairs, FP32 accumulation) with the learned
 proposal-scale network; the plain FP32, split-BF16 and plain BF16 samplers,
 time-to-accuracy of each leg, the dominant kernel's roofline fraction and the
-CPU oracle are reported beside it.  The network is trained before any timed
+CPU oracle are reported beside it, with the CIFAR-shaped convolutional workload
+and a smooth-data-annealing run (Section 3.1) of the split-BF16 sampler.  The network is trained before any timed
 region on traces of two plain FP32 runs (its cost is reported separately and
 added to the learned leg's time-to-accuracy in `seconds_with_training`).
 
@@ -63,6 +64,8 @@ def parse():
                     help="comma list of precision[-learned]; the first is the headline")
     ap.add_argument("--no-cnn", action="store_true", help="skip the convolutional-network workload")
     ap.add_argument("--cnn-steps", type=int, default=8)
+    ap.add_argument("--no-sda", action="store_true", help="skip the smooth-data-annealing run")
+    ap.add_argument("--sda-iters", type=int, default=SDA_MAX_ITERS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -284,6 +287,48 @@ def run_cnn(P, steps, seed):
             "host_seconds_incl_schedule": round(dt, 3)}
 
 
+SDA_MAX_ITERS = 600
+SDA_PRIOR = 0.05  # with N(0, 1) the weighted variance of the first batch's negative LL is ~1e5 after the
+                  # first resampling, so the entropy-rate rule with dS = 1 moves beta by ~1e-6 per iteration
+
+
+def run_sda(P, dev, seed, max_iters):
+    """Smooth data annealing (Section 3.1) on the MNIST-shaped workload: the split-BF16 sampler
+    with Langevin moves, C = kappa = 1000, beta_0 = 0.1, dS = 1, run until every sample is
+    annealed in at beta = 1 (or max_iters iterations); the moments come from the device."""
+    import torch
+    from paper_2601_21983_amd.schedules import SDASchedule
+    cfg = P.SMCConfig(widths=WIDTHS, n_particles=J, activation="relu", precision="bf16x3", step_size=STEP,
+                      prior_std=SDA_PRIOR, seed=seed)
+    s = P.SMCSampler(cfg, dev["X"], dev["y"], m0=C0, lambda0=0.1)
+    s.resample()
+    sched = SDASchedule(C0, KAPPA, N_TRAIN, beta0=0.1, dS=1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals, ess, k, appends = 0, [], 0, 0
+    while not sched.done() and k < max_iters:
+        k += 1
+        m, split, beta = sched.target
+        info = s.step_tempered(m, split, 1.0, beta)
+        evals += info["grad_evals"]
+        ess.append(info["ess"])
+        s.resample()
+        appends += sched.next(s)[0] > m
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = s.predict(dev["Xt"], dev["yt"])
+    s.close()
+    betas = [b for _, _, b in sched.history]
+    return {"value": round(evals / dt, 1), "unit": "grad-evals/s", "iterations": k, "seconds": round(dt, 3),
+            "ms_per_step": round(1e3 * dt / max(k, 1), 3), "appends": appends, "final_target": list(sched.target),
+            "complete": sched.done(), "beta_updates_below_one": sum(1 for b in betas if b < 1.0),
+            "mean_ess": round(float(np.mean(ess)), 2) if ess else None,
+            "test_accuracy": round(r["accuracy"], 4), "test_mean_log_pred": round(r["mean_log_pred"], 5),
+            "config": {"workload": "MNIST-shaped synthetic templates 60000/10000, MLP 784-100-10 ReLU, J=256, "
+                                   "smooth data annealing C=kappa=1000 beta0=0.1 dS=1, prior N(0, 0.05^2), "
+                                   "Langevin h=0.002, systematic resampling", "precision": "bf16x3"}}
+
+
 def cpu_baseline(X, y, sizes, budget_s=12.0, J_s=8):
     """The FP64 oracle on the host cores: iterations k = 1, 2, ... of the same schedule
     with J_s particles until about budget_s seconds of work; rate in grad evals/s."""
@@ -379,6 +424,11 @@ def main():
         cnn = run_cnn(P, max(1, args.cnn_steps), args.seed)
         log(f"cnn: {json.dumps(cnn)}")
 
+    sda = None
+    if not args.no_sda:
+        sda = run_sda(P, dev, args.seed, max(1, args.sda_iters))
+        log(f"sda: {json.dumps(sda)}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(X, y, sizes)
@@ -408,6 +458,7 @@ def main():
         "time_to_accuracy": tta,
         "proposal_network": training,
         "cnn_config2": cnn,
+        "sda": sda,
         "kernels": {l: kernel_table(res[l]["prof"], leg_parts(l)[0]) for l in legs},
     }
     for l in legs[1:]:
