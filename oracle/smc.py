@@ -24,8 +24,8 @@ Readings taken where the paper is silent (each is listed in the design notes):
   (and so lambda) changed, otherwise the final gradient of the previous move is
   reused;
 * mass matrix M = I;
-* resampling is systematic (the paper uses multinomial) with the exact
-  integer rule of ``systematic_ancestors``; the ESS test is strict (< J/2) and
+* resampling is systematic (the paper uses multinomial, also provided) with
+  the exact integer rule of ``systematic_ancestors``; the ESS test is strict (< J/2) and
   is applied after every reweighting, including the initial one;
 * a particle whose log-likelihood is not finite gets log-weight -inf.
 
@@ -107,6 +107,46 @@ def systematic_ancestors(w, u):
                 lo = mid + 1
         anc[k] = lo
     return anc
+
+
+def multinomial_ancestors(w, uniforms):
+    """Multinomial resampling (the paper's scheme, Section 2) with the same exact integer rule.
+
+    J independent uniforms U_k in [0, 1) are placed on the quantised cumulative
+    distribution of ``systematic_ancestors``:
+
+        t_k = min(floor(U_k * T), T - 1)   (one correctly rounded FP64 product each)
+        a_k = #{ j : S_j <= t_k }
+
+    and the ancestors are returned in non-decreasing order (the order of the
+    uniforms does not matter).  Particle j is chosen Binomial(J, Q_j / T) times.
+    """
+    w = np.asarray(w, dtype=np.float64)
+    u = np.asarray(uniforms, dtype=np.float64)
+    J = w.shape[0]
+    if u.shape != (J,):
+        raise ValueError("one uniform per particle")
+    Q = [int(math.floor(float(x) * float(2 ** FIX_BITS))) for x in w]
+    S = []
+    acc = 0
+    for q in Q:
+        acc += q
+        S.append(acc)
+    T = S[-1]
+    if T <= 0:
+        raise ValueError("all weights quantise to zero")
+    anc = []
+    for k in range(J):
+        t = min(int(math.floor(float(u[k]) * float(T))), T - 1)
+        lo, hi = 0, J - 1
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if S[mid] > t:
+                hi = mid
+            else:
+                lo = mid + 1
+        anc.append(lo)
+    return np.array(sorted(anc), dtype=np.int64)
 
 
 def placement(ancestors):
@@ -284,13 +324,17 @@ class Sampler:
         return self
 
     # ---- resampling when the ESS drops below ess_frac * J
-    def resample(self, u, mode="if_needed"):
+    def resample(self, u, mode="if_needed", scheme="systematic"):
+        """u: the systematic offset, or for scheme="multinomial" the J uniforms."""
         J = self.theta.shape[0]
         if mode == "never" or (mode == "if_needed" and not (self.ess < self.ess_frac * J)):
             self.ancestors = None
             return False
         w = np.exp(self.logw)
-        self.ancestors = systematic_ancestors(w, u)
+        if scheme == "multinomial":
+            self.ancestors = multinomial_ancestors(w, u)
+        else:
+            self.ancestors = systematic_ancestors(w, u)
         p = placement(self.ancestors)
         self.placement = p
         self.theta = self.theta[p]

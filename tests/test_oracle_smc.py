@@ -82,6 +82,58 @@ def test_systematic_counts_and_order():
         assert np.all((counts == np.floor(J * w)) | (counts == np.ceil(J * w)) | (np.abs(J * w - np.round(J * w)) < 1e-9))
 
 
+# ----------------------------------------------------------------- multinomial resampling
+def _golden_multinomial():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "multinomial.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        u, w, a = [p.strip() for p in line.split(";")]
+        rows.append((np.array([float(x) for x in u.split()]), np.array([float(x) for x in w.split()]),
+                     [int(x) for x in a.split()]))
+    return rows
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_multinomial_worked_examples(case):
+    u, w, a = _golden_multinomial()[case]
+    assert list(smc.multinomial_ancestors(w, u)) == a
+
+
+def test_multinomial_agrees_with_the_float_inverse_cdf_and_ignores_uniform_order():
+    rng = np.random.default_rng(14)
+    J = 300
+    for _ in range(10):
+        lw, _ = smc.normalise(2 * rng.standard_normal(J))
+        w = np.exp(lw)
+        u = rng.random(J)
+        a = smc.multinomial_ancestors(w, u)
+        assert np.all(np.diff(a) >= 0)
+        assert np.array_equal(a, smc.multinomial_ancestors(w, u[rng.permutation(J)]))
+        cdf = np.cumsum(w)
+        ref = np.sort(np.minimum(np.searchsorted(cdf, u, side="right"), J - 1))
+        for k in np.nonzero(a != ref)[0]:
+            # only a uniform within rounding distance of a boundary may land differently
+            assert np.min(np.abs(cdf[:, None] - u[None, :])) < 1e-12
+
+
+def test_multinomial_counts_follow_the_binomial_law():
+    """Over 4000 draws with J = 8 the mean count of particle j is J w_j and its variance
+    J w_j (1 - w_j); the sample means must lie within 5 standard errors."""
+    rng = np.random.default_rng(15)
+    w = np.array([0.02, 0.08, 0.1, 0.2, 0.25, 0.05, 0.3, 0.0])
+    J, R = 8, 4000
+    counts = np.zeros((R, J))
+    for r in range(R):
+        counts[r] = np.bincount(smc.multinomial_ancestors(w, rng.random(J)), minlength=J)
+    mean = counts.mean(axis=0)
+    se = np.sqrt(J * w * (1 - w) / R)
+    assert np.all(np.abs(mean - J * w) <= 5 * se + 1e-12)
+    assert np.all(counts[:, 7] == 0)
+    var = counts.var(axis=0)
+    assert np.all(np.abs(var - J * w * (1 - w)) <= 0.15 * J * w * (1 - w) + 1e-12)
+
+
 def test_systematic_agrees_with_textbook_float_rule():
     rng = np.random.default_rng(4)
     J = 257
