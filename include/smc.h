@@ -94,7 +94,7 @@ enum { SMC_RESAMPLE_IF_NEEDED = 0, SMC_RESAMPLE_ALWAYS = 1, SMC_RESAMPLE_NEVER =
  * per-chunk operand buffers (patch matrices, activations and errors of all particles).
  */
 typedef struct smc_config {
-  int32_t n_particles;                 /* J >= 1 (at most 8192) */
+  int32_t n_particles;                 /* J >= 1 (at most 4096) */
   int32_t n_layers;                    /* L >= 1 weight layers (at most SMC_MAX_LAYERS); 3 for SMC_MODEL_CNN */
   int32_t widths[SMC_MAX_LAYERS + 1];  /* MLP: n_0 = input features, ..., n_L = outputs.
                                           CNN: {H, W, Cin, C1, C2, n_cls} (see below) */
@@ -196,6 +196,19 @@ SMC_API smc_status smc_segment_moments(smc_t h, double* out4);
  * Weights are reset to 1/J after resampling.
  */
 SMC_API smc_status smc_resample(smc_t h, int32_t mode, const double* u, int32_t* resampled, int32_t* ancestors_host);
+
+/*
+ * Multinomial resampling, the paper's scheme (Section 2): J ancestors drawn
+ * independently with probabilities w~_j.  Same exact integer rule as
+ * smc_resample: with the weights quantised to Q_j = floor(w~_j 2^50), prefix
+ * sums S_j and total T, uniform U_k goes to t_k = min(floor(U_k T), T - 1) and
+ * ancestor #{j : S_j <= t_k}; the ancestors are reported sorted.
+ *   u_dev  device [J] float64 uniforms in [0, 1) (clamped into [0, 1]), or NULL
+ *          to draw them on the device (Philox, one counter per particle).
+ * Other arguments, the decision, placement and weight reset as smc_resample.
+ */
+SMC_API smc_status smc_resample_multinomial(smc_t h, int32_t mode, const double* u_dev, int32_t* resampled,
+                                            int32_t* ancestors_host);
 
 /*
  * Posterior predictive p(y | x) = sum_j w~_j softmax(f_{theta_j}(x)) (Section 2,
@@ -380,6 +393,16 @@ SMC_API smc_status smc_normalise(const double* logw_dev, int32_t J, double* logw
  */
 SMC_API smc_status smc_systematic_resample(const double* w_dev, int32_t J, double u, int32_t* ancestors_dev,
                                    int32_t* placement_dev, void* hip_stream);
+
+/*
+ * Multinomial resampling of normalised weights w_dev [J] (float64) with the
+ * device uniforms u_dev [J] (float64, clamped into [0, 1]), exact integer rule
+ * of smc_resample_multinomial: t_k = min(floor(U_k T), T - 1), ancestor
+ * #{j : S_j <= t_k}.  ancestors_dev [J] int32 receives the ancestors sorted;
+ * placement_dev [J] int32 (nullable) the in-place arrangement.
+ */
+SMC_API smc_status smc_multinomial_resample(const double* w_dev, int32_t J, const double* u_dev,
+                                            int32_t* ancestors_dev, int32_t* placement_dev, void* hip_stream);
 
 /*
  * Raw Philox-4x32-10 blocks: for i in [0, n_blocks) out_dev[4i..4i+3] =

@@ -81,6 +81,7 @@ _SIGS = {
     "smc_step_tempered": (_i32, [_handle, _i64, _i64, _d, _d, C.POINTER(smc_step_info)]),
     "smc_segment_moments": (_i32, [_handle, C.POINTER(_d)]),
     "smc_resample": (_i32, [_handle, _i32, C.POINTER(_d), C.POINTER(_i32), C.POINTER(_i32)]),
+    "smc_resample_multinomial": (_i32, [_handle, _i32, _vp, C.POINTER(_i32), C.POINTER(_i32)]),
     "smc_posterior_predict": (_i32, [_handle, _vp, _vp, _i64, _vp, C.POINTER(_d), C.POINTER(_d)]),
     "smc_posterior_mean": (_i32, [_handle, _vp]),
     "smc_posterior_mean_change": (_i32, [_handle, C.POINTER(_d)]),
@@ -96,6 +97,7 @@ _SIGS = {
     "smc_chunk_samples": (_i64, [_handle]),
     "smc_normalise": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "smc_systematic_resample": (_i32, [_vp, _i32, _d, _vp, _vp, _vp]),
+    "smc_multinomial_resample": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "smc_philox": (_i32, [_u32, _u32, _u32, _u32, _u32, _i64, _vp, _vp]),
     "smc_proposal_targets": (_i32, [_handle, _i64, _d, C.POINTER(_d), _i32, _d, _d, _vp, _vp]),
     "smc_mlp_n_params": (_i32, [_i32]),
@@ -175,6 +177,15 @@ def smc_resample(h, mode: int, u=None, want_result: bool = False, want_ancestors
     return (bool(res.value) if want_result else None), (list(anc) if want_ancestors else None)
 
 
+def smc_resample_multinomial(h, mode: int, u_dev=None, want_result: bool = False, want_ancestors: bool = False,
+                             J: int = 0):
+    res = C.c_int32(0)
+    anc = (C.c_int32 * J)() if want_ancestors else None
+    _check(lib.smc_resample_multinomial(h, mode, _opt(u_dev), C.byref(res) if want_result else None, anc),
+           "smc_resample_multinomial")
+    return (bool(res.value) if want_result else None), (list(anc) if want_ancestors else None)
+
+
 def smc_posterior_predict(h, x_dev, y_dev, n: int, probs_dev=None, want_metrics: bool = True):
     acc, mlp = C.c_double(0.0), C.c_double(0.0)
     _check(lib.smc_posterior_predict(h, _opt(x_dev), _opt(y_dev), n, _opt(probs_dev),
@@ -239,6 +250,11 @@ def smc_chunk_samples(h) -> int:
 
 def smc_normalise(logw_dev, J: int, logw_out_dev, stats_dev, stream) -> None:
     _check(lib.smc_normalise(_opt(logw_dev), J, _opt(logw_out_dev), _opt(stats_dev), _opt(stream)), "smc_normalise")
+
+
+def smc_multinomial_resample(w_dev, J: int, u_dev, ancestors_dev, placement_dev, stream) -> None:
+    _check(lib.smc_multinomial_resample(_opt(w_dev), J, _opt(u_dev), _opt(ancestors_dev), _opt(placement_dev),
+                                        _opt(stream)), "smc_multinomial_resample")
 
 
 def smc_systematic_resample(w_dev, J: int, u: float, ancestors_dev, placement_dev, stream) -> None:

@@ -12,7 +12,8 @@ constexpr int MOVE_ELEMS = 1024; // parameters per move workgroup (256 threads x
 
 enum { HEAD_TRAIN = 0, HEAD_FORWARD = 1, HEAD_PREDICT = 2 };
 enum { MOVE_FIRST = 0, MOVE_MID = 1, MOVE_LAST = 2 };
-enum { TAG_MOMENTUM = 1, TAG_RESAMPLE_U = 2, TAG_PRIOR = 3 };
+enum { TAG_MOMENTUM = 1, TAG_RESAMPLE_U = 2, TAG_PRIOR = 3, TAG_RESAMPLE_MULTI = 4 };
+enum { RESAMPLE_SYSTEMATIC = 0, RESAMPLE_MULTINOMIAL = 1 };
 
 struct HeadArgs {
   const void* A = nullptr;          // activation (j, m, h) at A + j*sAj + m*sAm + h
@@ -192,6 +193,8 @@ struct ResampleArgs {
   int mode = 0;                  // 0 if needed, 1 always, 2 never
   double ess_frac = 0.5;
   const double* u_dev = nullptr; // device scalar u (or null: draw with Philox)
+  int scheme = 0;                // RESAMPLE_SYSTEMATIC or RESAMPLE_MULTINOMIAL
+  const double* u_arr = nullptr; // multinomial: device [J] uniforms (or null: Philox per particle)
   uint32_t key0 = 0, key1 = 0, ctr_iter = 0;
   double* w = nullptr;           // [J] normalised weights (in; reset to 1/J)
   double* logw = nullptr;        // [J] (reset to -log J)
@@ -211,6 +214,8 @@ hipError_t normalise_run(const double* logw, int J, double* out, double* stats, 
 hipError_t segment_moments_run(const double* w, const double* ll, const double* ll_b, int J, double* out,
                                hipStream_t s);
 hipError_t systematic_run(const double* w, int J, double u, int32_t* anc, int32_t* placement, hipStream_t s);
+hipError_t multinomial_run(const double* w, int J, const double* u_arr, int32_t* anc, int32_t* placement,
+                           hipStream_t s);
 hipError_t philox_run(uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t* out,
                       hipStream_t s);
 hipError_t prior_draw_run(float* theta, int J, int64_t D, float prior_std, uint32_t k0, uint32_t k1, hipStream_t s);

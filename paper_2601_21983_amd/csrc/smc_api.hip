@@ -1402,14 +1402,18 @@ smc_status smc_segment_moments(smc_t h, double* out4) {
   });
 }
 
-smc_status smc_resample(smc_t h, int32_t mode, const double* u, int32_t* resampled, int32_t* ancestors_host) {
-  return run([&]() {
+namespace {
+
+void resample_impl(smc_t h, int32_t mode, int scheme, const double* u, const double* u_arr_dev, int32_t* resampled,
+                   int32_t* ancestors_host) {
     if (!h) fail(SMC_ERR_ARG, "null handle");
     if (mode < 0 || mode > 2) fail(SMC_ERR_ARG, "mode");
     if (u && !(*u >= 0.0 && *u < 1.0)) fail(SMC_ERR_ARG, "u must be in [0, 1)");
     ResampleArgs ra;
     ra.J = h->J;
     ra.mode = mode;
+    ra.scheme = scheme;
+    ra.u_arr = u_arr_dev;
     ra.ess_frac = h->cfg.ess_frac;
     double* u_dev = nullptr;
     if (u) {
@@ -1443,7 +1447,17 @@ smc_status smc_resample(smc_t h, int32_t mode, const double* u, int32_t* resampl
         sync(h);
       }
     }
-  });
+}
+
+}  // namespace
+
+smc_status smc_resample(smc_t h, int32_t mode, const double* u, int32_t* resampled, int32_t* ancestors_host) {
+  return run([&]() { resample_impl(h, mode, RESAMPLE_SYSTEMATIC, u, nullptr, resampled, ancestors_host); });
+}
+
+smc_status smc_resample_multinomial(smc_t h, int32_t mode, const double* u_dev, int32_t* resampled,
+                                    int32_t* ancestors_host) {
+  return run([&]() { resample_impl(h, mode, RESAMPLE_MULTINOMIAL, nullptr, u_dev, resampled, ancestors_host); });
 }
 
 smc_status smc_posterior_predict(smc_t h, const float* x_dev, const int32_t* y_dev, int64_t n, float* probs_dev,
@@ -1809,6 +1823,15 @@ smc_status smc_systematic_resample(const double* w_dev, int32_t J, double u, int
     if (J < 1 || J > MAX_J) fail(SMC_ERR_ARG, "J out of range");
     if (!(u >= 0.0 && u < 1.0)) fail(SMC_ERR_ARG, "u must be in [0, 1)");
     HIPCHECK(systematic_run(w_dev, J, u, ancestors_dev, placement_dev, (hipStream_t)hip_stream));
+  });
+}
+
+smc_status smc_multinomial_resample(const double* w_dev, int32_t J, const double* u_dev, int32_t* ancestors_dev,
+                                    int32_t* placement_dev, void* hip_stream) {
+  return run([&]() {
+    if (!w_dev || !u_dev || !ancestors_dev) fail(SMC_ERR_ARG, "null argument");
+    if (J < 1 || J > MAX_J) fail(SMC_ERR_ARG, "J out of range");
+    HIPCHECK(multinomial_run(w_dev, J, u_dev, ancestors_dev, placement_dev, (hipStream_t)hip_stream));
   });
 }
 

@@ -281,9 +281,25 @@ __device__ SysScratch sys_scratch(char* smem, int J) {
 }
 size_t sys_smem_bytes(int J) { return (size_t)J * 8 + 17 * 8 + (size_t)J * 12 + 17 * 4; }
 
-// ancestors (sorted) and in-place placement from normalised weights w, offset u
+// a uniform double in [0, 1) (53 bits) from Philox at counter (idx, 0, iter, tag)
+__device__ __forceinline__ double philox_u01_double(uint32_t k0, uint32_t k1, uint32_t iter, uint32_t tag,
+                                                    uint32_t idx = 0) {
+  const u32x4 c = {idx, 0u, iter, tag};
+  const u32x4 r = philox4x32_10(c, k0, k1);
+  const uint64_t hi = r[0] >> 5, lo = r[1] >> 6;  // 27 + 26 bits
+  return (double)((hi << 26) | lo) * 0x1p-53;
+}
+
+// Uniforms of multinomial resampling: an array, or Philox at counters (k, 0, iter, TAG_RESAMPLE_MULTI)
+struct Uniforms {
+  const double* arr = nullptr;
+  uint32_t k0 = 0, k1 = 0, iter = 0;
+};
+
+// ancestors (sorted) and in-place placement from normalised weights w: systematic with
+// offset u (multi = false) or multinomial with the uniforms U (multi = true)
 __device__ void systematic_core(const double* w, int J, double u, const SysScratch& s, int32_t* anc,
-                                int32_t* place) {
+                                int32_t* place, bool multi = false, const Uniforms& U = Uniforms{}) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int per = (J + nt - 1) / nt;
   const int b = min(J, tid * per), e = min(J, b + per);
@@ -301,17 +317,47 @@ __device__ void systematic_core(const double* w, int J, double u, const SysScrat
   uint64_t R = (uint64_t)floor(u * (double)T);
   if (R > T - 1) R = T - 1;
   for (int k = tid; k < J; k += nt) {
-    const uint64_t t = ((uint64_t)k * T + R) / (uint64_t)J;
+    uint64_t t;
+    if (multi) {
+      const double uk = U.arr ? fmin(fmax(U.arr[k], 0.0), 1.0)
+                              : philox_u01_double(U.k0, U.k1, U.iter, TAG_RESAMPLE_MULTI, (uint32_t)k);
+      t = (uint64_t)floor(uk * (double)T);
+      if (t > T - 1) t = T - 1;
+    } else {
+      t = ((uint64_t)k * T + R) / (uint64_t)J;
+    }
     int lo = 0, hi = J - 1;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
       if (s.S[mid] > t) hi = mid;
       else lo = mid + 1;
     }
-    anc[k] = lo;
+    if (!multi) anc[k] = lo;  // systematic positions are already in increasing order
     atomicAdd(&s.cnt[lo], 1);
   }
   __syncthreads();
+  if (multi) {
+    // sorted ancestor list from the counts: anc[k] = first i whose inclusive count prefix exceeds k
+    int cloc = 0;
+    for (int i = b; i < e; ++i) cloc += s.cnt[i];
+    int ctot;
+    int cr = block_exclusive_scan<int>(cloc, s.wsi, ctot);
+    for (int i = b; i < e; ++i) {
+      cr += s.cnt[i];
+      s.einc[i] = cr;
+    }
+    __syncthreads();
+    for (int k = tid; k < J; k += nt) {
+      int lo = 0, hi = J - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s.einc[mid] > k) hi = mid;
+        else lo = mid + 1;
+      }
+      anc[k] = lo;
+    }
+    __syncthreads();
+  }
   if (!place) return;
   int dloc = 0, xloc = 0;
   for (int i = b; i < e; ++i) {
@@ -354,11 +400,13 @@ __global__ __launch_bounds__(1024) void systematic_kernel(const double* w, int J
   systematic_core(w, J, u, s, anc, place);
 }
 
-__device__ __forceinline__ double philox_u01_double(uint32_t k0, uint32_t k1, uint32_t iter, uint32_t tag) {
-  const u32x4 c = {0u, 0u, iter, tag};
-  const u32x4 r = philox4x32_10(c, k0, k1);
-  const uint64_t hi = r[0] >> 5, lo = r[1] >> 6;  // 27 + 26 bits
-  return (double)((hi << 26) | lo) * 0x1p-53;
+__global__ __launch_bounds__(1024) void multinomial_kernel(const double* w, int J, const double* u_arr, int32_t* anc,
+                                                           int32_t* place) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const SysScratch s = sys_scratch(smem, J);
+  Uniforms U;
+  U.arr = u_arr;
+  systematic_core(w, J, 0.0, s, anc, place, true, U);
 }
 
 __global__ __launch_bounds__(1024) void resample_kernel(const ResampleArgs a) {
@@ -374,9 +422,18 @@ __global__ __launch_bounds__(1024) void resample_kernel(const ResampleArgs a) {
     if (tid == 0) a.stats[ST_RESAMPLED] = 0.0;
     return;
   }
-  const double u = a.u_dev ? *a.u_dev : philox_u01_double(a.key0, a.key1, a.ctr_iter, TAG_RESAMPLE_U);
   const SysScratch s = sys_scratch(smem, J);
-  systematic_core(a.w, J, u, s, a.ancestors, a.placement);
+  if (a.scheme == RESAMPLE_MULTINOMIAL) {
+    Uniforms U;
+    U.arr = a.u_arr;
+    U.k0 = a.key0;
+    U.k1 = a.key1;
+    U.iter = a.ctr_iter;
+    systematic_core(a.w, J, 0.0, s, a.ancestors, a.placement, true, U);
+  } else {
+    const double u = a.u_dev ? *a.u_dev : philox_u01_double(a.key0, a.key1, a.ctr_iter, TAG_RESAMPLE_U);
+    systematic_core(a.w, J, u, s, a.ancestors, a.placement);
+  }
   // gather the per-particle scalars (read everything before writing)
   constexpr int NPT = MAX_J / 1024;
 #pragma unroll
@@ -599,6 +656,8 @@ __global__ __launch_bounds__(1024) void segment_moments_kernel(const double* __r
 hipError_t kernels_set_smem_limits() {
   const int big = 160 * 1024;
   hipError_t e = hipFuncSetAttribute((const void*)systematic_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)multinomial_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)resample_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
@@ -637,6 +696,13 @@ hipError_t normalise_run(const double* logw, int J, double* out, double* stats, 
 hipError_t resample_run(const ResampleArgs& a, hipStream_t s) {
   if (a.J > MAX_J) return hipErrorInvalidValue;
   hipLaunchKernelGGL(resample_kernel, dim3(1), dim3(1024), sys_smem_bytes(a.J), s, a);
+  return hipGetLastError();
+}
+
+hipError_t multinomial_run(const double* w, int J, const double* u_arr, int32_t* anc, int32_t* placement,
+                           hipStream_t s) {
+  if (J > MAX_J || J < 1 || !u_arr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(multinomial_kernel, dim3(1), dim3(1024), sys_smem_bytes(J), s, w, J, u_arr, anc, placement);
   return hipGetLastError();
 }
 

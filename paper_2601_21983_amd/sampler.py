@@ -155,8 +155,26 @@ class SMCSampler:
         e_b, var_b, e_a, cov = L.smc_segment_moments(self.handle)
         return {"mean_hat": e_b, "var_hat": var_b, "mean": e_a, "cov": cov}
 
-    def resample(self, mode: str = "if_needed", u: Optional[float] = None, want: bool = False):
-        res, anc = L.smc_resample(self.handle, _RES[mode], u, want_result=want, want_ancestors=want, J=self.J)
+    def resample(self, mode: str = "if_needed", u: Optional[float] = None, want: bool = False,
+                 scheme: str = "systematic", uniforms: Optional[torch.Tensor] = None):
+        """Systematic (offset u, host float, or None: drawn on the device) or multinomial
+        (uniforms: float64 GPU tensor [J], or None: drawn on the device) resampling."""
+        if scheme == "multinomial":
+            if u is not None:
+                raise ValueError("multinomial resampling takes `uniforms`, not `u`")
+            up = None
+            if uniforms is not None:
+                up = _dev(uniforms, torch.float64, "uniforms")
+                if tuple(uniforms.shape) != (self.J,):
+                    raise ValueError("uniforms must be [J]")
+            res, anc = L.smc_resample_multinomial(self.handle, _RES[mode], up, want_result=want,
+                                                  want_ancestors=want, J=self.J)
+        elif scheme == "systematic":
+            if uniforms is not None:
+                raise ValueError("systematic resampling takes one offset `u`")
+            res, anc = L.smc_resample(self.handle, _RES[mode], u, want_result=want, want_ancestors=want, J=self.J)
+        else:
+            raise ValueError("scheme must be 'systematic' or 'multinomial'")
         return (res, anc) if want else None
 
     def predict(self, Xt: torch.Tensor, yt: Optional[torch.Tensor] = None, probs: bool = False):
