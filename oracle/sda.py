@@ -21,10 +21,13 @@ import numpy as np
 
 
 def weighted_moments(w, omega, omega_hat):
-    """(Var(Omega^), Cov(Omega, Omega^)) under normalised weights w."""
+    """(Var(Omega^), Cov(Omega, Omega^)) under normalised weights w.  A particle of zero
+    weight does not enter the sums (its log-likelihood may be infinite)."""
     w = np.asarray(w, dtype=np.float64)
-    a = np.asarray(omega, dtype=np.float64)
-    b = np.asarray(omega_hat, dtype=np.float64)
+    keep = w > 0.0
+    w = w[keep]
+    a = np.asarray(omega, dtype=np.float64)[keep]
+    b = np.asarray(omega_hat, dtype=np.float64)[keep]
     e_b = np.sum(w * b)
     var_b = np.sum(w * b * b) - e_b * e_b
     e_a = np.sum(w * a)

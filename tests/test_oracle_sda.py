@@ -29,6 +29,14 @@ def test_moments_under_a_point_mass_vanish_and_are_shift_invariant():
     assert abs(v0 - v1) < 1e-12 and abs(c0 - c1) < 1e-12
 
 
+def test_zero_weight_particles_do_not_enter():
+    w = np.array([0.5, 0.0, 0.5])
+    a = np.array([1.0, np.inf, 3.0])
+    b = np.array([2.0, -np.inf, 4.0])
+    assert sda.weighted_moments(w, a, b) == sda.weighted_moments(np.array([0.5, 0.5]), a[[0, 2]], b[[0, 2]])
+    assert sda.weighted_moments(w, a, b) == (1.0, 1.0)
+
+
 # ----------------------------------------------------------------- beta updates
 W4 = np.full(4, 0.25)
 OH = np.array([1.0, 2.0, 3.0, 4.0])  # E = 2.5, Var = 1.25
