@@ -73,9 +73,11 @@ def parse():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mnist_shaped_bf16x3_learned_hbm_traffic.json")
 TRAFFIC_LEG = "bf16x3-learned"
-TRAFFIC_SOURCES = ["paper_2601_21983_amd/csrc/gemm.hip", "paper_2601_21983_amd/csrc/head.hip",
-                   "paper_2601_21983_amd/csrc/smc_kernels.hip", "paper_2601_21983_amd/csrc/learned.hip",
-                   "paper_2601_21983_amd/csrc/smc_api.hip"]
+TRAFFIC_SOURCES = ["paper_2601_21983_amd/csrc/gemm.hip", "paper_2601_21983_amd/csrc/gemm_core.h",
+                   "paper_2601_21983_amd/csrc/head.hip", "paper_2601_21983_amd/csrc/smc_kernels.hip",
+                   "paper_2601_21983_amd/csrc/learned.hip", "paper_2601_21983_amd/csrc/smc_api.hip",
+                   "paper_2601_21983_amd/csrc/kernels.h", "paper_2601_21983_amd/csrc/common.h",
+                   "paper_2601_21983_amd/csrc/gemm.h"]
 
 
 def source_digest():
