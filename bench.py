@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-cnn", action="store_true", help="skip the convolutional-network workload")
     ap.add_argument("--cnn-steps", type=int, default=8)
     ap.add_argument("--no-sda", action="store_true", help="skip the smooth-data-annealing run")
+    ap.add_argument("--table1", action="store_true",
+                    help="instead of the benchmark: the batching-scheme study (six schemes x LD/HMC, K = 200)")
     ap.add_argument("--sda-iters", type=int, default=SDA_MAX_ITERS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference kernel for HBM counters)")
@@ -331,6 +333,74 @@ def run_sda(P, dev, seed, max_iters):
                                    "Langevin h=0.002, systematic resampling", "precision": "bf16x3"}}
 
 
+TABLE1_K, TABLE1_C, TABLE1_PRIOR = 200, 500, 0.05
+# the paper's Table 1 MNIST runtimes in seconds (LD, HMC): context for the ratio structure only
+PAPER_TABLE1_MNIST_S = {"constant": (502.76, 453.33), "fb": (8985.56, 10658.68), "ctr": (1297.93, 1535.95),
+                        "linear": (7904.98, 9507.66), "automated": (4801.25, 5666.36), "sda": (6872.41, 7683.07)}
+
+
+def run_table1(P, dev, seed):
+    """The batching-scheme study of Table 1 on the MNIST-shaped workload: Constant, FB, CTR,
+    Linear, Automated (Section 3.1 schedules) and SDA, each with Langevin (S = 1) and HMC
+    (S = 3) moves, K = 200 iterations, C = kappa = 500, h = 0.002, split-BF16 sampler with the
+    fixed proposal.  Per run: wall time of initialisation and the K iterations (evaluation
+    excluded), its ratio to Constant with the same move, the data volume and test metrics."""
+    import torch
+    from paper_2601_21983_amd import schedules
+    from paper_2601_21983_amd.schedules import SDASchedule
+    K, C = TABLE1_K, TABLE1_C
+    runs = {}
+    for move, S in (("LD", 1), ("HMC", 3)):
+        for name in ("constant", "fb", "ctr", "linear", "automated", "sda"):
+            sizes = None if name == "sda" else schedules.sizes(name, K, N_TRAIN, C, C)
+            cfg = P.SMCConfig(widths=WIDTHS, n_particles=J, activation="relu", precision="bf16x3", step_size=STEP,
+                              leapfrog_steps=S, prior_std=TABLE1_PRIOR, seed=seed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "sda":
+                s = P.SMCSampler(cfg, dev["X"], dev["y"], m0=C, lambda0=0.1)
+                sched = SDASchedule(C, C, N_TRAIN, beta0=0.1, dS=1.0)
+            else:
+                s = P.SMCSampler(cfg, dev["X"], dev["y"], m0=sizes[0], lambda0=N_TRAIN / sizes[0])
+            s.resample()
+            evals, data = 0, 0
+            for k in range(1, K + 1):
+                if name == "sda":
+                    m, split, beta = sched.target
+                    info = s.step_tempered(m, split, 1.0, beta)
+                    s.resample()
+                    sched.next(s)
+                else:
+                    m = sizes[k]
+                    info = s.step(m, N_TRAIN / m)
+                    s.resample()
+                evals += info["grad_evals"]
+                data += m
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            r = s.predict(dev["Xt"], dev["yt"])
+            s.close()
+            e = {"seconds": round(dt, 3), "grad_evals": evals, "mean_subset": round(data / K, 1),
+                 "final_subset": int(m), "test_accuracy": round(r["accuracy"], 4),
+                 "test_mean_log_pred": round(r["mean_log_pred"], 5)}
+            if name == "sda":
+                e["final_target"] = list(sched.target)
+            runs[f"{name}_{move}"] = e
+            log(f"table1 {name} {move}: {json.dumps(e)}")
+    for move in ("LD", "HMC"):
+        base = runs[f"constant_{move}"]["seconds"]
+        i = 0 if move == "LD" else 1
+        for name, paper in PAPER_TABLE1_MNIST_S.items():
+            e = runs[f"{name}_{move}"]
+            e["ratio_to_constant"] = round(e["seconds"] / base, 2)
+            e["paper_ratio_to_constant"] = round(paper[i] / PAPER_TABLE1_MNIST_S["constant"][i], 2)
+    return {"study": "batching schemes (Table 1 structure)",
+            "workload": f"MNIST-shaped synthetic templates 60000/10000, MLP 784-100-10 ReLU (the paper's LeNet-5 is "
+                        f"not built), J={J}, K={K}, C=kappa={C}, h={STEP}, HMC S=3, prior N(0, {TABLE1_PRIOR}^2), "
+                        f"split-BF16 operands, systematic resampling",
+            "runs": runs}
+
+
 def cpu_baseline(X, y, sizes, budget_s=12.0, J_s=8):
     """The FP64 oracle on the host cores: iterations k = 1, 2, ... of the same schedule
     with J_s particles until about budget_s seconds of work; rate in grad evals/s."""
@@ -393,6 +463,10 @@ def main():
     if any(leg_parts(l)[1] == "learned" for l in legs):
         net, training = train_proposal(P, dev, sizes)
         log(f"proposal network: {training}")
+    if args.table1:
+        print(json.dumps(run_table1(P, dev, args.seed)), flush=True)
+        return
+
     res = {}
     for leg in legs:
         r = run_timed(P, dev, leg, sizes, steps, args.warmup, args.seed, net)
