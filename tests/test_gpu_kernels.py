@@ -107,6 +107,12 @@ NET_CASES = [
     ([5, 1], "relu", "gaussian", 33, 999, "bf16x3", 0),
     ([784, 100, 10], "tanh", "categorical", 24, 1000, "bf16", 0),
     ([784, 100, 10], "tanh", "categorical", 24, 1000, "bf16x3", 24 * 100 * 2 * 3 * 256),
+    # the fused kernel's limits: 127 hidden units (bias column fills the 128-row tile), 16 outputs,
+    # one hidden unit, one sample; the Gaussian likelihood through the fused kernel
+    ([784, 127, 16], "relu", "categorical", 5, 257, "bf16x3", 0),
+    ([784, 127, 16], "tanh", "categorical", 3, 65, "bf16", 0),
+    ([784, 1, 10], "tanh", "categorical", 7, 1, "bf16", 0),
+    ([5, 16, 1], "tanh", "gaussian", 9, 333, "bf16x3", 0),
 ]
 
 

@@ -69,6 +69,21 @@ def test_blobs_trajectory_matches_oracle():
     g.close()
 
 
+def test_single_particle_trajectory_matches_oracle():
+    """J = 1: the normalised log-weight stays 0, the ESS is 1 (never below J/2), and the
+    particle's path and log-evidence increments follow the oracle."""
+    cuda()
+    X, y = smc_inputs.blobs(256, seed=6)
+    sizes = schedules.sizes("linear", 6, 256, 64, 64)
+    print_case("single-particle", J=1, sizes=sizes)
+    for k, o, g, res_o, res_g, anc_g in _run_pair([2, 16, 2], "tanh", X, y, None, None, 1, sizes, 256, h=1e-3,
+                                                   seed=8):
+        _compare(o, g, res_o, res_g, anc_g, 1e-5, 1e-3, k)
+        assert not res_g
+        assert g.state()["logw"].cpu().numpy()[0] == 0.0
+    g.close()
+
+
 def test_blobs_hmc_trajectory_matches_oracle():
     cuda()
     X, y = smc_inputs.blobs(512, seed=2)
