@@ -4,7 +4,7 @@ Every function here has the name and argument order of the C entry point in
 include/smc.h.  Device pointers are plain integers (``tensor.data_ptr()``);
 streams are ``hipStream_t`` integers (``torch.cuda.current_stream().cuda_stream``).
 Each call raises ``SMCError`` on a non-OK status.  The library must be built
-(``python -m paper_2601_21983_amd.build``); importing this module without it
+(``python paper_2601_21983_amd/build.py``); importing this module without it
 raises ``ImportError`` - there is no fallback implementation.
 """
 from __future__ import annotations
@@ -66,7 +66,16 @@ class SMCError(RuntimeError):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2601_21983_amd.build`")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2601_21983_amd/build.py`")
+# PyTorch ships its own HIP runtime (soname libamdhip64.so.7) and its libraries ask for it as
+# libamdhip64.so.  Loading torch first makes libsmc.so's libamdhip64.so.7 resolve to that same
+# runtime; loading libsmc.so first would bring in the system runtime and torch would then load
+# a second one, whose device memory and streams this library could not use.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the C ABI itself does not need torch
+    pass
+
 lib = C.CDLL(LIB_PATH)
 
 _vp, _i32, _i64, _u32, _u64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double

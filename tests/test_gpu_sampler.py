@@ -84,6 +84,27 @@ def test_single_particle_trajectory_matches_oracle():
     g.close()
 
 
+def test_package_imported_before_torch_shares_its_hip_runtime():
+    """A program that imports the package before torch: the binding loads torch's HIP runtime
+    before libsmc.so, so the library sees the device and torch's tensors."""
+    cuda()
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    prog = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_2601_21983_amd as P\n"
+            "import numpy as np, torch, smc_inputs\n"
+            "X, y = smc_inputs.blobs(64, seed=0)\n"
+            "cfg = P.SMCConfig(widths=[2, 4, 2], n_particles=4, activation='tanh')\n"
+            "s = P.SMCSampler(cfg, torch.from_numpy(X).cuda(), torch.from_numpy(y.astype(np.int32)).cuda(), 64, 1.0)\n"
+            "print('ess', s.step(64, 1.0)['ess'])\n" % root)
+    print_case("import-order")
+    r = subprocess.run([sys.executable, "-c", prog], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "ess" in r.stdout
+
+
 def test_blobs_hmc_trajectory_matches_oracle():
     cuda()
     X, y = smc_inputs.blobs(512, seed=2)
