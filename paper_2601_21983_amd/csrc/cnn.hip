@@ -20,8 +20,6 @@ namespace smc {
 
 namespace {
 
-__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
-
 // input pixel read by patch element (tap) of output pixel pix, or -1 outside the image
 __device__ __forceinline__ int tap_src(const CnnDims& d, int pix, int tap) {
   const int y = pix / d.W, x = pix - y * d.W;
@@ -29,17 +27,21 @@ __device__ __forceinline__ int tap_src(const CnnDims& d, int pix, int tap) {
   return (yy >= 0 && yy < d.H && xx >= 0 && xx < d.W) ? yy * d.W + xx : -1;
 }
 
-// p1[r][k] = patch of image pixel r (k < K1), zero for K1 <= k < K1p
+// Index layout of the kernels below: blockIdx.z = particle, blockIdx.y = image (or tap /
+// channel vector), blockIdx.x * 256 + threadIdx.x the position inside it, so every thread
+// decomposes a 32-bit index with at most two divisions (the launchers check the ranges).
+// Consecutive lanes take consecutive pixels: the reads, which these kernels are bound by,
+// then come from neighbouring rows.
+
+// p1[r][k] = patch of image pixel r (k < K1), zero for K1 <= k < K1p; grid (HW K1p / 256, images)
 template <typename T>
 __global__ void im2col_x_kernel(const T* __restrict__ X, int64_t xld, int64_t c0, int mcv, CnnDims d,
                                 T* __restrict__ p1) {
-  const int64_t i = gtid();
-  const int64_t R = (int64_t)mcv * d.HW;
-  if (i >= R * d.K1p) return;
-  const int64_t r = i / d.K1p;
-  const int k = (int)(i - r * d.K1p);
-  const int64_t n = r / d.HW;
-  const int pix = (int)(r - n * d.HW);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d.HW * d.K1p) return;
+  const int64_t n = blockIdx.y;
+  const int pix = e / d.K1p, k = e - pix * d.K1p;
+  const int64_t i = n * d.HW * d.K1p + e;
   float v = 0.0f;
   if (k < d.K1) {
     const int tap = k / d.Cin, c = k - tap * d.Cin;
@@ -49,19 +51,18 @@ __global__ void im2col_x_kernel(const T* __restrict__ X, int64_t xld, int64_t c0
   p1[i] = cvt_out<T>(v);
 }
 
-// p1t[k][r] (row stride ld): the same patches transposed, with a ones row at k = K1
+// p1t[k][r] (row stride ld): the same patches transposed, with a ones row at k = K1;
+// grid (R / 256, K1 + 1)
 template <typename T>
 __global__ void im2col_xt_kernel(const T* __restrict__ X, int64_t xld, int64_t c0, int mcv, CnnDims d, int64_t ld,
                                  T* __restrict__ p1t) {
-  const int64_t i = gtid();
-  const int64_t R = (int64_t)mcv * d.HW;
-  if (i >= R * (d.K1 + 1)) return;
-  const int k = (int)(i / R);
-  const int64_t r = i - (int64_t)k * R;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mcv * d.HW) return;
+  const int k = blockIdx.y;
   float v = 1.0f;
   if (k < d.K1) {
     const int64_t n = r / d.HW;
-    const int pix = (int)(r - n * d.HW);
+    const int pix = r - (int)n * d.HW;
     const int tap = k / d.Cin, c = k - tap * d.Cin;
     const int s = tap_src(d, pix, tap);
     v = s >= 0 ? cvt_in<T>(X[(c0 + n) * xld + (int64_t)s * d.Cin + c]) : 0.0f;
@@ -70,20 +71,18 @@ __global__ void im2col_xt_kernel(const T* __restrict__ X, int64_t xld, int64_t c
 }
 
 // big[j][r][k] (row length K2 = 9 C1) = act1 patch, in 16-byte vectors of channels
+// grid (HW K2 / (VEC 256), images, particles)
 template <typename T>
 __global__ void im2col_a_kernel(const T* __restrict__ act1, int64_t sA, int mcv, CnnDims d, int J,
                                 T* __restrict__ big, int64_t sB) {
   constexpr int VEC = 16 / (int)sizeof(T);
-  const int64_t i = gtid();
-  const int64_t R = (int64_t)mcv * d.HW;
   const int nv = d.K2 / VEC;
-  if (i >= (int64_t)J * R * nv) return;
-  const int64_t jr = i / nv;
-  const int kv = (int)(i - jr * nv);
-  const int j = (int)(jr / R);
-  const int64_t r = jr - (int64_t)j * R;
-  const int64_t n = r / d.HW;
-  const int pix = (int)(r - n * d.HW);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d.HW * nv) return;
+  const int j = blockIdx.z;
+  const int64_t n = blockIdx.y;
+  const int pix = e / nv, kv = e - pix * nv;
+  const int64_t r = n * d.HW + pix;
   const int k = kv * VEC, tap = k / d.C1, c = k - tap * d.C1;
   const int s = tap_src(d, pix, tap);
   u32x4 v = {0u, 0u, 0u, 0u};
@@ -94,29 +93,24 @@ __global__ void im2col_a_kernel(const T* __restrict__ act1, int64_t sA, int mcv,
 // bigT[j][k][r] (row stride ld) = act1 patch transposed, ones row at k = K2.  One thread per
 // (j, tap, 8-channel vector, pixel r), pixels fastest: a 16-byte read of 8 channels of the
 // source pixel, eight 2-byte writes that are contiguous across the wave's pixels.
+// grid (R / 256, 9 C1 / VEC + 1, particles); the last y-row of blocks writes the ones row
 template <typename T>
 __global__ void im2col_at_kernel(const T* __restrict__ act1, int64_t sA, int mcv, CnnDims d, int J, int64_t ld,
                                  T* __restrict__ bigT, int64_t sB) {
   constexpr int VEC = 16 / (int)sizeof(T);
-  const int64_t i = gtid();
-  const int64_t R = (int64_t)mcv * d.HW;
   const int nv = d.C1 / VEC;
-  const int64_t per = (int64_t)9 * nv * R;
-  if (i >= (int64_t)J * per + (int64_t)J * R) return;
-  if (i >= (int64_t)J * per) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mcv * d.HW) return;
+  const int j = blockIdx.z;
+  const int tv = blockIdx.y;
+  if (tv == 9 * nv) {
     // the ones row (bias gradient)
-    const int64_t e = i - (int64_t)J * per;
-    const int j = (int)(e / R);
-    bigT[(int64_t)j * sB + (int64_t)d.K2 * ld + (e - (int64_t)j * R)] = cvt_out<T>(1.0f);
+    bigT[(int64_t)j * sB + (int64_t)d.K2 * ld + r] = cvt_out<T>(1.0f);
     return;
   }
-  const int j = (int)(i / per);
-  const int64_t e = i - (int64_t)j * per;
-  const int tv = (int)(e / R);
-  const int64_t r = e - (int64_t)tv * R;
   const int tap = tv / nv, c = (tv - tap * nv) * VEC;
   const int64_t n = r / d.HW;
-  const int pix = (int)(r - n * d.HW);
+  const int pix = r - (int)n * d.HW;
   const int s = tap_src(d, pix, tap);
   u32x4 v = {0u, 0u, 0u, 0u};
   if (s >= 0) v = *(const u32x4*)(act1 + (int64_t)j * sA + (n * d.HW + s) * d.C1 + c);
@@ -127,16 +121,14 @@ __global__ void im2col_at_kernel(const T* __restrict__ act1, int64_t sA, int mcv
 }
 
 // pooled[j][n][(py Wp + px) C2 + c] = mean of the 2x2 block of act2
+// grid (F3 / 256, images, particles)
 template <typename T>
 __global__ void pool_kernel(const T* __restrict__ act2, int64_t sA, int mcv, CnnDims d, int J,
                             T* __restrict__ pooled, int64_t sP) {
-  const int64_t i = gtid();
-  const int64_t per = (int64_t)mcv * d.F3;
-  if (i >= (int64_t)J * per) return;
-  const int j = (int)(i / per);
-  const int64_t e = i - (int64_t)j * per;
-  const int64_t n = e / d.F3;
-  const int f = (int)(e - n * d.F3);
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= d.F3) return;
+  const int j = blockIdx.z;
+  const int64_t n = blockIdx.y;
   const int p = f / d.C2, c = f - p * d.C2;
   const int py = p / d.Wp, px = p - py * d.Wp;
   const T* a = act2 + (int64_t)j * sA + (n * d.HW + (2 * py) * d.W + 2 * px) * d.C2 + c;
@@ -241,23 +233,18 @@ __global__ __launch_bounds__(256) void cnn_dw3_kernel(const T* __restrict__ d3, 
 // error at the conv2 output: d2 = (unpooled dpool / 4) * 1{act2 > 0}, written as rows
 // d2[j][r][c] and transposed d2t[j][c][r] (row stride ld).  One thread per (j, 8-channel
 // vector, pixel r), pixels fastest: 16-byte reads of act2 and dpool, a 16-byte row write and
-// eight 2-byte transposed writes contiguous across the wave's pixels.
+// eight 2-byte transposed writes contiguous across the wave's pixels.  Grid (R / 256, C2 / VEC,
+// particles).
 template <typename T>
 __global__ void unpool_kernel(const T* __restrict__ dpool, int64_t sP, const T* __restrict__ act2, int64_t sA,
                               int mcv, CnnDims d, int J, int64_t ld, T* __restrict__ d2, T* __restrict__ d2t) {
   constexpr int VEC = 16 / (int)sizeof(T);
-  const int64_t i = gtid();
-  const int64_t R = (int64_t)mcv * d.HW;
-  const int nv = d.C2 / VEC;
-  const int64_t per = (int64_t)nv * R;
-  if (i >= (int64_t)J * per) return;
-  const int j = (int)(i / per);
-  const int64_t e = i - (int64_t)j * per;
-  const int cvi = (int)(e / R);
-  const int64_t r = e - (int64_t)cvi * R;
-  const int c = cvi * VEC;
-  const int64_t n = r / d.HW;
-  const int pix = (int)(r - n * d.HW);
+  const int64_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (int64_t)mcv * d.HW) return;
+  const int j = blockIdx.z;
+  const int c = blockIdx.y * VEC;
+  const int64_t n = (int)r / d.HW;
+  const int pix = (int)r - (int)n * d.HW;
   const int y = pix / d.W, x = pix - y * d.W;
   const int64_t ai = (int64_t)j * sA + r * d.C2 + c;
   const u32x4 av = *(const u32x4*)(act2 + ai);
@@ -278,23 +265,18 @@ __global__ void unpool_kernel(const T* __restrict__ dpool, int64_t sP, const T* 
 // error at the conv1 output: sum over taps of the patch errors that read pixel r, times
 // 1{act1 > 0}; written transposed as d1t[j C1 + c][r] (row stride ld).  One thread per
 // (j, 8-channel vector, pixel r), pixels fastest: nine 16-byte patch-error reads, one
-// 16-byte activation read, eight 2-byte writes contiguous across the wave's pixels.
+// 16-byte activation read, eight 2-byte writes contiguous across the wave's pixels.  Grid
+// (R / 256, C1 / VEC, particles).
 template <typename T>
 __global__ void col2im_kernel(const T* __restrict__ dp2, int64_t sB, const T* __restrict__ act1, int64_t sA,
                               int mcv, CnnDims d, int J, int64_t ld, T* __restrict__ d1t) {
   constexpr int VEC = 16 / (int)sizeof(T);
-  const int64_t i = gtid();
-  const int64_t R = (int64_t)mcv * d.HW;
-  const int nv = d.C1 / VEC;
-  const int64_t per = (int64_t)nv * R;
-  if (i >= (int64_t)J * per) return;
-  const int j = (int)(i / per);
-  const int64_t e = i - (int64_t)j * per;
-  const int cvi = (int)(e / R);
-  const int64_t r = e - (int64_t)cvi * R;
-  const int c = cvi * VEC;
-  const int64_t n = r / d.HW;
-  const int pix = (int)(r - n * d.HW);
+  const int64_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (int64_t)mcv * d.HW) return;
+  const int j = blockIdx.z;
+  const int c = blockIdx.y * VEC;
+  const int64_t n = (int)r / d.HW;
+  const int pix = (int)r - (int)n * d.HW;
   const int y = pix / d.W, x = pix - y * d.W;
   float acc[VEC];
 #pragma unroll
@@ -318,21 +300,31 @@ __global__ void col2im_kernel(const T* __restrict__ dp2, int64_t sB, const T* __
 
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// the kernels index pixels of a chunk (mcv * HW) and positions inside one image in 32 bits,
+// images and taps / channel vectors on the y axis of the grid
+bool grid_ok(int mcv, const CnnDims& d, int64_t per_image) {
+  return mcv >= 1 && mcv <= 65535 && (int64_t)mcv * d.HW < ((int64_t)1 << 31) && per_image < ((int64_t)1 << 31);
+}
+
 }  // namespace
 
 hipError_t cnn_im2col_x_run(const void* X, int64_t xld, int64_t c0, int mcv, const CnnDims& d, void* p1, int bf16,
                             hipStream_t s) {
-  const int64_t n = (int64_t)mcv * d.HW * d.K1p;
-  if (bf16) hipLaunchKernelGGL(im2col_x_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)X, xld, c0, mcv, d, (__bf16*)p1);
-  else hipLaunchKernelGGL(im2col_x_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)X, xld, c0, mcv, d, (float*)p1);
+  if (mcv <= 0) return hipSuccess;
+  if (!grid_ok(mcv, d, (int64_t)d.HW * d.K1p)) return hipErrorInvalidValue;
+  const dim3 grid(nb((int64_t)d.HW * d.K1p, 256), mcv);
+  if (bf16) hipLaunchKernelGGL(im2col_x_kernel<__bf16>, grid, dim3(256), 0, s, (const __bf16*)X, xld, c0, mcv, d, (__bf16*)p1);
+  else hipLaunchKernelGGL(im2col_x_kernel<float>, grid, dim3(256), 0, s, (const float*)X, xld, c0, mcv, d, (float*)p1);
   return hipGetLastError();
 }
 
 hipError_t cnn_im2col_xt_run(const void* X, int64_t xld, int64_t c0, int mcv, const CnnDims& d, int64_t ld, void* p1t,
                              int bf16, hipStream_t s) {
-  const int64_t n = (int64_t)mcv * d.HW * (d.K1 + 1);
-  if (bf16) hipLaunchKernelGGL(im2col_xt_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)X, xld, c0, mcv, d, ld, (__bf16*)p1t);
-  else hipLaunchKernelGGL(im2col_xt_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)X, xld, c0, mcv, d, ld, (float*)p1t);
+  if (mcv <= 0) return hipSuccess;
+  if (!grid_ok(mcv, d, 0) || d.K1 + 1 > 65535) return hipErrorInvalidValue;
+  const dim3 grid(nb((int64_t)mcv * d.HW, 256), d.K1 + 1);
+  if (bf16) hipLaunchKernelGGL(im2col_xt_kernel<__bf16>, grid, dim3(256), 0, s, (const __bf16*)X, xld, c0, mcv, d, ld, (__bf16*)p1t);
+  else hipLaunchKernelGGL(im2col_xt_kernel<float>, grid, dim3(256), 0, s, (const float*)X, xld, c0, mcv, d, ld, (float*)p1t);
   return hipGetLastError();
 }
 
@@ -340,9 +332,12 @@ hipError_t cnn_im2col_a_run(const void* act1, int64_t sA, int mcv, const CnnDims
                             int bf16, hipStream_t s) {
   const int vec = bf16 ? 8 : 4;
   if (d.C1 % vec) return hipErrorInvalidValue;
-  const int64_t n = (int64_t)J * mcv * d.HW * (d.K2 / vec);
-  if (bf16) hipLaunchKernelGGL(im2col_a_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)act1, sA, mcv, d, J, (__bf16*)big, sB);
-  else hipLaunchKernelGGL(im2col_a_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)act1, sA, mcv, d, J, (float*)big, sB);
+  if (mcv <= 0 || J <= 0) return hipSuccess;
+  const int64_t per = (int64_t)d.HW * (d.K2 / vec);
+  if (!grid_ok(mcv, d, per) || J > 65535) return hipErrorInvalidValue;
+  const dim3 grid(nb(per, 256), mcv, J);
+  if (bf16) hipLaunchKernelGGL(im2col_a_kernel<__bf16>, grid, dim3(256), 0, s, (const __bf16*)act1, sA, mcv, d, J, (__bf16*)big, sB);
+  else hipLaunchKernelGGL(im2col_a_kernel<float>, grid, dim3(256), 0, s, (const float*)act1, sA, mcv, d, J, (float*)big, sB);
   return hipGetLastError();
 }
 
@@ -350,22 +345,28 @@ hipError_t cnn_im2col_at_run(const void* act1, int64_t sA, int mcv, const CnnDim
                              int64_t sB, int bf16, hipStream_t s) {
   const int vec = bf16 ? 8 : 4;
   if (d.C1 % vec) return hipErrorInvalidValue;
-  const int64_t n = (int64_t)J * (9 * (d.C1 / vec) + 1) * mcv * d.HW;
-  if (bf16) hipLaunchKernelGGL(im2col_at_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)act1, sA, mcv, d, J, ld, (__bf16*)bigT, sB);
-  else hipLaunchKernelGGL(im2col_at_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)act1, sA, mcv, d, J, ld, (float*)bigT, sB);
+  if (mcv <= 0 || J <= 0) return hipSuccess;
+  const int rows = 9 * (d.C1 / vec) + 1;  // tap x channel-vector rows, then the ones row
+  if (!grid_ok(mcv, d, 0) || rows > 65535 || J > 65535) return hipErrorInvalidValue;
+  const dim3 grid(nb((int64_t)mcv * d.HW, 256), rows, J);
+  if (bf16) hipLaunchKernelGGL(im2col_at_kernel<__bf16>, grid, dim3(256), 0, s, (const __bf16*)act1, sA, mcv, d, J, ld, (__bf16*)bigT, sB);
+  else hipLaunchKernelGGL(im2col_at_kernel<float>, grid, dim3(256), 0, s, (const float*)act1, sA, mcv, d, J, ld, (float*)bigT, sB);
   return hipGetLastError();
 }
 
 hipError_t cnn_pool_run(const void* act2, int64_t sA, int mcv, const CnnDims& d, int J, void* pooled, int64_t sP,
                         int bf16, hipStream_t s) {
-  const int64_t n = (int64_t)J * mcv * d.F3;
-  if (bf16) hipLaunchKernelGGL(pool_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)act2, sA, mcv, d, J, (__bf16*)pooled, sP);
-  else hipLaunchKernelGGL(pool_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)act2, sA, mcv, d, J, (float*)pooled, sP);
+  if (mcv <= 0 || J <= 0) return hipSuccess;
+  if (!grid_ok(mcv, d, d.F3) || J > 65535) return hipErrorInvalidValue;
+  const dim3 grid(nb(d.F3, 256), mcv, J);
+  if (bf16) hipLaunchKernelGGL(pool_kernel<__bf16>, grid, dim3(256), 0, s, (const __bf16*)act2, sA, mcv, d, J, (__bf16*)pooled, sP);
+  else hipLaunchKernelGGL(pool_kernel<float>, grid, dim3(256), 0, s, (const float*)act2, sA, mcv, d, J, (float*)pooled, sP);
   return hipGetLastError();
 }
 
 hipError_t cnn_ll_run(const CnnLLArgs& a, int J, int bf16, hipStream_t s) {
   if (a.ncls < 1 || a.ncls > 16) return hipErrorInvalidValue;
+  if (J <= 0) return hipSuccess;
   if (bf16) hipLaunchKernelGGL(cnn_ll_kernel<__bf16>, dim3(J), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(cnn_ll_kernel<float>, dim3(J), dim3(256), 0, s, a);
   return hipGetLastError();
@@ -375,6 +376,7 @@ hipError_t cnn_dw3_run(const void* d3, const void* pooled, int64_t sP, int mc, i
                        float* g, int64_t D, int64_t off, int beta, int bf16, hipStream_t s) {
   const size_t smem = (size_t)mcv * 16 * sizeof(float);
   if (smem > 64 * 1024) return hipErrorInvalidValue;
+  if (mcv <= 0 || J <= 0) return hipSuccess;
   dim3 grid(nb(F3 + 1, 256), J);
   if (bf16) hipLaunchKernelGGL(cnn_dw3_kernel<__bf16>, grid, dim3(256), smem, s, (const __bf16*)d3, (const __bf16*)pooled, sP, mc, mcv, F3, ncls, g, D, off, beta);
   else hipLaunchKernelGGL(cnn_dw3_kernel<float>, grid, dim3(256), smem, s, (const float*)d3, (const float*)pooled, sP, mc, mcv, F3, ncls, g, D, off, beta);
@@ -385,9 +387,11 @@ hipError_t cnn_unpool_run(const void* dpool, int64_t sP, const void* act2, int64
                           int J, int64_t ld, void* d2, void* d2t, int bf16, hipStream_t s) {
   const int vec = bf16 ? 8 : 4;
   if (d.C2 % vec) return hipErrorInvalidValue;
-  const int64_t n = (int64_t)J * (d.C2 / vec) * mcv * d.HW;
-  if (bf16) hipLaunchKernelGGL(unpool_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)dpool, sP, (const __bf16*)act2, sA, mcv, d, J, ld, (__bf16*)d2, (__bf16*)d2t);
-  else hipLaunchKernelGGL(unpool_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)dpool, sP, (const float*)act2, sA, mcv, d, J, ld, (float*)d2, (float*)d2t);
+  if (mcv <= 0 || J <= 0) return hipSuccess;
+  if (!grid_ok(mcv, d, 0) || J > 65535) return hipErrorInvalidValue;
+  const dim3 grid(nb((int64_t)mcv * d.HW, 256), d.C2 / vec, J);
+  if (bf16) hipLaunchKernelGGL(unpool_kernel<__bf16>, grid, dim3(256), 0, s, (const __bf16*)dpool, sP, (const __bf16*)act2, sA, mcv, d, J, ld, (__bf16*)d2, (__bf16*)d2t);
+  else hipLaunchKernelGGL(unpool_kernel<float>, grid, dim3(256), 0, s, (const float*)dpool, sP, (const float*)act2, sA, mcv, d, J, ld, (float*)d2, (float*)d2t);
   return hipGetLastError();
 }
 
@@ -395,9 +399,11 @@ hipError_t cnn_col2im_run(const void* dp2, int64_t sB, const void* act1, int64_t
                           int64_t ld, void* d1t, int bf16, hipStream_t s) {
   const int vec = bf16 ? 8 : 4;
   if (d.C1 % vec) return hipErrorInvalidValue;
-  const int64_t n = (int64_t)J * (d.C1 / vec) * mcv * d.HW;
-  if (bf16) hipLaunchKernelGGL(col2im_kernel<__bf16>, dim3(nb(n, 256)), dim3(256), 0, s, (const __bf16*)dp2, sB, (const __bf16*)act1, sA, mcv, d, J, ld, (__bf16*)d1t);
-  else hipLaunchKernelGGL(col2im_kernel<float>, dim3(nb(n, 256)), dim3(256), 0, s, (const float*)dp2, sB, (const float*)act1, sA, mcv, d, J, ld, (float*)d1t);
+  if (mcv <= 0 || J <= 0) return hipSuccess;
+  if (!grid_ok(mcv, d, 0) || J > 65535) return hipErrorInvalidValue;
+  const dim3 grid(nb((int64_t)mcv * d.HW, 256), d.C1 / vec, J);
+  if (bf16) hipLaunchKernelGGL(col2im_kernel<__bf16>, grid, dim3(256), 0, s, (const __bf16*)dp2, sB, (const __bf16*)act1, sA, mcv, d, J, ld, (__bf16*)d1t);
+  else hipLaunchKernelGGL(col2im_kernel<float>, grid, dim3(256), 0, s, (const float*)dp2, sB, (const float*)act1, sA, mcv, d, J, ld, (float*)d1t);
   return hipGetLastError();
 }
 
