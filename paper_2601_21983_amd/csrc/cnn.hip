@@ -263,30 +263,35 @@ __global__ void unpool_kernel(const T* __restrict__ dpool, int64_t sP, const T* 
 }
 
 // error at the conv1 output: sum over taps of the patch errors that read pixel r, times
-// 1{act1 > 0}; written transposed as d1t[j C1 + c][r] (row stride ld).  One thread per
-// (j, 8-channel vector, pixel r), pixels fastest: nine 16-byte patch-error reads, one
-// 16-byte activation read, eight 2-byte writes contiguous across the wave's pixels.  Grid
-// (R / 256, C1 / VEC, particles).
+// 1{act1 > 0}; written transposed as d1t[j C1 + c][r] (row stride ld).  The patch errors are
+// tap-major, dp2[j][tap][r'][c] with tap planes ld * C1 apart.  One thread per (j, pixel r,
+// VEC-channel vector), channel vectors fastest: a wave reads one contiguous stretch of each
+// tap plane; nine 16-byte patch-error reads, one 16-byte activation read, eight 2-byte writes.
+// Grid (R C1 / (VEC 256), 1, particles).
 template <typename T>
 __global__ void col2im_kernel(const T* __restrict__ dp2, int64_t sB, const T* __restrict__ act1, int64_t sA,
                               int mcv, CnnDims d, int J, int64_t ld, T* __restrict__ d1t) {
   constexpr int VEC = 16 / (int)sizeof(T);
-  const int64_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= (int64_t)mcv * d.HW) return;
+  const int nv = d.C1 / VEC;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mcv * d.HW * nv) return;
   const int j = blockIdx.z;
-  const int c = blockIdx.y * VEC;
-  const int64_t n = (int)r / d.HW;
-  const int pix = (int)r - (int)n * d.HW;
+  const int ri = e / nv;
+  const int c = (e - ri * nv) * VEC;
+  const int64_t r = ri;
+  const int64_t n = ri / d.HW;
+  const int pix = ri - (int)n * d.HW;
   const int y = pix / d.W, x = pix - y * d.W;
   float acc[VEC];
 #pragma unroll
   for (int t = 0; t < VEC; ++t) acc[t] = 0.0f;
-  const T* pj = dp2 + (int64_t)j * sB;
+  const T* pj = dp2 + (int64_t)j * sB + n * d.HW * d.C1 + c;
+  const int64_t plane = ld * d.C1;
   for (int tap = 0; tap < 9; ++tap) {
     // output pixel (y - ky + 1, x - kx + 1) reads this pixel through tap (ky, kx)
     const int yo = y - tap / 3 + 1, xo = x - tap % 3 + 1;
     if (yo < 0 || yo >= d.H || xo < 0 || xo >= d.W) continue;
-    const u32x4 v = *(const u32x4*)(pj + (n * d.HW + yo * d.W + xo) * d.K2 + tap * d.C1 + c);
+    const u32x4 v = *(const u32x4*)(pj + tap * plane + (int64_t)(yo * d.W + xo) * d.C1);
     const T* vv = (const T*)&v;
 #pragma unroll
     for (int t = 0; t < VEC; ++t) acc[t] += cvt_in<T>(vv[t]);
@@ -400,8 +405,9 @@ hipError_t cnn_col2im_run(const void* dp2, int64_t sB, const void* act1, int64_t
   const int vec = bf16 ? 8 : 4;
   if (d.C1 % vec) return hipErrorInvalidValue;
   if (mcv <= 0 || J <= 0) return hipSuccess;
-  if (!grid_ok(mcv, d, 0) || J > 65535) return hipErrorInvalidValue;
-  const dim3 grid(nb((int64_t)mcv * d.HW, 256), d.C1 / vec, J);
+  const int64_t work = (int64_t)mcv * d.HW * (d.C1 / vec);
+  if (!grid_ok(mcv, d, 0) || work >= ((int64_t)1 << 31) || J > 65535) return hipErrorInvalidValue;
+  const dim3 grid(nb(work, 256), 1, J);
   if (bf16) hipLaunchKernelGGL(col2im_kernel<__bf16>, grid, dim3(256), 0, s, (const __bf16*)dp2, sB, (const __bf16*)act1, sA, mcv, d, J, ld, (__bf16*)d1t);
   else hipLaunchKernelGGL(col2im_kernel<float>, grid, dim3(256), 0, s, (const float*)dp2, sB, (const float*)act1, sA, mcv, d, J, ld, (float*)d1t);
   return hipGetLastError();

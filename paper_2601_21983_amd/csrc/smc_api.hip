@@ -866,9 +866,13 @@ void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const doubl
       p.sBb = (int64_t)d.K2 * b.ldwT[1];
       p.N = d.K2;
       p.batch = J;
+      // stored tap-major, [tap][r][c] with tap planes RP * C1 apart, so that col2im reads each
+      // tap's errors of consecutive pixels contiguously
       p.out0.ptr = b.big;
       p.out0.sb = b.s_big;
-      p.out0.rstr = d.K2;
+      p.out0.rstr = d.C1;
+      p.out0.cs = d.C1;
+      p.out0.sC = b.RP * d.C1;
       gemm(h, p, SMC_K_GEMM_OTHER, 2.0 * R * J * d.C2 * d.K2);
     }
     timed(h, SMC_K_OTHER, 0.0, (double)J * R * (d.K2 + 2 * d.C1) * h->esz, [&]() {
