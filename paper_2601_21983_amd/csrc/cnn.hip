@@ -303,6 +303,20 @@ __global__ void col2im_kernel(const T* __restrict__ dp2, int64_t sB, const T* __
   for (int t = 0; t < VEC; ++t) dt[(int64_t)t * ld] = cvt_out<T>(cvt_in<T>(a[t]) > 0.0f ? acc[t] : 0.0f);
 }
 
+// conv1 weight gradient from its K-slice partials: g[j][o (N) + n] (+)= sum over slices s,
+// in order, of part[s][j C1 + o][n]
+__global__ void slice_sum_kernel(const float* __restrict__ part, int S, int M, int N, int C1, float* g, int64_t D,
+                                 int beta) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  float acc = 0.0f;
+  for (int k = 0; k < S; ++k) acc += part[(int64_t)k * M * N + e];
+  const int m = e / N, n = e - m * N;
+  const int j = m / C1, o = m - j * C1;
+  float* dst = g + (int64_t)j * D + (int64_t)o * N + n;
+  *dst = beta ? *dst + acc : acc;
+}
+
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // the kernels index pixels of a chunk (mcv * HW) and positions inside one image in 32 bits,
@@ -385,6 +399,14 @@ hipError_t cnn_dw3_run(const void* d3, const void* pooled, int64_t sP, int mc, i
   dim3 grid(nb(F3 + 1, 256), J);
   if (bf16) hipLaunchKernelGGL(cnn_dw3_kernel<__bf16>, grid, dim3(256), smem, s, (const __bf16*)d3, (const __bf16*)pooled, sP, mc, mcv, F3, ncls, g, D, off, beta);
   else hipLaunchKernelGGL(cnn_dw3_kernel<float>, grid, dim3(256), smem, s, (const float*)d3, (const float*)pooled, sP, mc, mcv, F3, ncls, g, D, off, beta);
+  return hipGetLastError();
+}
+
+hipError_t cnn_slice_sum_run(const float* part, int S, int M, int N, int C1, float* g, int64_t D, int beta,
+                             hipStream_t s) {
+  if (S < 1 || (int64_t)M * N >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (M <= 0 || N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(slice_sum_kernel, dim3(nb((int64_t)M * N, 256)), dim3(256), 0, s, part, S, M, N, C1, g, D, beta);
   return hipGetLastError();
 }
 

@@ -99,6 +99,9 @@ hipError_t cnn_im2col_at_run(const void* act1, int64_t sA, int mcv, const CnnDim
 hipError_t cnn_pool_run(const void* act2, int64_t sA, int mcv, const CnnDims& d, int J, void* pooled, int64_t sP,
                         int bf16, hipStream_t s);
 hipError_t cnn_ll_run(const CnnLLArgs& a, int J, int bf16, hipStream_t s);
+// g[j][o N + n] (+)= sum_{s < S} part[s][j C1 + o][n]: the K-slice partials of the conv1 gradient
+hipError_t cnn_slice_sum_run(const float* part, int S, int M, int N, int C1, float* g, int64_t D, int beta,
+                             hipStream_t s);
 hipError_t cnn_dw3_run(const void* d3, const void* pooled, int64_t sP, int mc, int mcv, int F3, int ncls, int J,
                        float* g, int64_t D, int64_t off, int beta, int bf16, hipStream_t s);
 hipError_t cnn_unpool_run(const void* dpool, int64_t sP, const void* act2, int64_t sA, int mcv, const CnnDims& d,

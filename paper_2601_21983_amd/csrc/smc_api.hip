@@ -157,6 +157,8 @@ struct CnnBufs {
   void *d3 = nullptr, *dpool = nullptr;         // [J][mc][16], [J][mc][F3]
   void *d2 = nullptr, *d2t = nullptr;           // [J][RP][C2], [J][C2][RP]
   void* d1t = nullptr;                          // [J*C1][RP]
+  float* dw1part = nullptr;                     // [kslices][J*C1][K1+1] split-K partials of the conv1 gradient
+  int kslices = 1;                              // their capacity
   float* logits = nullptr;                      // [J][mc][ncls]
   void* wT[3] = {nullptr, nullptr, nullptr};    // transposed copies of layers 1, 2: [J][nin][ldwT]
   int ldwT[3] = {0, 0, 0};
@@ -436,6 +438,11 @@ void alloc_cnn(smc_t h) {
   b.d2t = dalloc<char>(h->owned, J * b.s_act2 * e);
   b.d1t = dalloc<char>(h->owned, J * b.s_act1 * e);
   b.logits = dalloc<float>(h->owned, J * mc * d.ncls);
+  // the conv1 weight gradient is one GEMM with J*C1 output rows over all pixels of the chunk:
+  // it runs as up to 64 K-slices into FP32 partials (at most 256 MB) summed in a fixed order
+  const int64_t out1 = J * d.C1 * (d.K1 + 1);
+  b.kslices = (int)std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)256 << 20) / (out1 * 4)));
+  if (b.kslices > 1) b.dw1part = dalloc<float>(h->owned, b.kslices * out1);
   for (int l = 1; l < 3; ++l) {
     b.ldwT[l] = (int)round_up(h->net.nout[l], 8);
     const int64_t n = J * h->net.nin[l] * b.ldwT[l] * e;
@@ -881,22 +888,44 @@ void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const doubl
     timed(h, SMC_K_OTHER, 0.0, (double)R * (d.K1 + 1) * h->esz,
           [&]() { HIPCHECK(cnn_im2col_xt_run(h->X, h->xld, c0, mcv, d, b.RP, b.p1t, bf, h->stream)); });
     {
-      // conv1 weight gradient of every particle: d1^T [J*C1 x R] . [patches | 1]
+      // conv1 weight gradient of every particle: d1^T [J*C1 x R] . [patches | 1].  Its output has
+      // only J*C1/256 row tiles, so the pixels are split into S equal K-slices (S divides R/8)
+      // whose FP32 partials are summed in slice order.
+      const int M = J * d.C1, N = d.K1 + 1;
+      const int64_t tiles = (M + 255) / 256;
+      int S = (int)std::min<int64_t>(b.kslices, std::max<int64_t>(1, 1024 / tiles));
+      while (S > 1 && (R / 8) % S) --S;
       GemmParams p;
       p.epi = EPI_GRAD;
-      p.beta = beta;
       p.A = b.d1t;
       p.lda = b.RP;
-      p.M = J * d.C1;
-      p.K = (int)R;
+      p.M = M;
       p.B = b.p1t;
       p.ldb = b.RP;
-      p.N = d.K1 + 1;
-      p.out0.ptr = g_out;
-      p.out0.rs = d.C1;
-      p.out0.sR = h->D;
-      p.out0.rstr = d.K1 + 1;
-      gemm(h, p, SMC_K_GEMM_DW1, 2.0 * R * J * d.C1 * (d.K1 + 1));
+      p.N = N;
+      if (S == 1) {
+        p.beta = beta;
+        p.K = (int)R;
+        p.out0.ptr = g_out;
+        p.out0.rs = d.C1;
+        p.out0.sR = h->D;
+        p.out0.rstr = N;
+        gemm(h, p, SMC_K_GEMM_DW1, 2.0 * R * J * d.C1 * N);
+      } else {
+        const int Kc = (int)(R / S);
+        p.beta = 0;
+        p.K = Kc;
+        p.sAb = Kc;
+        p.sBb = Kc;
+        p.batch = S;
+        p.out0.ptr = b.dw1part;
+        p.out0.sb = (int64_t)M * N;
+        p.out0.rstr = N;
+        gemm(h, p, SMC_K_GEMM_DW1, 2.0 * R * J * d.C1 * N);
+        timed(h, SMC_K_OTHER, 0.0, (double)S * M * N * 4.0, [&]() {
+          HIPCHECK(cnn_slice_sum_run(b.dw1part, S, M, N, d.C1, g_out, h->D, beta, h->stream));
+        });
+      }
     }
   }
   if (train) h->grad_evals += (int64_t)J * m;
