@@ -93,22 +93,24 @@ __global__ void im2col_a_kernel(const T* __restrict__ act1, int64_t sA, int mcv,
 // bigT[j][k][r] (row stride ld) = act1 patch transposed, ones row at k = K2.  One thread per
 // (j, tap, 8-channel vector, pixel r), pixels fastest: a 16-byte read of 8 channels of the
 // source pixel, eight 2-byte writes that are contiguous across the wave's pixels.
-// grid (R / 256, 9 C1 / VEC + 1, particles); the last y-row of blocks writes the ones row
+// lanes take (pixel, channel vector) with the vector fastest, so a wave reads whole source
+// pixels; grid (R C1 / (VEC 256), 10, particles): y = tap, y = 9 writes the ones row
 template <typename T>
 __global__ void im2col_at_kernel(const T* __restrict__ act1, int64_t sA, int mcv, CnnDims d, int J, int64_t ld,
                                  T* __restrict__ bigT, int64_t sB) {
   constexpr int VEC = 16 / (int)sizeof(T);
   const int nv = d.C1 / VEC;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= mcv * d.HW) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mcv * d.HW * nv) return;
+  const int r = e / nv;
+  const int c = (e - r * nv) * VEC;
   const int j = blockIdx.z;
-  const int tv = blockIdx.y;
-  if (tv == 9 * nv) {
+  const int tap = blockIdx.y;
+  if (tap == 9) {
     // the ones row (bias gradient)
-    bigT[(int64_t)j * sB + (int64_t)d.K2 * ld + r] = cvt_out<T>(1.0f);
+    if (c == 0) bigT[(int64_t)j * sB + (int64_t)d.K2 * ld + r] = cvt_out<T>(1.0f);
     return;
   }
-  const int tap = tv / nv, c = (tv - tap * nv) * VEC;
   const int64_t n = r / d.HW;
   const int pix = r - (int)n * d.HW;
   const int s = tap_src(d, pix, tap);
@@ -233,18 +235,21 @@ __global__ __launch_bounds__(256) void cnn_dw3_kernel(const T* __restrict__ d3, 
 // error at the conv2 output: d2 = (unpooled dpool / 4) * 1{act2 > 0}, written as rows
 // d2[j][r][c] and transposed d2t[j][c][r] (row stride ld).  One thread per (j, 8-channel
 // vector, pixel r), pixels fastest: 16-byte reads of act2 and dpool, a 16-byte row write and
-// eight 2-byte transposed writes contiguous across the wave's pixels.  Grid (R / 256, C2 / VEC,
-// particles).
+// eight 2-byte transposed writes.  Lanes take (pixel, channel vector) with the vector fastest,
+// so a wave reads and writes whole pixel rows.  Grid (R C2 / (VEC 256), 1, particles).
 template <typename T>
 __global__ void unpool_kernel(const T* __restrict__ dpool, int64_t sP, const T* __restrict__ act2, int64_t sA,
                               int mcv, CnnDims d, int J, int64_t ld, T* __restrict__ d2, T* __restrict__ d2t) {
   constexpr int VEC = 16 / (int)sizeof(T);
-  const int64_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= (int64_t)mcv * d.HW) return;
+  const int nv = d.C2 / VEC;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mcv * d.HW * nv) return;
+  const int ri = e / nv;
+  const int c = (e - ri * nv) * VEC;
+  const int64_t r = ri;
   const int j = blockIdx.z;
-  const int c = blockIdx.y * VEC;
-  const int64_t n = (int)r / d.HW;
-  const int pix = (int)r - (int)n * d.HW;
+  const int64_t n = ri / d.HW;
+  const int pix = ri - (int)n * d.HW;
   const int y = pix / d.W, x = pix - y * d.W;
   const int64_t ai = (int64_t)j * sA + r * d.C2 + c;
   const u32x4 av = *(const u32x4*)(act2 + ai);
@@ -365,9 +370,9 @@ hipError_t cnn_im2col_at_run(const void* act1, int64_t sA, int mcv, const CnnDim
   const int vec = bf16 ? 8 : 4;
   if (d.C1 % vec) return hipErrorInvalidValue;
   if (mcv <= 0 || J <= 0) return hipSuccess;
-  const int rows = 9 * (d.C1 / vec) + 1;  // tap x channel-vector rows, then the ones row
-  if (!grid_ok(mcv, d, 0) || rows > 65535 || J > 65535) return hipErrorInvalidValue;
-  const dim3 grid(nb((int64_t)mcv * d.HW, 256), rows, J);
+  const int64_t work = (int64_t)mcv * d.HW * (d.C1 / vec);
+  if (!grid_ok(mcv, d, 0) || work >= ((int64_t)1 << 31) || J > 65535) return hipErrorInvalidValue;
+  const dim3 grid(nb(work, 256), 10, J);  // nine taps, then the ones row
   if (bf16) hipLaunchKernelGGL(im2col_at_kernel<__bf16>, grid, dim3(256), 0, s, (const __bf16*)act1, sA, mcv, d, J, ld, (__bf16*)bigT, sB);
   else hipLaunchKernelGGL(im2col_at_kernel<float>, grid, dim3(256), 0, s, (const float*)act1, sA, mcv, d, J, ld, (float*)bigT, sB);
   return hipGetLastError();
@@ -415,8 +420,9 @@ hipError_t cnn_unpool_run(const void* dpool, int64_t sP, const void* act2, int64
   const int vec = bf16 ? 8 : 4;
   if (d.C2 % vec) return hipErrorInvalidValue;
   if (mcv <= 0 || J <= 0) return hipSuccess;
-  if (!grid_ok(mcv, d, 0) || J > 65535) return hipErrorInvalidValue;
-  const dim3 grid(nb((int64_t)mcv * d.HW, 256), d.C2 / vec, J);
+  const int64_t work = (int64_t)mcv * d.HW * (d.C2 / vec);
+  if (!grid_ok(mcv, d, 0) || work >= ((int64_t)1 << 31) || J > 65535) return hipErrorInvalidValue;
+  const dim3 grid(nb(work, 256), 1, J);
   if (bf16) hipLaunchKernelGGL(unpool_kernel<__bf16>, grid, dim3(256), 0, s, (const __bf16*)dpool, sP, (const __bf16*)act2, sA, mcv, d, J, ld, (__bf16*)d2, (__bf16*)d2t);
   else hipLaunchKernelGGL(unpool_kernel<float>, grid, dim3(256), 0, s, (const float*)dpool, sP, (const float*)act2, sA, mcv, d, J, ld, (float*)d2, (float*)d2t);
   return hipGetLastError();
