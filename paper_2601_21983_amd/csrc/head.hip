@@ -324,7 +324,10 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
         *(u32x4*)((T*)a.dT + (int64_t)j * a.sdTj + (int64_t)h * a.sdTh + s0 + v * (16 / (int)sizeof(T))) = val;
       }
     }
-    // ---- 4. dW_L += delta^T [A | 1]: this wave owns h-blocks w, w+4, ...
+    // ---- 4. dW_L += delta^T [A | 1]: this wave owns h-blocks w, w+4, ...  Like the other weight
+    // gradients, a product with the single-BF16 output error: the activations' hi plane only (the
+    // rounding of the errors and of the activations changes from sample to sample and averages
+    // out in the sum over samples)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int hb = w + 4 * q;
@@ -333,7 +336,6 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
       for (int kb = 0; kb < HT / 16; ++kb) {
         const typename V4<T>::type av = ld4(Dt + cl * DS + kb * 16 + 4 * g);
         const typename V4<T>::type bv = gather4(As + (kb * 16 + 4 * g) * AS + hb * 16 + cl, AS);
-        if (alo) dacc[q] = mma16(av, gather4(AsLo + (kb * 16 + 4 * g) * AS + hb * 16 + cl, AS), dacc[q]);
         dacc[q] = mma16(av, bv, dacc[q]);
       }
     }
