@@ -76,7 +76,7 @@ enum { SMC_LIK_CATEGORICAL = 0, SMC_LIK_GAUSSIAN = 1 };
  */
 enum { SMC_PREC_FP32 = 0, SMC_PREC_BF16 = 1, SMC_PREC_BF16X3 = 2 };
 enum { SMC_PROPOSAL_FIXED = 0, SMC_PROPOSAL_LEARNED = 1 };
-enum { SMC_MODEL_MLP = 0, SMC_MODEL_CNN = 1 };
+enum { SMC_MODEL_MLP = 0, SMC_MODEL_CNN = 1, SMC_MODEL_LENET = 2 };
 enum { SMC_RESAMPLE_IF_NEEDED = 0, SMC_RESAMPLE_ALWAYS = 1, SMC_RESAMPLE_NEVER = 2 };
 
 #define SMC_MAX_LAYERS 8
@@ -92,14 +92,30 @@ enum { SMC_RESAMPLE_IF_NEEDED = 0, SMC_RESAMPLE_ALWAYS = 1, SMC_RESAMPLE_NEVER =
  * [n_cls x ((H/2)(W/2) C2 + 1)] with input index (py*(W/2) + px)*C2 + c; output pixel
  * (y, x) reads input pixel (y + ky - 1, x + kx - 1).  act_budget_bytes bounds the
  * per-chunk operand buffers (patch matrices, activations and errors of all particles).
+ *
+ * SMC_MODEL_LENET: the LeNet-5 classifier of the paper's MNIST study (Section 4, Table 1)
+ * conv kxk(C1) "same" -> act -> 2x2 average pool -> conv kxk(C2) "valid" -> act -> 2x2
+ * average pool -> dense(F1) -> act -> dense(F2) -> act -> dense(n_cls), stride 1, zero
+ * padding (k-1)/2 on the first convolution, one activation (tanh in the paper) throughout,
+ * on H x W images with Cin channels stored channel-last.  n_layers = 5 and widths = {H, W,
+ * Cin, k, C1, C2, F1, F2, n_cls}; {28, 28, 1, 5, 6, 16, 120, 84, 10} is LeNet-5 with
+ * D = 61,706.  Limits: k = 3 or 5, H and W even, (H/2 - k + 1) and (W/2 - k + 1) even and
+ * >= 2, Cin and C1 <= 8, ceil(C2/2) k^2 <= 256, F1 and F2 multiples of 4, 2 <= n_cls <= 16,
+ * FP32 operands, categorical likelihood, the fixed proposal.  Parameter blocks, each
+ * output unit's weights followed by its bias: conv1 [C1 x (k^2 Cin + 1)] with weight index
+ * (ky*k + kx)*Cin + c, conv2 [C2 x (k^2 C1 + 1)] with index (ky*k + kx)*C1 + c, dense1
+ * [F1 x (F + 1)] with input index (py*Wq + px)*C2 + c over the Hq x Wq x C2 pooled map
+ * (F = Hq Wq C2), dense2 [F2 x (F1 + 1)], output [n_cls x (F2 + 1)].  Output pixel (y, x)
+ * of the first convolution reads input pixel (y + ky - (k-1)/2, x + kx - (k-1)/2); of the
+ * second, pooled pixel (y + ky, x + kx).
  */
 typedef struct smc_config {
   int32_t n_particles;                 /* J >= 1 (at most 4096) */
-  int32_t n_layers;                    /* L >= 1 weight layers (at most SMC_MAX_LAYERS); 3 for SMC_MODEL_CNN */
+  int32_t n_layers;                    /* L >= 1 weight layers (at most SMC_MAX_LAYERS); 3 for SMC_MODEL_CNN, 5 for SMC_MODEL_LENET */
   int32_t widths[SMC_MAX_LAYERS + 1];  /* MLP: n_0 = input features, ..., n_L = outputs.
-                                          CNN: {H, W, Cin, C1, C2, n_cls} (see below) */
+                                          CNN: {H, W, Cin, C1, C2, n_cls}; LENET: {H, W, Cin, k, C1, C2, F1, F2, n_cls} */
   int32_t activation;                  /* hidden activation: SMC_ACT_TANH | SMC_ACT_RELU (CNN: ReLU) */
-  int32_t model_kind;                  /* SMC_MODEL_MLP | SMC_MODEL_CNN */
+  int32_t model_kind;                  /* SMC_MODEL_MLP | SMC_MODEL_CNN | SMC_MODEL_LENET */
   int32_t likelihood;                  /* SMC_LIK_CATEGORICAL (n_L <= 16 classes) | SMC_LIK_GAUSSIAN (n_L = 1) */
   int32_t precision;                   /* GEMM operand precision; accumulation is always FP32 */
   int32_t proposal;                    /* SMC_PROPOSAL_FIXED | SMC_PROPOSAL_LEARNED (needs S = 1) */

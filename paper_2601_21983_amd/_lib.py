@@ -19,7 +19,7 @@ SMC_ACT_TANH, SMC_ACT_RELU = 0, 1
 SMC_LIK_CATEGORICAL, SMC_LIK_GAUSSIAN = 0, 1
 SMC_PREC_FP32, SMC_PREC_BF16, SMC_PREC_BF16X3 = 0, 1, 2
 SMC_PROPOSAL_FIXED, SMC_PROPOSAL_LEARNED = 0, 1
-SMC_MODEL_MLP, SMC_MODEL_CNN = 0, 1
+SMC_MODEL_MLP, SMC_MODEL_CNN, SMC_MODEL_LENET = 0, 1, 2
 SMC_RESAMPLE_IF_NEEDED, SMC_RESAMPLE_ALWAYS, SMC_RESAMPLE_NEVER = 0, 1, 2
 
 STATUS = {0: "SMC_OK", 1: "SMC_ERR_ARG", 2: "SMC_ERR_OOM", 3: "SMC_ERR_DEVICE", 4: "SMC_ERR_STATE",

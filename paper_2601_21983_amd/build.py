@@ -21,7 +21,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsmc.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["gemm.hip", "head.hip", "smc_kernels.hip", "learned.hip", "cnn.hip", "smc_api.hip"]
+SOURCES = ["gemm.hip", "head.hip", "smc_kernels.hip", "learned.hip", "cnn.hip", "lenet.hip", "smc_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 CFLAGS = [

@@ -109,6 +109,33 @@ hipError_t cnn_unpool_run(const void* dpool, int64_t sP, const void* act2, int64
 hipError_t cnn_col2im_run(const void* dp2, int64_t sB, const void* act1, int64_t sA, int mcv, const CnnDims& d, int J,
                           int64_t ld, void* d1t, int bf16, hipStream_t s);
 
+// LeNet-5 convolution stack (lenet.hip): conv kxk "same" (C1) -> act -> 2x2 average pool ->
+// conv kxk "valid" (C2) -> act -> 2x2 average pool -> F features; FP32 operands.
+constexpr int LENET_CMAX = 8;  // Cin and C1 at most this
+struct LenetDims {
+  int H = 0, W = 0, Cin = 0, k = 0, pad = 0, C1 = 0, C2 = 0;
+  int Hp = 0, Wp = 0;  // after the first pool
+  int H2 = 0, W2 = 0;  // second convolution's output
+  int Hq = 0, Wq = 0;  // after the second pool
+  int K1 = 0, K2 = 0;  // k k Cin, k k C1
+  int F = 0;           // Hq Wq C2
+  int Dconv = 0;       // C1 (K1 + 1) + C2 (K2 + 1): the conv blocks at the start of each theta row
+  int ns1 = 1;         // pixel slices of the conv1 weight-gradient items
+};
+size_t lenet_smem_bytes(const LenetDims& d, bool bwd);
+// feat[j][n][f] (stride sF per particle) and, if featT, featT[j][f][n] ([(F+1) x ldT] per
+// particle, the ones row f = F untouched) for images n < rows of the chunk starting at global
+// row c0 of X; rows mcv <= n < rows are written as zeros.  ipb images per workgroup.
+hipError_t lenet_fwd_run(const float* X, int64_t xld, int64_t c0, int mcv, int rows, int ipb, const LenetDims& d,
+                         const float* theta, int64_t D, int J, int act, float* feat, int64_t sF, float* featT,
+                         int64_t ldT, hipStream_t s);
+// Conv weight gradients of the chunk from the features' error dfeat[j][n][f]: per-block
+// partials part[j][blk][Dconv] (part_blocks >= ceil(mcv / ipb) per particle), then
+// g[j][0, Dconv) (+)= their sum in block order (beta = 1 accumulates).
+hipError_t lenet_bwd_run(const float* X, int64_t xld, int64_t c0, int mcv, int ipb, const LenetDims& d,
+                         const float* theta, int64_t D, int J, int act, const float* dfeat, int64_t sF, float* part,
+                         int part_blocks, float* g, int beta, hipStream_t s);
+
 // Network shape shared by the elementwise kernels.
 struct NetShape {
   int L = 0;

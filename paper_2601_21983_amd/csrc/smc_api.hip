@@ -174,6 +174,13 @@ struct smc_handle {
   int J = 0, L = 0, F = 0, C = 0, bf16 = 0, split = 0, cnn = 0;
   int fused = 0;  // one hidden layer, BF16 operands: layer 1 and the output layer in one kernel
   CnnBufs cb;
+  // LeNet-5: a convolution stack (lenet.hip) whose F features feed the dense layers in place
+  // of X; per chunk lfeat [J][mc][F], lfeatT [J][(F+1)][mc] (ones row F), ldfeat [J][mc][F]
+  // and the conv-gradient partials lpart [J][lpart_blocks][Dconv]
+  int lenet = 0;
+  LenetDims ld;
+  float *lfeat = nullptr, *lfeatT = nullptr, *ldfeat = nullptr, *lpart = nullptr;
+  int lpart_blocks = 0;
   int64_t D = 0;
   int64_t n_data = 0, n_pad = 0;
   int ldx = 0;  // padded feature count
@@ -275,6 +282,48 @@ int head_type(int precision) {
   return precision == SMC_PREC_BF16X3 ? HEAD_BF16_SPLIT : precision == SMC_PREC_BF16 ? HEAD_BF16 : HEAD_F32;
 }
 
+LenetDims lenet_dims(const int32_t* w) {
+  LenetDims d;
+  d.H = w[0], d.W = w[1], d.Cin = w[2], d.k = w[3], d.C1 = w[4], d.C2 = w[5];
+  d.pad = (d.k - 1) / 2;
+  d.Hp = d.H / 2, d.Wp = d.W / 2;
+  d.H2 = d.Hp - d.k + 1, d.W2 = d.Wp - d.k + 1;
+  d.Hq = d.H2 / 2, d.Wq = d.W2 / 2;
+  d.K1 = d.k * d.k * d.Cin, d.K2 = d.k * d.k * d.C1;
+  d.F = d.Hq * d.Wq * d.C2;
+  d.Dconv = d.C1 * (d.K1 + 1) + d.C2 * (d.K2 + 1);
+  // conv1 weight-gradient items (channel pair, tap) replicated over pixel slices to fill 256 threads
+  d.ns1 = std::max(1, 256 / (((d.C1 + 1) / 2) * d.k * d.k));
+  return d;
+}
+
+void check_lenet(const smc_config* c) {
+  const int* w = c->widths;
+  if (c->n_layers != 5) fail(SMC_ERR_ARG, "LeNet has n_layers = 5 (widths H, W, Cin, k, C1, C2, F1, F2, n_cls)");
+  for (int q = 0; q < 9; ++q)
+    if (w[q] < 1) fail(SMC_ERR_ARG, "every LeNet dimension must be >= 1");
+  if (w[3] != 3 && w[3] != 5) fail(SMC_ERR_UNSUPPORTED, "LeNet kernel size must be 3 or 5");
+  if (w[0] % 2 || w[1] % 2 || w[0] > 512 || w[1] > 512) fail(SMC_ERR_UNSUPPORTED, "H and W must be even and at most 512");
+  const LenetDims d = lenet_dims(w);
+  if (d.H2 < 2 || d.W2 < 2 || d.H2 % 2 || d.W2 % 2)
+    fail(SMC_ERR_UNSUPPORTED, "the second convolution's output (H/2 - k + 1, W/2 - k + 1) must be even and >= 2");
+  if (d.Cin > LENET_CMAX || d.C1 > LENET_CMAX) fail(SMC_ERR_UNSUPPORTED, "LeNet Cin and C1 must be at most 8");
+  if ((d.C2 + 1) / 2 * d.k * d.k > 256) fail(SMC_ERR_UNSUPPORTED, "LeNet needs ceil(C2/2) k^2 <= 256");
+  if (d.F % 4 || w[6] % 4 || w[7] % 4) fail(SMC_ERR_UNSUPPORTED, "LeNet F, F1 and F2 must be multiples of 4");
+  if (lenet_smem_bytes(d, true) > 65536) fail(SMC_ERR_UNSUPPORTED, "LeNet image too large for the convolution kernels");
+  if (w[8] < 2 || w[8] > 16) fail(SMC_ERR_UNSUPPORTED, "categorical likelihood needs 2..16 classes");
+  if (c->activation != SMC_ACT_TANH && c->activation != SMC_ACT_RELU) fail(SMC_ERR_ARG, "activation");
+  if (c->likelihood != SMC_LIK_CATEGORICAL) fail(SMC_ERR_UNSUPPORTED, "LeNet is a classifier");
+  if (c->precision != SMC_PREC_FP32) fail(SMC_ERR_UNSUPPORTED, "LeNet runs with FP32 operands");
+  if (c->proposal != SMC_PROPOSAL_FIXED) fail(SMC_ERR_UNSUPPORTED, "LeNet uses the fixed proposal");
+  if (c->leapfrog_steps < 1) fail(SMC_ERR_ARG, "leapfrog_steps must be >= 1");
+  if (!(c->step_size >= 0) || !isfinite(c->step_size)) fail(SMC_ERR_ARG, "step_size must be finite and >= 0");
+  if (!(c->prior_std > 0)) fail(SMC_ERR_ARG, "prior_std must be > 0");
+  if (!(c->ess_frac >= 0 && c->ess_frac <= 1)) fail(SMC_ERR_ARG, "ess_frac must be in [0, 1]");
+  if (c->act_budget_bytes < 0) fail(SMC_ERR_ARG, "act_budget_bytes must be >= 0");
+  if (!head_supported(w[7], w[8], HEAD_F32)) fail(SMC_ERR_UNSUPPORTED, "F2 too wide for the output-layer kernel");
+}
+
 void check_config(const smc_config* c) {
   if (!c) fail(SMC_ERR_ARG, "null config");
   if (c->n_particles < 1 || c->n_particles > MAX_J)
@@ -291,6 +340,9 @@ void check_config(const smc_config* c) {
     if (c->activation != SMC_ACT_RELU) fail(SMC_ERR_UNSUPPORTED, "the convolutional network uses ReLU");
     if (c->likelihood != SMC_LIK_CATEGORICAL) fail(SMC_ERR_UNSUPPORTED, "the convolutional network is a classifier");
     if (c->precision == SMC_PREC_BF16X3) fail(SMC_ERR_UNSUPPORTED, "split BF16 is not built for the convolutional network");
+  } else if (c->model_kind == SMC_MODEL_LENET) {
+    check_lenet(c);
+    return;
   } else if (c->model_kind != SMC_MODEL_MLP) {
     fail(SMC_ERR_ARG, "model_kind");
   }
@@ -339,7 +391,20 @@ void setup_shapes(smc_t h) {
   h->F = c.widths[0];
   h->C = c.widths[c.n_layers];
   h->cnn = c.model_kind == SMC_MODEL_CNN;
+  h->lenet = c.model_kind == SMC_MODEL_LENET;
   int cnn_in[3] = {0, 0, 0}, cnn_out[3] = {0, 0, 0};
+  int64_t off = 0;
+  if (h->lenet) {
+    // the dense layers F -> F1 -> F2 -> n_cls after the convolution blocks
+    h->ld = lenet_dims(c.widths);
+    const LenetDims& d = h->ld;
+    h->L = 3;
+    h->F = d.H * d.W * d.Cin;  // the X operand holds the images
+    h->C = c.widths[8];
+    cnn_in[0] = d.F, cnn_in[1] = c.widths[6], cnn_in[2] = c.widths[7];
+    cnn_out[0] = c.widths[6], cnn_out[1] = c.widths[7], cnn_out[2] = c.widths[8];
+    off = d.Dconv;
+  }
   if (h->cnn) {
     CnnDims& d = h->cb.d;
     d.H = c.widths[0];
@@ -368,10 +433,9 @@ void setup_shapes(smc_t h) {
   n.J = h->J;
   n.bf16 = h->bf16;
   n.split = h->split;
-  int64_t off = 0;
   for (int l = 0; l < h->L; ++l) {
-    n.nin[l] = h->cnn ? cnn_in[l] : c.widths[l];
-    n.nout[l] = h->cnn ? cnn_out[l] : c.widths[l + 1];
+    n.nin[l] = h->cnn || h->lenet ? cnn_in[l] : c.widths[l];
+    n.nout[l] = h->cnn || h->lenet ? cnn_out[l] : c.widths[l + 1];
     n.off[l] = off;
     n.ldw[l] = (int)round_up(n.nin[l], 8);
     n.rowpad[l] = n.nout[l];
@@ -409,6 +473,8 @@ int64_t choose_chunk(smc_t h) {
     if (l >= 1) per_sample += u * h->esz;                          // dR
     if (l + 1 < h->L - 1) per_sample += (int64_t)h->J * (h->net.nout[l] + 1) * h->esz;  // actT
   }
+  if (h->lenet)  // features, their transpose and their error; the first dense layer's dR
+    per_sample += (int64_t)h->J * (3 * h->ld.F + 1 + h->net.nout[0]) * 4;
   if (per_sample == 0) per_sample = 1;
   int64_t mc = budget / per_sample;
   mc = mc / 256 * 256;
@@ -456,7 +522,7 @@ void alloc_all(smc_t h) {
   const int64_t D = h->D;
   h->n_pad = round_up(h->n_data, 256);
   h->X = dalloc<char>(h->owned, h->n_pad * h->xld * (int64_t)h->esz);
-  if (!h->cnn) h->XT = dalloc<char>(h->owned, (int64_t)(h->F + 1) * h->n_pad * (int64_t)h->esz);
+  if (!h->cnn && !h->lenet) h->XT = dalloc<char>(h->owned, (int64_t)(h->F + 1) * h->n_pad * (int64_t)h->esz);
   if (h->cfg.likelihood == SMC_LIK_GAUSSIAN) h->yreal = dalloc<float>(h->owned, h->n_pad);
   else h->ylab = dalloc<int32_t>(h->owned, h->n_pad);
   h->theta = dalloc<float>(h->owned, (int64_t)J * D);
@@ -493,7 +559,7 @@ void alloc_all(smc_t h) {
     LayerBufs& b = h->lb[l];
     if (!h->fused) b.act = dalloc<char>(h->owned, mc * u * (int64_t)h->esz * (h->split ? 2 : 1));
     b.dT = dalloc<char>(h->owned, mc * u * (int64_t)h->esz);
-    if (l >= 1) b.dR = dalloc<char>(h->owned, mc * u * (int64_t)h->esz);
+    if (l >= 1 || h->lenet) b.dR = dalloc<char>(h->owned, mc * u * (int64_t)h->esz);
     if (l + 1 < h->L - 1) {
       const int64_t nc = (int64_t)J * (h->net.nout[l] + 1);
       b.actT = dalloc<char>(h->owned, nc * mc * (int64_t)h->esz);
@@ -507,12 +573,24 @@ void alloc_all(smc_t h) {
       HIPCHECK(hipGetLastError());
     }
   }
-  for (int l = 1; l < h->L - 1; ++l) {
+  for (int l = h->lenet ? 0 : 1; l < h->L - 1; ++l) {
     LayerBufs& b = h->lb[l];
     b.ldwT = (int)round_up(h->net.nout[l], 8);
     const int64_t n = (int64_t)J * h->net.nin[l] * b.ldwT * (int64_t)h->esz;
     b.wT = dalloc<char>(h->owned, n);
     HIPCHECK(hipMemsetAsync(b.wT, 0, (size_t)n, h->stream));
+  }
+  if (h->lenet) {
+    const int F = h->ld.F;
+    h->lfeat = dalloc<float>(h->owned, (int64_t)J * mc * F);
+    h->lfeatT = dalloc<float>(h->owned, (int64_t)J * (F + 1) * mc);
+    h->ldfeat = dalloc<float>(h->owned, (int64_t)J * mc * F);
+    h->lpart_blocks = (int)std::min<int64_t>(64, mc);
+    h->lpart = dalloc<float>(h->owned, (int64_t)J * h->lpart_blocks * h->ld.Dconv);
+    const int64_t tot = (int64_t)J * mc;
+    hipLaunchKernelGGL(fill_ones_rows_kernel<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h->stream,
+                       h->lfeatT, J, F, mc, mc);
+    HIPCHECK(hipGetLastError());
   }
   const int ntiles = (int)(mc / 64);
   h->nsplit_max = std::max(1, std::min(ntiles, (2048 + J - 1) / J));
@@ -546,7 +624,7 @@ void upload_data(smc_t h, const float* x, const void* y) {
 }
 
 void transpose_weights(smc_t h, const float* theta) {
-  const int l0 = 1, l1 = h->cnn ? 3 : h->L - 1;
+  const int l0 = h->lenet ? 0 : 1, l1 = h->cnn ? 3 : h->L - 1;
   for (int l = l0; l < l1; ++l) {
     LayerBufs cbuf;
     if (h->cnn) {
@@ -573,6 +651,21 @@ void gemm(smc_t h, const GemmParams& p, int cls, double flops) {
   });
 }
 
+// LeNet: features of images [c0, c0 + mcv) of the operand Xop (rows up to `rows` zeroed),
+// and their transpose for the first dense layer's weight gradient when with_t.
+double lenet_macs_per_image(const LenetDims& d) {
+  return (double)d.H * d.W * d.C1 * d.K1 + (double)d.H2 * d.W2 * d.C2 * d.K2;
+}
+
+void lenet_features(smc_t h, const float* theta, const void* Xop, int64_t c0, int mcv, int rows, bool with_t) {
+  const int J = h->J;
+  const int ipb = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)rows * J / 4096));
+  timed(h, SMC_K_OTHER, 2.0 * J * mcv * lenet_macs_per_image(h->ld), 0.0, [&]() {
+    HIPCHECK(lenet_fwd_run((const float*)Xop, h->xld, c0, mcv, rows, ipb, h->ld, theta, h->D, J, h->cfg.activation,
+                           h->lfeat, h->mc * h->ld.F, with_t ? h->lfeatT : nullptr, h->mc, h->stream));
+  });
+}
+
 // Forward through the hidden layers for samples [c0, c0 + rows) of the operand X
 // (xld-strided rows).  Writes act_l (and actT_l when a hidden layer follows).
 void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows, int m_valid) {
@@ -585,7 +678,30 @@ void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows, int m_valid)
     p.act = h->cfg.activation;
     p.M = rows;
     p.K = h->net.ldw[l];
-    if (l == 0) {
+    if (l == 0 && h->lenet) {
+      // batched over particles: particle j's features from the convolution stack
+      const int F = h->ld.F;
+      p.A = h->lfeat;
+      p.lda = F;
+      p.sAb = h->mc * F;
+      p.B = h->net.w[0];
+      p.ldb = h->net.ldw[0];
+      p.sBb = (int64_t)h->net.rowpad[0] * h->net.ldw[0];
+      p.K = F;
+      p.N = nout;
+      p.batch = J;
+      p.bias = h->net.bias[0];
+      p.sbias = nout;
+      p.out0.ptr = h->lb[0].act;
+      p.out0.sb = h->mc * nout;
+      p.out0.rstr = nout;
+      if (h->lb[0].actT) {
+        p.out1.ptr = h->lb[0].actT;
+        p.out1.sb = (int64_t)(nout + 1) * h->mc;
+        p.out1.cstr = h->mc;
+        p.out1.rstr = 1;
+      }
+    } else if (l == 0) {
       // one dense GEMM over the concatenation of all particles' units
       p.A = (const char*)Xop + c0 * h->xld * (int64_t)h->esz;
       p.lda = h->xld;
@@ -633,7 +749,7 @@ void forward_hidden(smc_t h, const void* Xop, int64_t c0, int rows, int m_valid)
         p.out1.rstr = 1;
       }
     }
-    const double fl = 2.0 * m_valid * (double)U * (l == 0 ? h->F : h->net.nin[l]);
+    const double fl = 2.0 * m_valid * (double)U * (l == 0 && !h->lenet ? h->F : h->net.nin[l]);
     gemm(h, p, l == 0 ? SMC_K_GEMM_FWD1 : SMC_K_GEMM_OTHER, fl);
   }
 }
@@ -970,6 +1086,7 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
     const int mcv = (int)std::min<int64_t>(h->mc, m - c0);
     const int rows = (int)round_up(mcv, 64);
     const int beta = c0 > 0 ? 1 : 0;
+    if (h->lenet) lenet_features(h, theta, h->X, c0, mcv, rows, train);
     if (!h->fused) forward_hidden(h, h->X, c0, rows, mcv);
     HeadArgs a = head_args(h, theta);
     if (L == 1) a.A = (const char*)h->X + c0 * h->xld * (int64_t)h->esz;
@@ -1015,7 +1132,18 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
         p.K = rows;
         p.A = h->lb[l].dT;
         p.lda = h->mc;
-        if (l == 0) {
+        if (l == 0 && h->lenet) {
+          p.M = nout;
+          p.N = nin + 1;
+          p.sAb = (int64_t)nout * h->mc;
+          p.B = h->lfeatT;
+          p.ldb = h->mc;
+          p.sBb = (int64_t)(nin + 1) * h->mc;
+          p.batch = J;
+          p.out0.ptr = g_out + h->net.off[0];
+          p.out0.sb = h->D;
+          p.out0.rstr = nin + 1;
+        } else if (l == 0) {
           p.M = J * nout;
           p.N = nin + 1;
           p.B = (const char*)h->XT + c0 * (int64_t)h->esz;
@@ -1067,6 +1195,31 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
           p.out1.rstr = nin;
         }
         gemm(h, p, SMC_K_GEMM_OTHER, 2.0 * J * nout * (double)nin * mcv);
+      }
+      if (l == 0 && h->lenet) {
+        // error of the features, delta_0 W_0 (the pooling and activation below it belong to
+        // the convolution stack), then the convolution weight gradients
+        GemmParams p;
+        p.epi = EPI_FWD;
+        p.M = rows;
+        p.N = nin;
+        p.K = nout;
+        p.A = h->lb[0].dR;
+        p.lda = nout;
+        p.sAb = h->mc * nout;
+        p.B = h->lb[0].wT;
+        p.ldb = h->lb[0].ldwT;
+        p.sBb = (int64_t)nin * h->lb[0].ldwT;
+        p.batch = J;
+        p.out0.ptr = h->ldfeat;
+        p.out0.sb = h->mc * nin;
+        p.out0.rstr = nin;
+        gemm(h, p, SMC_K_GEMM_OTHER, 2.0 * J * nout * (double)nin * mcv);
+        const int ipb = (mcv + h->lpart_blocks - 1) / h->lpart_blocks;
+        timed(h, SMC_K_OTHER, 4.0 * J * mcv * lenet_macs_per_image(h->ld), 0.0, [&]() {
+          HIPCHECK(lenet_bwd_run((const float*)h->X, h->xld, c0, mcv, ipb, h->ld, theta, h->D, J, h->cfg.activation,
+                                 h->ldfeat, h->mc * h->ld.F, h->lpart, h->lpart_blocks, g_out, beta, h->stream));
+        });
       }
     }
   }
@@ -1544,6 +1697,7 @@ smc_status smc_posterior_predict(smc_t h, const float* x_dev, const int32_t* y_d
         continue;
       }
       const int rows = (int)round_up(mcv, 64);
+      if (h->lenet) lenet_features(h, h->theta, h->tx, c0, mcv, rows, false);
       forward_hidden(h, h->tx, c0, rows, mcv);
       HeadArgs a = head_args(h, h->theta);
       if (h->L == 1) a.A = (const char*)h->tx + c0 * h->xld * (int64_t)h->esz;

@@ -19,6 +19,7 @@ namespace {
 
 // ------------------------------------------------------------------ GEMM-layout cast
 __device__ __forceinline__ void cast_any(const NetShape& n, int j, int64_t e, float v) {
+  if (e < n.off[0]) return;  // parameters ahead of the dense layers (a convolution stack)
   int l = 0;
 #pragma unroll
   for (int q = 1; q < MAX_LAYERS; ++q)

@@ -34,10 +34,16 @@ def _dev(t: torch.Tensor, dtype, name: str) -> int:
 def n_params(widths: Sequence[int], model: str = "mlp") -> int:
     """Parameters per particle: dense layers [n_0, ..., n_L], or for the convolutional network
     widths = [H, W, Cin, C1, C2, n_cls] (blocks [C1 x (9 Cin + 1)], [C2 x (9 C1 + 1)],
-    [n_cls x ((H/2)(W/2) C2 + 1)])."""
+    [n_cls x ((H/2)(W/2) C2 + 1)]), or for LeNet widths = [H, W, Cin, k, C1, C2, F1, F2, n_cls]
+    (conv blocks [C1 x (k^2 Cin + 1)], [C2 x (k^2 C1 + 1)], then dense F -> F1 -> F2 -> n_cls
+    with F = ((H/2 - k + 1)/2) ((W/2 - k + 1)/2) C2)."""
     if model == "cnn":
         H, W, Cin, C1, C2, n = widths
         return C1 * (9 * Cin + 1) + C2 * (9 * C1 + 1) + n * ((H // 2) * (W // 2) * C2 + 1)
+    if model == "lenet":
+        H, W, Cin, k, C1, C2, F1, F2, n = widths
+        F = (H // 2 - k + 1) // 2 * ((W // 2 - k + 1) // 2) * C2
+        return C1 * (k * k * Cin + 1) + C2 * (k * k * C1 + 1) + F1 * (F + 1) + F2 * (F1 + 1) + n * (F2 + 1)
     return sum(widths[i + 1] * (widths[i] + 1) for i in range(len(widths) - 1))
 
 
@@ -57,7 +63,8 @@ class SMCConfig:
     seed: int = 0
     act_budget_bytes: int = 0
     n_iterations: int = 0
-    model: str = "mlp"  # "mlp" or "cnn" (widths = [H, W, Cin, C1, C2, n_cls])
+    model: str = "mlp"  # "mlp", "cnn" (widths = [H, W, Cin, C1, C2, n_cls]) or "lenet"
+    #                     (widths = [H, W, Cin, k, C1, C2, F1, F2, n_cls])
 
     def to_c(self) -> L.smc_config:
         c = L.smc_config()
@@ -66,12 +73,18 @@ class SMCConfig:
             if len(self.widths) != 6:
                 raise ValueError("the convolutional network takes widths [H, W, Cin, C1, C2, n_cls]")
             c.n_layers = 3
-        else:
+        elif self.model == "lenet":
+            if len(self.widths) != 9:
+                raise ValueError("LeNet takes widths [H, W, Cin, k, C1, C2, F1, F2, n_cls]")
+            c.n_layers = 5
+        elif self.model == "mlp":
             c.n_layers = len(self.widths) - 1
+        else:
+            raise ValueError(f"unknown model {self.model!r}")
         for i, w in enumerate(self.widths):
             c.widths[i] = int(w)
         c.activation = _ACT[self.activation]
-        c.model_kind = L.SMC_MODEL_CNN if self.model == "cnn" else L.SMC_MODEL_MLP
+        c.model_kind = {"mlp": L.SMC_MODEL_MLP, "cnn": L.SMC_MODEL_CNN, "lenet": L.SMC_MODEL_LENET}[self.model]
         c.likelihood = _LIK[self.likelihood]
         c.precision = _PREC[self.precision]
         c.proposal = _PROP[self.proposal]
@@ -103,7 +116,7 @@ class SMCSampler:
             tp = _dev(theta0, torch.float32, "theta0")
             if tuple(theta0.shape) != (self.J, self.D):
                 raise ValueError("theta0 must be [J x D]")
-        F = cfg.widths[0] * cfg.widths[1] * cfg.widths[2] if cfg.model == "cnn" else cfg.widths[0]
+        F = cfg.widths[0] * cfg.widths[1] * cfg.widths[2] if cfg.model in ("cnn", "lenet") else cfg.widths[0]
         if X.dim() != 2 or X.shape[1] != F:
             raise ValueError("X has the wrong number of features")
         self.N = X.shape[0]
