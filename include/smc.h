@@ -100,7 +100,7 @@ enum { SMC_RESAMPLE_IF_NEEDED = 0, SMC_RESAMPLE_ALWAYS = 1, SMC_RESAMPLE_NEVER =
  * on H x W images with Cin channels stored channel-last.  n_layers = 5 and widths = {H, W,
  * Cin, k, C1, C2, F1, F2, n_cls}; {28, 28, 1, 5, 6, 16, 120, 84, 10} is LeNet-5 with
  * D = 61,706.  Limits: k = 3 or 5, H and W even, (H/2 - k + 1) and (W/2 - k + 1) even and
- * >= 2, Cin and C1 <= 8, ceil(C2/2) k^2 <= 256, F1 and F2 multiples of 4, 2 <= n_cls <= 16,
+ * >= 2, Cin and C1 <= 8, ceil(C2/2) C1 k <= 256, F1 and F2 multiples of 4, 2 <= n_cls <= 16,
  * FP32 operands, categorical likelihood, the fixed proposal.  Parameter blocks, each
  * output unit's weights followed by its bias: conv1 [C1 x (k^2 Cin + 1)] with weight index
  * (ky*k + kx)*Cin + c, conv2 [C2 x (k^2 C1 + 1)] with index (ky*k + kx)*C1 + c, dense1

@@ -120,7 +120,7 @@ struct LenetDims {
   int K1 = 0, K2 = 0;  // k k Cin, k k C1
   int F = 0;           // Hq Wq C2
   int Dconv = 0;       // C1 (K1 + 1) + C2 (K2 + 1): the conv blocks at the start of each theta row
-  int ns1 = 1;         // pixel slices of the conv1 weight-gradient items
+  int ns1 = 1;         // row slices of the conv1 weight-gradient items
 };
 size_t lenet_smem_bytes(const LenetDims& d, bool bwd);
 // feat[j][n][f] (stride sF per particle) and, if featT, featT[j][f][n] ([(F+1) x ldT] per

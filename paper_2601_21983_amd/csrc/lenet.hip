@@ -28,38 +28,58 @@ namespace {
 
 constexpr int LT = 256;  // threads per workgroup
 
+// LDS regions.  Maps are planar ([channel][row][col]); the conv weights are stored
+// [out][in][ky][kx] with the biases apart, so that an item's weight reads for one
+// (out, in) pair sit at compile-time offsets from one base.
 struct LenetSmem {
-  float *wl, *xin, *a1, *p1, *a2, *dp1, *g1s;
+  float *w1, *b1, *w2, *b2, *xin, *a1, *p1, *a2, *dp1, *g1s;
 };
 
-// LDS carve-up (floats); the forward uses wl, xin, p1 only
 __host__ __device__ inline int lenet_smem_floats(const LenetDims& d, bool bwd, int* offs) {
-  const int Hpd = d.H + 2 * d.pad, Wpd = d.W + 2 * d.pad;
+  const int Hpd = d.H + 2 * d.pad, Wpd = d.W + 2 * d.pad, kk = d.k * d.k;
+  const int g1s = d.ns1 * d.C1 * (d.K1 + 1);
   int n = 0;
   auto take = [&](int q, int cnt) {
     if (offs) offs[q] = n;
     n += (cnt + 3) & ~3;
   };
-  take(0, d.Dconv);
-  take(1, Hpd * Wpd * d.Cin);
-  take(2, bwd ? d.H * d.W * d.C1 : 0);
-  take(3, d.Hp * d.Wp * d.C1);
-  take(4, bwd ? d.H2 * d.W2 * d.C2 : 0);
-  take(5, bwd ? d.Hp * d.Wp * d.C1 : 0);
-  take(6, bwd ? d.ns1 * d.C1 * (d.K1 + 1) : 0);
+  take(0, d.C1 * d.Cin * kk);
+  take(1, d.C1);
+  take(2, d.C2 * d.C1 * kk);
+  take(3, d.C2);
+  take(4, Hpd * Wpd * d.Cin);
+  // a1 also holds the conv1 gradient's slice partials once the last image is done
+  take(5, bwd ? (d.H * d.W * d.C1 > g1s ? d.H * d.W * d.C1 : g1s) : 0);
+  take(6, d.Hp * d.Wp * d.C1);
+  take(7, bwd ? d.H2 * d.W2 * d.C2 : 0);
+  take(8, bwd ? d.Hp * d.Wp * d.C1 : 0);
   return n;
 }
 
 __device__ inline LenetSmem lenet_smem(float* base, const LenetDims& d, bool bwd) {
-  int o[7];
+  int o[9];
   lenet_smem_floats(d, bwd, o);
-  return LenetSmem{base + o[0], base + o[1], base + o[2], base + o[3], base + o[4], base + o[5], base + o[6]};
+  return LenetSmem{base + o[0], base + o[1], base + o[2], base + o[3], base + o[4],
+                   base + o[5], base + o[6], base + o[7], base + o[8], base + o[5]};
+}
+
+// tanh from the exponential: 1 - 2 / (e^{2|z|} + 1) with the sign of z, and its Taylor series
+// z - z^3/3 + 2 z^5/15 - 17 z^7/315 for |z| < 1/8, where the subtraction would cancel
+// (truncation error below 2e-10 there)
+__device__ __forceinline__ float tanh_exp(float z) {
+  const float a = fabsf(z);
+  if (a < 0.125f) {
+    const float z2 = z * z;
+    return z * fmaf(z2, fmaf(z2, fmaf(z2, -17.0f / 315.0f, 2.0f / 15.0f), -1.0f / 3.0f), 1.0f);
+  }
+  const float t = 1.0f - 2.0f / (__expf(2.0f * a) + 1.0f);
+  return copysignf(t, z);
 }
 
 template <int ACT>
 __device__ __forceinline__ float actf(float z) {
   if constexpr (ACT == ACT_RELU) return fmaxf(z, 0.0f);
-  else return tanhf(z);
+  else return tanh_exp(z);
 }
 template <int ACT>
 __device__ __forceinline__ float actg(float a) {
@@ -67,73 +87,91 @@ __device__ __forceinline__ float actg(float a) {
   else return 1.0f - a * a;
 }
 
-// Particle j's two conv blocks into LDS (contiguous at the start of its theta row).
-__device__ inline void load_conv_weights(const float* theta, int64_t D, int j, const LenetDims& d, float* wl) {
+// Particle j's conv blocks (theta layout [out][(ky k + kx) in + c | bias]) into the LDS layout.
+__device__ inline void load_conv_weights(const float* theta, int64_t D, int j, const LenetDims& d, const LenetSmem& S) {
   const float* src = theta + (int64_t)j * D;
-  for (int e = threadIdx.x; e < d.Dconv; e += LT) wl[e] = src[e];
-}
-
-// Image n (global sample row c0 + n) into xin with a zero border of pad pixels.
-__device__ inline void load_image(const float* X, int64_t xld, int64_t row, const LenetDims& d, float* xin) {
-  const int Hpd = d.H + 2 * d.pad, Wpd = d.W + 2 * d.pad, tot = Hpd * Wpd * d.Cin;
-  const float* src = X + row * xld;
-  for (int e = threadIdx.x; e < tot; e += LT) {
-    const int pix = e / d.Cin, c = e - pix * d.Cin;
-    const int y = pix / Wpd - d.pad, x = pix - (pix / Wpd) * Wpd - d.pad;
-    xin[e] = (y >= 0 && y < d.H && x >= 0 && x < d.W) ? src[(y * d.W + x) * d.Cin + c] : 0.0f;
+  const int kk = d.k * d.k, r1 = d.K1 + 1, r2 = d.K2 + 1, n1 = d.C1 * r1;
+  for (int e = threadIdx.x; e < d.Dconv; e += LT) {
+    const float v = src[e];
+    const bool first = e < n1;
+    const int cin = first ? d.Cin : d.C1, rl = first ? r1 : r2;
+    const int ee = first ? e : e - n1;
+    const int o = ee / rl, r = ee - o * rl;
+    if (r == rl - 1) {
+      (first ? S.b1 : S.b2)[o] = v;
+    } else {
+      const int tap = r / cin, c = r - tap * cin;
+      (first ? S.w1 : S.w2)[(o * cin + c) * kk + tap] = v;
+    }
   }
 }
 
-// Convolution + activation + 2x2 average pool over an LDS input of row length win pixels and
-// cin channels, for output channels cout with weights w[cout][K+1] (K = k k cin, bias last).
-// Item e = (channel pair, pooled pixel), pixels fastest.  The input rows of an item's
-// (k+1) x (k+1) window are read once into registers.  Writes pooled[q][c] through `pool`
-// (q = pooled pixel, c = channel) and, if act_out, the activations act_out[y][x][c] of the
-// conv output (row length 2 Wo).
+// Image (global sample row `row`) into the planar xin [Cin][Hpd][Wpd] with a zero border.
+__device__ inline void load_image(const float* X, int64_t xld, int64_t row, const LenetDims& d, float* xin) {
+  const int Hpd = d.H + 2 * d.pad, Wpd = d.W + 2 * d.pad, plane = Hpd * Wpd;
+  const float* src = X + row * xld;
+  for (int e = threadIdx.x; e < plane * d.Cin; e += LT) {
+    const int pix = e / d.Cin, c = e - pix * d.Cin;  // read the image pixel-major (contiguous)
+    const int yy = pix / Wpd, xx = pix - yy * Wpd;
+    const int y = yy - d.pad, x = xx - d.pad;
+    xin[c * plane + pix] = (y >= 0 && y < d.H && x >= 0 && x < d.W) ? src[(y * d.W + x) * d.Cin + c] : 0.0f;
+  }
+}
+
+// Convolution + activation + 2x2 average pool over the planar LDS input `in` ([cin][.][win],
+// plane stride `plane`) for cout output channels (weights w [cout][cin][KS][KS], biases b).
+// Item e = (channel pair, pooled pixel), pixels fastest, so the weight reads of a wave are
+// broadcasts.  Each input row of an item's (KS+1)^2 window is read once.  Writes the pooled
+// value through pool(q, c, v) (q = pooled pixel) and, if act_out, the activations
+// act_out[c][y][x] (planar, 2Ho x 2Wo).
 template <int KS, int ACT, typename PoolW>
-__device__ __forceinline__ void conv_act_pool(const float* in, int win, int cin, const float* w, int cout, int Ho,
-                                              int Wo, float* act_out, PoolW pool) {
-  constexpr int K1 = KS + 1;
-  const int K = KS * KS * cin, nq = Ho * Wo, ncp = (cout + 1) / 2;
+__device__ __forceinline__ void conv_act_pool(const float* in, int plane, int win, int cin, const float* w,
+                                              const float* b, int cout, int Ho, int Wo, float* act_out, PoolW pool) {
+  constexpr int K1 = KS + 1, KK = KS * KS;
+  const int nq = Ho * Wo, ncp = (cout + 1) / 2;
   for (int e = threadIdx.x; e < ncp * nq; e += LT) {
     const int cp = e / nq, q = e - cp * nq;
     const int c0 = 2 * cp;
     const bool two = c0 + 1 < cout;
     const int py = q / Wo, px = q - py * Wo;
-    const float* w0 = w + c0 * (K + 1);
-    const float* w1 = two ? w0 + (K + 1) : w0;
+    const float* wa = w + c0 * cin * KK;
+    const float* wb = two ? wa + cin * KK : wa;
     float acc[2][2][2];
+    const float ba = b[c0], bb = two ? b[c0 + 1] : 0.0f;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        acc[a][b][0] = w0[K];
-        acc[a][b][1] = w1[K];
+      for (int v = 0; v < 2; ++v) {
+        acc[u][v][0] = ba;
+        acc[u][v][1] = bb;
       }
+    const float* ib = in + 2 * py * win + 2 * px;
     for (int ci = 0; ci < cin; ++ci) {
+      const float* ip = ib + ci * plane;
+      const float* wca = wa + ci * KK;
+      const float* wcb = wb + ci * KK;
 #pragma unroll
       for (int iy = 0; iy < K1; ++iy) {
         float r[K1];
-        const float* row = in + ((2 * py + iy) * win + 2 * px) * cin + ci;
 #pragma unroll
-        for (int ix = 0; ix < K1; ++ix) r[ix] = row[ix * cin];
+        for (int ix = 0; ix < K1; ++ix) r[ix] = ip[iy * win + ix];
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
           const int ky = iy - dy;
           if (ky < 0 || ky >= KS) continue;
 #pragma unroll
           for (int kx = 0; kx < KS; ++kx) {
-            const int t = (ky * KS + kx) * cin + ci;
-            const float v0 = w0[t], v1 = w1[t];
+            const float va = wca[ky * KS + kx], vb = wcb[ky * KS + kx];
 #pragma unroll
             for (int dx = 0; dx < 2; ++dx) {
-              acc[dy][dx][0] = fmaf(r[kx + dx], v0, acc[dy][dx][0]);
-              acc[dy][dx][1] = fmaf(r[kx + dx], v1, acc[dy][dx][1]);
+              acc[dy][dx][0] = fmaf(r[kx + dx], va, acc[dy][dx][0]);
+              acc[dy][dx][1] = fmaf(r[kx + dx], vb, acc[dy][dx][1]);
             }
           }
         }
       }
     }
+    const int oplane = 4 * nq;
 #pragma unroll
     for (int ch = 0; ch < 2; ++ch) {
       if (ch == 1 && !two) break;
@@ -144,7 +182,7 @@ __device__ __forceinline__ void conv_act_pool(const float* in, int win, int cin,
         for (int dx = 0; dx < 2; ++dx) {
           const float a = actf<ACT>(acc[dy][dx][ch]);
           s += a;
-          if (act_out) act_out[((2 * py + dy) * (2 * Wo) + 2 * px + dx) * cout + c0 + ch] = a;
+          if (act_out) act_out[(c0 + ch) * oplane + (2 * py + dy) * (2 * Wo) + 2 * px + dx] = a;
         }
       pool(q, c0 + ch, 0.25f * s);
     }
@@ -162,8 +200,8 @@ __global__ __launch_bounds__(LT) void lenet_fwd_kernel(const float* __restrict__
   const int n0 = blockIdx.x * ipb, n1 = min(n0 + ipb, rows);
   float* fj = feat + (int64_t)j * sF;
   float* fTj = featT ? featT + (int64_t)j * (d.F + 1) * ldT : nullptr;
-  load_conv_weights(theta, D, j, d, S.wl);
-  const float* w2 = S.wl + d.C1 * (d.K1 + 1);
+  load_conv_weights(theta, D, j, d, S);
+  const int Wpd = d.W + 2 * d.pad, P0 = (d.H + 2 * d.pad) * Wpd, P1 = d.Hp * d.Wp;
   for (int n = n0; n < n1; ++n) {
     if (n >= mcv) {
       // rows past the chunk's samples feed the dense GEMMs: keep them zero
@@ -173,16 +211,15 @@ __global__ __launch_bounds__(LT) void lenet_fwd_kernel(const float* __restrict__
       }
       continue;
     }
-    __syncthreads();  // the previous image's readers are done with xin and p1
+    __syncthreads();  // the weights are in; the previous image's readers are done with xin and p1
     load_image(X, xld, c0 + n, d, S.xin);
     __syncthreads();
     float* p1 = S.p1;
-    const int C1 = d.C1;
-    conv_act_pool<KS, ACT>(S.xin, d.W + 2 * d.pad, d.Cin, S.wl, d.C1, d.Hp, d.Wp, nullptr,
-                           [&](int q, int c, float v) { p1[q * C1 + c] = v; });
+    conv_act_pool<KS, ACT>(S.xin, P0, Wpd, d.Cin, S.w1, S.b1, d.C1, d.Hp, d.Wp, nullptr,
+                           [&](int q, int c, float v) { p1[c * P1 + q] = v; });
     __syncthreads();
     const int C2 = d.C2;
-    conv_act_pool<KS, ACT>(p1, d.Wp, d.C1, w2, d.C2, d.Hq, d.Wq, nullptr, [&](int q, int c, float v) {
+    conv_act_pool<KS, ACT>(p1, P1, d.Wp, d.C1, S.w2, S.b2, d.C2, d.Hq, d.Wq, nullptr, [&](int q, int c, float v) {
       const int f = q * C2 + c;
       fj[(int64_t)n * d.F + f] = v;
       if (fTj) fTj[(int64_t)f * ldT + n] = v;
@@ -199,29 +236,27 @@ __global__ __launch_bounds__(LT) void lenet_bwd_kernel(const float* __restrict__
   const LenetSmem S = lenet_smem(lsm, d, true);
   const int j = blockIdx.y, tid = threadIdx.x;
   const int n0 = blockIdx.x * ipb, n1 = min(n0 + ipb, mcv);
-  load_conv_weights(theta, D, j, d, S.wl);
-  const float* w2 = S.wl + d.C1 * (d.K1 + 1);
-  const int Wpd = d.W + 2 * d.pad, C1 = d.C1, C2 = d.C2, Cin = d.Cin;
+  load_conv_weights(theta, D, j, d, S);
   constexpr int KK = KS * KS;
-  // conv2 weight-gradient item: channel pair cp2 = tid / KK, tap t2 = tid % KK (all C1 inputs)
-  const int cp2 = tid / KK, t2 = tid - cp2 * KK;
-  const bool own2 = cp2 < (C2 + 1) / 2;
-  const int o2 = 2 * cp2;
+  const int Wpd = d.W + 2 * d.pad, P0 = (d.H + 2 * d.pad) * Wpd;
+  const int HW = d.H * d.W, P1 = d.Hp * d.Wp, P2 = d.H2 * d.W2;
+  const int C1 = d.C1, C2 = d.C2, Cin = d.Cin;
+  // conv2 weight-gradient item (output pair o2, input channel c2i, kernel row ky2): KS
+  // accumulators per output, a sweep over the rows of the conv2 output
+  const int i2 = tid / KS, ky2 = tid - i2 * KS, o2 = 2 * (i2 / C1), c2i = i2 - (i2 / C1) * C1;
+  const bool own2 = o2 < C2;
   const bool two2 = o2 + 1 < C2;
-  const int ky2 = t2 / KS, kx2 = t2 - ky2 * KS;
-  float g2[2][LENET_CMAX], gb2[2] = {0.0f, 0.0f};
-  // conv1 weight-gradient item: (channel pair, tap, slice of the pixels)
-  const int n1i = (C1 + 1) / 2 * KK;
-  const int s1 = tid / n1i, r1 = tid - s1 * n1i, cp1 = r1 / KK, t1 = r1 - cp1 * KK;
+  // conv1 weight-gradient item (output pair o1, input channel c1i, kernel row ky1, row slice s1)
+  const int n1i = (C1 + 1) / 2 * Cin * KS;
+  const int s1 = tid / n1i, r1 = tid - s1 * n1i;
+  const int i1 = r1 / KS, ky1 = r1 - i1 * KS, o1 = 2 * (i1 / Cin), c1i = i1 - (i1 / Cin) * Cin;
   const bool own1 = s1 < d.ns1;
-  const int o1 = 2 * cp1;
   const bool two1 = o1 + 1 < C1;
-  const int ky1 = t1 / KS, kx1 = t1 - ky1 * KS;
-  const int HW = d.H * d.W, span1 = (HW + d.ns1 - 1) / d.ns1;
-  const int pa = min(HW, s1 * span1), pb = min(HW, pa + span1);
-  float g1[2][LENET_CMAX], gb1[2] = {0.0f, 0.0f};
+  const int span1 = (d.H + d.ns1 - 1) / d.ns1;
+  const int ya = min(d.H, s1 * span1), yb = min(d.H, ya + span1);
+  float g2[2][KS], g1[2][KS], gb2[2] = {0.0f, 0.0f}, gb1[2] = {0.0f, 0.0f};
 #pragma unroll
-  for (int c = 0; c < LENET_CMAX; ++c) g1[0][c] = g1[1][c] = g2[0][c] = g2[1][c] = 0.0f;
+  for (int kx = 0; kx < KS; ++kx) g1[0][kx] = g1[1][kx] = g2[0][kx] = g2[1][kx] = 0.0f;
 
   const float* dfj = dfeat + (int64_t)j * sF;
   for (int n = n0; n < n1; ++n) {
@@ -230,94 +265,116 @@ __global__ __launch_bounds__(LT) void lenet_bwd_kernel(const float* __restrict__
     __syncthreads();
     // forward again, keeping the activations
     float* p1 = S.p1;
-    conv_act_pool<KS, ACT>(S.xin, Wpd, Cin, S.wl, C1, d.Hp, d.Wp, S.a1,
-                           [&](int q, int c, float v) { p1[q * C1 + c] = v; });
+    conv_act_pool<KS, ACT>(S.xin, P0, Wpd, Cin, S.w1, S.b1, C1, d.Hp, d.Wp, S.a1,
+                           [&](int q, int c, float v) { p1[c * P1 + q] = v; });
     __syncthreads();
-    conv_act_pool<KS, ACT>(p1, d.Wp, C1, w2, C2, d.Hq, d.Wq, S.a2, [](int, int, float) {});
+    conv_act_pool<KS, ACT>(p1, P1, d.Wp, C1, S.w2, S.b2, C2, d.Hq, d.Wq, S.a2, [](int, int, float) {});
     __syncthreads();
-    // dz2 = unpool(dfeat) * act'(a2), in place
-    for (int e = tid; e < d.H2 * d.W2 * C2; e += LT) {
-      const int pix = e / C2, c = e - pix * C2;
+    // dz2 = unpool(dfeat) * act'(a2), in place (planar)
+    for (int e = tid; e < C2 * P2; e += LT) {
+      const int c = e / P2, pix = e - c * P2;
       const int y = pix / d.W2, x = pix - y * d.W2;
       const float g = dfj[(int64_t)n * d.F + ((y >> 1) * d.Wq + (x >> 1)) * C2 + c];
       S.a2[e] = 0.25f * g * actg<ACT>(S.a2[e]);
     }
     __syncthreads();
     const float* dz2 = S.a2;
-    // conv2 weight gradient: sum over output pixels of dz2[pix][o] * p1[pix + tap][c]
+    // conv2 weight gradient: sum over conv2 output pixels of dz2[o][y][x] p1[c][y + ky][x + kx]
     if (own2) {
-      for (int pix = 0; pix < d.H2 * d.W2; ++pix) {
-        const int y = pix / d.W2, x = pix - y * d.W2;
-        const float e0 = dz2[pix * C2 + o2], e1 = two2 ? dz2[pix * C2 + o2 + 1] : 0.0f;
-        if (t2 == 0) {
-          gb2[0] += e0;
-          gb2[1] += e1;
-        }
-        const float* src = p1 + ((y + ky2) * d.Wp + x + kx2) * C1;
-#pragma unroll
-        for (int c = 0; c < LENET_CMAX; ++c)
-          if (c < C1) {
-            g2[0][c] = fmaf(e0, src[c], g2[0][c]);
-            g2[1][c] = fmaf(e1, src[c], g2[1][c]);
+      const float* e0r = dz2 + o2 * P2;
+      const float* e1r = two2 ? e0r + P2 : e0r;
+      const float* pr = p1 + c2i * P1 + ky2 * d.Wp;
+      const bool bias = c2i == 0 && ky2 == 0;
+      for (int y = 0; y < d.H2; ++y) {
+        for (int x = 0; x < d.W2; ++x) {
+          const float e0 = e0r[y * d.W2 + x], e1 = e1r[y * d.W2 + x];
+          if (bias) {
+            gb2[0] += e0;
+            gb2[1] += e1;
           }
+#pragma unroll
+          for (int kx = 0; kx < KS; ++kx) {
+            const float v = pr[y * d.Wp + x + kx];
+            g2[0][kx] = fmaf(e0, v, g2[0][kx]);
+            g2[1][kx] = fmaf(e1, v, g2[1][kx]);
+          }
+        }
       }
     }
-    // error of the pooled conv1 map: dp1[pix][c] = sum over taps and o of dz2[pix - tap][o] w2[o][tap][c]
-    for (int pix = tid; pix < d.Hp * d.Wp; pix += LT) {
-      const int y = pix / d.Wp, x = pix - y * d.Wp;
-      float acc[LENET_CMAX];
+    // error of the pooled conv1 map: dp1[c][y][x] = sum over taps and o of dz2[o][y - ky][x - kx] w2[o][c][ky][kx].
+    // The tap loops run in full for every lane (out-of-range taps read a clamped address and
+    // contribute zero), so their weight addresses are uniform and come from the particle's
+    // global row through the scalar cache.
+    {
+      typedef const __attribute__((address_space(4))) float* cfloat_p;  // read-only: scalar loads
+      const cfloat_p w2g = (cfloat_p)(theta + (int64_t)j * D + C1 * (d.K1 + 1));  // rows [o][tap C1 + c | bias]
+      for (int base = 0; base < P1; base += LT) {  // uniform trip count: lanes past P1 repeat the last pixel
+        const int pix = min(base + tid, P1 - 1);
+        const int y = pix / d.Wp, x = pix - y * d.Wp;
+        float acc[LENET_CMAX];
 #pragma unroll
-      for (int c = 0; c < LENET_CMAX; ++c) acc[c] = 0.0f;
-      for (int ky = 0; ky < KS; ++ky) {
-        const int yy = y - ky;
-        if (yy < 0 || yy >= d.H2) continue;
-        for (int kx = 0; kx < KS; ++kx) {
-          const int xx = x - kx;
-          if (xx < 0 || xx >= d.W2) continue;
-          const float* e = dz2 + (yy * d.W2 + xx) * C2;
-          const float* wt = w2 + (ky * KS + kx) * C1;
-          for (int o = 0; o < C2; ++o) {
-            const float ev = e[o];
-            const float* wr = wt + o * (d.K2 + 1);
+        for (int c = 0; c < LENET_CMAX; ++c) acc[c] = 0.0f;
+        for (int o = 0; o < C2; ++o) {
+          const float* eo = dz2 + o * P2;
+          const cfloat_p wo = w2g + o * (d.K2 + 1);
 #pragma unroll
-            for (int c = 0; c < LENET_CMAX; ++c)
-              if (c < C1) acc[c] = fmaf(ev, wr[c], acc[c]);
+          for (int ky = 0; ky < KS; ++ky) {
+            const int yy = y - ky;
+            const bool vy = yy >= 0 && yy < d.H2;
+            const int yc = vy ? yy : 0;
+#pragma unroll
+            for (int kx = 0; kx < KS; ++kx) {
+              const int xx = x - kx;
+              const bool v = vy && xx >= 0 && xx < d.W2;
+              const float ev = eo[yc * d.W2 + (v ? xx : 0)];
+              const float e = v ? ev : 0.0f;
+              const cfloat_p wt = wo + (ky * KS + kx) * C1;
+#pragma unroll
+              for (int c = 0; c < LENET_CMAX; ++c)
+                if (c < C1) acc[c] = fmaf(e, wt[c], acc[c]);
+            }
           }
         }
-      }
+        if (base + tid < P1) {
 #pragma unroll
-      for (int c = 0; c < LENET_CMAX; ++c)
-        if (c < C1) S.dp1[pix * C1 + c] = acc[c];
+          for (int c = 0; c < LENET_CMAX; ++c)
+            if (c < C1) S.dp1[c * P1 + pix] = acc[c];
+        }
+      }
     }
     __syncthreads();
-    // dz1 = unpool(dp1) * act'(a1), in place
-    for (int e = tid; e < HW * C1; e += LT) {
-      const int pix = e / C1, c = e - pix * C1;
+    // dz1 = unpool(dp1) * act'(a1), in place (planar)
+    for (int e = tid; e < C1 * HW; e += LT) {
+      const int c = e / HW, pix = e - c * HW;
       const int y = pix / d.W, x = pix - y * d.W;
-      S.a1[e] = 0.25f * S.dp1[((y >> 1) * d.Wp + (x >> 1)) * C1 + c] * actg<ACT>(S.a1[e]);
+      S.a1[e] = 0.25f * S.dp1[c * P1 + (y >> 1) * d.Wp + (x >> 1)] * actg<ACT>(S.a1[e]);
     }
     __syncthreads();
-    // conv1 weight gradient over this item's slice of pixels
+    // conv1 weight gradient over this item's slice of rows
     if (own1) {
-      const float* dz1 = S.a1;
-      for (int pix = pa; pix < pb; ++pix) {
-        const int y = pix / d.W, x = pix - y * d.W;
-        const float e0 = dz1[pix * C1 + o1], e1 = two1 ? dz1[pix * C1 + o1 + 1] : 0.0f;
-        if (t1 == 0) {
-          gb1[0] += e0;
-          gb1[1] += e1;
-        }
-        const float* src = S.xin + ((y + ky1) * Wpd + x + kx1) * Cin;
-#pragma unroll
-        for (int c = 0; c < LENET_CMAX; ++c)
-          if (c < Cin) {
-            g1[0][c] = fmaf(e0, src[c], g1[0][c]);
-            g1[1][c] = fmaf(e1, src[c], g1[1][c]);
+      const float* e0r = S.a1 + o1 * HW;
+      const float* e1r = two1 ? e0r + HW : e0r;
+      const float* xr = S.xin + c1i * P0 + ky1 * Wpd;
+      const bool bias = c1i == 0 && ky1 == 0;
+      for (int y = ya; y < yb; ++y) {
+        for (int x = 0; x < d.W; ++x) {
+          const float e0 = e0r[y * d.W + x], e1 = e1r[y * d.W + x];
+          if (bias) {
+            gb1[0] += e0;
+            gb1[1] += e1;
           }
+#pragma unroll
+          for (int kx = 0; kx < KS; ++kx) {
+            const float v = xr[y * Wpd + x + kx];
+            g1[0][kx] = fmaf(e0, v, g1[0][kx]);
+            g1[1][kx] = fmaf(e1, v, g1[1][kx]);
+          }
+        }
       }
     }
   }
-  // the block's partial: conv2 items directly, conv1 slices summed in order through LDS
+  // the block's partial in the theta layout: conv2 items directly, conv1 row slices summed in
+  // order through LDS (the a1 region, free now)
   float* pj = part + ((int64_t)j * gridDim.x + blockIdx.x) * d.Dconv;
   float* pw2 = pj + C1 * (d.K1 + 1);
   if (own2) {
@@ -325,9 +382,8 @@ __global__ __launch_bounds__(LT) void lenet_bwd_kernel(const float* __restrict__
       if (h == 1 && !two2) break;
       float* row = pw2 + (o2 + h) * (d.K2 + 1);
 #pragma unroll
-      for (int c = 0; c < LENET_CMAX; ++c)
-        if (c < C1) row[t2 * C1 + c] = g2[h][c];
-      if (t2 == 0) row[d.K2] = gb2[h];
+      for (int kx = 0; kx < KS; ++kx) row[(ky2 * KS + kx) * C1 + c2i] = g2[h][kx];
+      if (c2i == 0 && ky2 == 0) row[d.K2] = gb2[h];
     }
   }
   __syncthreads();
@@ -337,9 +393,8 @@ __global__ __launch_bounds__(LT) void lenet_bwd_kernel(const float* __restrict__
       if (h == 1 && !two1) break;
       float* row = gs + (o1 + h) * (d.K1 + 1);
 #pragma unroll
-      for (int c = 0; c < LENET_CMAX; ++c)
-        if (c < Cin) row[t1 * Cin + c] = g1[h][c];
-      if (t1 == 0) row[d.K1] = gb1[h];
+      for (int kx = 0; kx < KS; ++kx) row[(ky1 * KS + kx) * Cin + c1i] = g1[h][kx];
+      if (c1i == 0 && ky1 == 0) row[d.K1] = gb1[h];
     }
   }
   __syncthreads();

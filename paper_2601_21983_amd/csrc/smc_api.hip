@@ -292,8 +292,9 @@ LenetDims lenet_dims(const int32_t* w) {
   d.K1 = d.k * d.k * d.Cin, d.K2 = d.k * d.k * d.C1;
   d.F = d.Hq * d.Wq * d.C2;
   d.Dconv = d.C1 * (d.K1 + 1) + d.C2 * (d.K2 + 1);
-  // conv1 weight-gradient items (channel pair, tap) replicated over pixel slices to fill 256 threads
-  d.ns1 = std::max(1, 256 / (((d.C1 + 1) / 2) * d.k * d.k));
+  // conv1 weight-gradient items (channel pair, input channel, kernel row) replicated over
+  // slices of the image rows to fill 256 threads
+  d.ns1 = std::max(1, 256 / (((d.C1 + 1) / 2) * d.Cin * d.k));
   return d;
 }
 
@@ -308,7 +309,7 @@ void check_lenet(const smc_config* c) {
   if (d.H2 < 2 || d.W2 < 2 || d.H2 % 2 || d.W2 % 2)
     fail(SMC_ERR_UNSUPPORTED, "the second convolution's output (H/2 - k + 1, W/2 - k + 1) must be even and >= 2");
   if (d.Cin > LENET_CMAX || d.C1 > LENET_CMAX) fail(SMC_ERR_UNSUPPORTED, "LeNet Cin and C1 must be at most 8");
-  if ((d.C2 + 1) / 2 * d.k * d.k > 256) fail(SMC_ERR_UNSUPPORTED, "LeNet needs ceil(C2/2) k^2 <= 256");
+  if ((d.C2 + 1) / 2 * d.C1 * d.k > 256) fail(SMC_ERR_UNSUPPORTED, "LeNet needs ceil(C2/2) C1 k <= 256");
   if (d.F % 4 || w[6] % 4 || w[7] % 4) fail(SMC_ERR_UNSUPPORTED, "LeNet F, F1 and F2 must be multiples of 4");
   if (lenet_smem_bytes(d, true) > 65536) fail(SMC_ERR_UNSUPPORTED, "LeNet image too large for the convolution kernels");
   if (w[8] < 2 || w[8] > 16) fail(SMC_ERR_UNSUPPORTED, "categorical likelihood needs 2..16 classes");
