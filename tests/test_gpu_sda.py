@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from gpu_helpers import bf16_round, cuda, lib, print_case, rel_err, to_dev, torch
-from oracle import cnn, mlp, sda, smc
+from oracle import cnn, lenet, mlp, sda, smc
 import smc_inputs
 
 pytestmark = pytest.mark.gpu
@@ -22,6 +22,7 @@ CASES = [
     ([2, 16, 2], "mlp", "tanh", "fp32", 16, 200, 75, 150, 75, 2.0, 0.25, 0),
     ((8, 8, 3, 8, 8, 3), "cnn", "relu", "fp32", 4, 40, 17, 30, 17, 1.0, 0.5, 400_000),
     ((8, 8, 3, 8, 8, 3), "cnn", "relu", "bf16", 4, 40, 17, 30, 17, 1.0, 0.5, 0),
+    ((28, 28, 1, 5, 6, 16, 120, 84, 10), "lenet", "tanh", "fp32", 4, 60, 20, 45, 20, 1.0, 0.4, 0),
 ]
 
 
@@ -30,7 +31,7 @@ def _data(widths, model, n, seed):
         H, W, Cin, _, _, ncls = widths
         rng = np.random.default_rng(seed)
         return rng.uniform(0, 1, (n, H * W * Cin)).astype(np.float32), rng.integers(0, ncls, n).astype(np.int32)
-    if widths[0] == 784:
+    if widths[0] == 784 or model == "lenet":
         X, y = smc_inputs.templates28(n, seed=seed)
     else:
         X, y = smc_inputs.blobs(n, seed=seed)
@@ -50,9 +51,12 @@ def test_tempered_target_vs_oracle(case):
     if model == "cnn":
         sh = cnn.CNNShape(*widths)
         D, omodel = sh.D, cnn.Model(sh)
+    elif model == "lenet":
+        sh = lenet.LeNetShape(*widths)
+        D, omodel = sh.D, lenet.Model(sh, act)
     else:
         D, omodel = mlp.n_params(widths), None
-    prior = 0.08 if model == "cnn" else (0.3 if widths[0] == 784 else 1.0)
+    prior = {"cnn": 0.08, "lenet": 0.2}.get(model, 0.3 if widths[0] == 784 else 1.0)
     th0 = smc_inputs.prior_draw(case + 70, J, D, prior)
     cfg = P.SMCConfig(widths=list(widths), n_particles=J, activation=act, precision=prec, model=model,
                       step_size=1e-3, prior_std=prior, act_budget_bytes=budget, seed=case)
@@ -65,7 +69,7 @@ def test_tempered_target_vs_oracle(case):
     st = g.state()
     th = st["theta"].cpu().numpy().astype(np.float64)
     Xo = bf16_round(X) if prec == "bf16x3" else X
-    o = smc.Sampler(Xo, y, None if model == "cnn" else widths, act, prior_std=prior, model=omodel)
+    o = smc.Sampler(Xo, y, None if omodel is not None else widths, act, prior_std=prior, model=omodel)
     ll, ll_b, grad = o.segment_loglik_grad(th, m, split, la, lb)
     lp = o.segment_log_target(ll, ll_b, th, la, lb)
     ll_g, lp_g, grad_g = st["loglik"].cpu().numpy(), st["logpi"].cpu().numpy(), st["grad"].cpu().numpy()
