@@ -62,3 +62,26 @@ def test_binding_names_match_header():
     assert sorted(_lib.EXPORTED) == _declared()
     for n in _declared():
         assert callable(getattr(_lib, n))
+
+
+def test_binding_constants_match_header_enums():
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    values = {}
+    for body in re.findall(r"enum\s*(?:[a-z_]+\s*)?\{([^}]*)\}", src):
+        for name, val in re.findall(r"(SMC_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            values[name] = int(val)
+    from paper_2601_21983_amd import _lib
+    checked = [n for n in values if hasattr(_lib, n)]
+    assert {"SMC_MODEL_MLP", "SMC_MODEL_CNN", "SMC_MODEL_LENET"} <= set(checked)
+    for n in checked:
+        assert getattr(_lib, n) == values[n], n
+
+
+def test_parameter_counts_match_the_oracle():
+    from oracle import cnn, lenet, mlp
+    from paper_2601_21983_amd.sampler import n_params
+    assert n_params(list(lenet.LENET5_MNIST), "lenet") == lenet.LeNetShape(*lenet.LENET5_MNIST).D == 61706
+    for shape in [(12, 12, 1, 5, 3, 4, 8, 8, 3), (12, 12, 2, 3, 3, 5, 8, 4, 3), (8, 12, 2, 3, 5, 6, 8, 4, 4)]:
+        assert n_params(list(shape), "lenet") == lenet.LeNetShape(*shape).D
+    assert n_params([32, 32, 3, 16, 32, 10], "cnn") == cnn.CNNShape(32, 32, 3, 16, 32, 10).D
+    assert n_params([784, 100, 10]) == mlp.n_params([784, 100, 10])
