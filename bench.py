@@ -69,6 +69,8 @@ def parse():
                     help="instead of the benchmark: the batching-scheme study on LeNet-5 (six schemes x LD/HMC)")
     ap.add_argument("--table1-k", type=int, default=TABLE1_K, help="iterations of each study run (the paper: 200)")
     ap.add_argument("--table1-moves", default="LD,HMC", help="moves of the study: LD, HMC or both")
+    ap.add_argument("--lenet-pass", action="store_true",
+                    help="instead of the benchmark: LeNet-5 gradient passes over the training set at J = 32 and 256")
     ap.add_argument("--sda-iters", type=int, default=SDA_MAX_ITERS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference kernel for HBM counters)")
@@ -385,6 +387,8 @@ def run_table1(P, dev, seed, K=TABLE1_K, moves=("LD", "HMC")):
                     s.resample()
                 evals += info["grad_evals"]
                 data += m
+                if k % 20 == 0:
+                    log(f"table1 {name} {move}: iteration {k}/{K}, M_k = {m}")
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             r = s.predict(dev["Xt"], dev["yt"])
@@ -409,6 +413,44 @@ def run_table1(P, dev, seed, K=TABLE1_K, moves=("LD", "HMC")):
                         f"C=kappa={C}, h={STEP}, HMC S=3, prior N(0, {TABLE1_PRIOR}^2), FP32 operands, "
                         f"systematic resampling",
             "runs": runs}
+
+
+# non-packed FP32 vector rate: 256 CUs x 64 FMA lanes per clock x 2 FLOP x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 78.6
+
+
+def run_lenet_pass(P, dev, J, reps=3):
+    """LeNet-5 gradient passes over the whole MNIST-shaped training set (60,000 images) at J
+    particles: per pass time, and the convolution stack's counted FLOPs per second against
+    the non-packed FP32 vector peak (HIP events on the library's stream)."""
+    import torch
+    cfg = P.SMCConfig(widths=LENET5, n_particles=J, model="lenet", activation="tanh", precision="fp32",
+                      step_size=STEP, prior_std=TABLE1_PRIOR)
+    s = P.SMCSampler(cfg, dev["X"], dev["y"], m0=N_TRAIN, lambda0=1.0)
+    th = s.state()["theta"]
+    s.nn_backward(th, N_TRAIN)
+    torch.cuda.synchronize()
+    s.profile(True)
+    s.profile_read()
+    t = time.perf_counter()
+    for _ in range(reps):
+        s.nn_backward(th, N_TRAIN)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    prof = s.profile_read()
+    mc = s.chunk_samples()
+    s.close()
+    classes = {k: {"ms_per_pass": round(v[0] / reps, 2), "launches_per_pass": v[1] // reps,
+                   "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 2) if v[0] > 0 and v[2] > 0 else None}
+               for k, v in prof.items() if v[1]}
+    conv = prof["other"]
+    achieved = conv[2] / (conv[0] * 1e-3) / 1e12
+    return {"workload": f"LeNet-5 (tanh, FP32, D=61706) gradient pass over {N_TRAIN} MNIST-shaped images, J={J}, "
+                        f"chunks of {mc} images", "ms_per_pass": round(dt * 1e3, 1),
+            "grad_evals_per_s": round(J * N_TRAIN / dt, 1),
+            "conv_stack": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VALU_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4)},
+            "classes": classes}
 
 
 def cpu_baseline(X, y, sizes, budget_s=12.0, J_s=8):
@@ -469,6 +511,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.lenet_pass:
+        for Jl in (TABLE1_J, 256):
+            print(json.dumps(run_lenet_pass(P, dev, Jl)), flush=True)
+        return
     if args.table1:
         moves = [m for m in args.table1_moves.split(",") if m]
         print(json.dumps(run_table1(P, dev, args.seed, args.table1_k, moves)), flush=True)

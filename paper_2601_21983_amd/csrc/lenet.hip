@@ -43,10 +43,11 @@ __host__ __device__ inline int lenet_smem_floats(const LenetDims& d, bool bwd, i
     if (offs) offs[q] = n;
     n += (cnt + 3) & ~3;
   };
-  take(0, d.C1 * d.Cin * kk);
-  take(1, d.C1);
-  take(2, d.C2 * d.C1 * kk);
-  take(3, d.C2);
+  // the backward reads no conv weights from LDS (its conv2 input error takes them through the scalar cache)
+  take(0, bwd ? 0 : d.C1 * d.Cin * kk);
+  take(1, bwd ? 0 : d.C1);
+  take(2, bwd ? 0 : d.C2 * d.C1 * kk);
+  take(3, bwd ? 0 : d.C2);
   take(4, Hpd * Wpd * d.Cin);
   // a1 also holds the conv1 gradient's slice partials once the last image is done
   take(5, bwd ? (d.H * d.W * d.C1 > g1s ? d.H * d.W * d.C1 : g1s) : 0);
@@ -193,7 +194,8 @@ template <int KS, int ACT>
 __global__ __launch_bounds__(LT) void lenet_fwd_kernel(const float* __restrict__ X, int64_t xld, int64_t c0, int mcv,
                                                        int rows, int ipb, LenetDims d, const float* __restrict__ theta,
                                                        int64_t D, float* __restrict__ feat, int64_t sF,
-                                                       float* __restrict__ featT, int64_t ldT) {
+                                                       float* __restrict__ featT, int64_t ldT, float* __restrict__ maps,
+                                                       int64_t sM) {
   extern __shared__ __attribute__((aligned(16))) float lsm[];
   const LenetSmem S = lenet_smem(lsm, d, false);
   const int j = blockIdx.y;
@@ -215,11 +217,16 @@ __global__ __launch_bounds__(LT) void lenet_fwd_kernel(const float* __restrict__
     load_image(X, xld, c0 + n, d, S.xin);
     __syncthreads();
     float* p1 = S.p1;
-    conv_act_pool<KS, ACT>(S.xin, P0, Wpd, d.Cin, S.w1, S.b1, d.C1, d.Hp, d.Wp, nullptr,
+    float* mn = maps ? maps + (int64_t)j * sM + (int64_t)n * d.Mimg : nullptr;  // a1 | p1 | a2 of this image
+    const int A1 = d.C1 * d.H * d.W;
+    conv_act_pool<KS, ACT>(S.xin, P0, Wpd, d.Cin, S.w1, S.b1, d.C1, d.Hp, d.Wp, mn,
                            [&](int q, int c, float v) { p1[c * P1 + q] = v; });
     __syncthreads();
+    if (mn)
+      for (int e = threadIdx.x; e < d.C1 * P1; e += LT) mn[A1 + e] = p1[e];
     const int C2 = d.C2;
-    conv_act_pool<KS, ACT>(p1, P1, d.Wp, d.C1, S.w2, S.b2, d.C2, d.Hq, d.Wq, nullptr, [&](int q, int c, float v) {
+    conv_act_pool<KS, ACT>(p1, P1, d.Wp, d.C1, S.w2, S.b2, d.C2, d.Hq, d.Wq, mn ? mn + A1 + d.C1 * P1 : nullptr,
+                           [&](int q, int c, float v) {
       const int f = q * C2 + c;
       fj[(int64_t)n * d.F + f] = v;
       if (fTj) fTj[(int64_t)f * ldT + n] = v;
@@ -231,13 +238,12 @@ template <int KS, int ACT>
 __global__ __launch_bounds__(LT) void lenet_bwd_kernel(const float* __restrict__ X, int64_t xld, int64_t c0, int mcv,
                                                        int ipb, LenetDims d, const float* __restrict__ theta, int64_t D,
                                                        const float* __restrict__ dfeat, int64_t sF,
+                                                       const float* __restrict__ maps, int64_t sM,
                                                        float* __restrict__ part) {
   extern __shared__ __attribute__((aligned(16))) float lsm[];
   const LenetSmem S = lenet_smem(lsm, d, true);
   const int j = blockIdx.y, tid = threadIdx.x;
   const int n0 = blockIdx.x * ipb, n1 = min(n0 + ipb, mcv);
-  load_conv_weights(theta, D, j, d, S);
-  constexpr int KK = KS * KS;
   const int Wpd = d.W + 2 * d.pad, P0 = (d.H + 2 * d.pad) * Wpd;
   const int HW = d.H * d.W, P1 = d.Hp * d.Wp, P2 = d.H2 * d.W2;
   const int C1 = d.C1, C2 = d.C2, Cin = d.Cin;
@@ -262,14 +268,16 @@ __global__ __launch_bounds__(LT) void lenet_bwd_kernel(const float* __restrict__
   for (int n = n0; n < n1; ++n) {
     __syncthreads();
     load_image(X, xld, c0 + n, d, S.xin);
+    // the activation maps the forward saved
+    {
+      const float* mn = maps + (int64_t)j * sM + (int64_t)n * d.Mimg;
+      const int A1 = C1 * HW;
+      for (int e = tid; e < A1; e += LT) S.a1[e] = mn[e];
+      for (int e = tid; e < C1 * P1; e += LT) S.p1[e] = mn[A1 + e];
+      for (int e = tid; e < C2 * P2; e += LT) S.a2[e] = mn[A1 + C1 * P1 + e];
+    }
     __syncthreads();
-    // forward again, keeping the activations
     float* p1 = S.p1;
-    conv_act_pool<KS, ACT>(S.xin, P0, Wpd, Cin, S.w1, S.b1, C1, d.Hp, d.Wp, S.a1,
-                           [&](int q, int c, float v) { p1[c * P1 + q] = v; });
-    __syncthreads();
-    conv_act_pool<KS, ACT>(p1, P1, d.Wp, C1, S.w2, S.b2, C2, d.Hq, d.Wq, S.a2, [](int, int, float) {});
-    __syncthreads();
     // dz2 = unpool(dfeat) * act'(a2), in place (planar)
     for (int e = tid; e < C2 * P2; e += LT) {
       const int c = e / P2, pix = e - c * P2;
@@ -421,19 +429,19 @@ __global__ void lenet_reduce_kernel(const float* __restrict__ part, int nblk, in
 template <int KS, int ACT>
 hipError_t launch_fwd(const float* X, int64_t xld, int64_t c0, int mcv, int rows, int ipb, const LenetDims& d,
                       const float* theta, int64_t D, int J, float* feat, int64_t sF, float* featT, int64_t ldT,
-                      size_t smem, hipStream_t s) {
+                      float* maps, int64_t sM, size_t smem, hipStream_t s) {
   const dim3 grid((unsigned)((rows + ipb - 1) / ipb), (unsigned)J);
   hipLaunchKernelGGL((lenet_fwd_kernel<KS, ACT>), grid, dim3(LT), smem, s, X, xld, c0, mcv, rows, ipb, d, theta, D,
-                     feat, sF, featT, ldT);
+                     feat, sF, featT, ldT, maps, sM);
   return hipGetLastError();
 }
 
 template <int KS, int ACT>
 hipError_t launch_bwd(const float* X, int64_t xld, int64_t c0, int mcv, int ipb, int nblk, const LenetDims& d,
-                      const float* theta, int64_t D, int J, const float* dfeat, int64_t sF, float* part, size_t smem,
-                      hipStream_t s) {
+                      const float* theta, int64_t D, int J, const float* dfeat, int64_t sF, const float* maps,
+                      int64_t sM, float* part, size_t smem, hipStream_t s) {
   hipLaunchKernelGGL((lenet_bwd_kernel<KS, ACT>), dim3((unsigned)nblk, (unsigned)J), dim3(LT), smem, s, X, xld, c0,
-                     mcv, ipb, d, theta, D, dfeat, sF, part);
+                     mcv, ipb, d, theta, D, dfeat, sF, maps, sM, part);
   return hipGetLastError();
 }
 
@@ -441,33 +449,44 @@ hipError_t launch_bwd(const float* X, int64_t xld, int64_t c0, int mcv, int ipb,
 
 size_t lenet_smem_bytes(const LenetDims& d, bool bwd) { return (size_t)lenet_smem_floats(d, bwd, nullptr) * 4; }
 
+int lenet_bwd_resident(const LenetDims& d, int act) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const void* f = d.k == 3 ? (act == ACT_RELU ? (const void*)lenet_bwd_kernel<3, ACT_RELU> : (const void*)lenet_bwd_kernel<3, ACT_TANH>)
+                           : (act == ACT_RELU ? (const void*)lenet_bwd_kernel<5, ACT_RELU> : (const void*)lenet_bwd_kernel<5, ACT_TANH>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, LT, lenet_smem_bytes(d, true)) != hipSuccess) return 0;
+  return ncu * per;
+}
+
 hipError_t lenet_fwd_run(const float* X, int64_t xld, int64_t c0, int mcv, int rows, int ipb, const LenetDims& d,
                          const float* theta, int64_t D, int J, int act, float* feat, int64_t sF, float* featT,
-                         int64_t ldT, hipStream_t s) {
+                         int64_t ldT, float* maps, int64_t sM, hipStream_t s) {
   if (rows <= 0 || J <= 0) return hipSuccess;
   if (ipb < 1 || mcv > rows || (d.k != 3 && d.k != 5)) return hipErrorInvalidValue;
   const size_t smem = lenet_smem_bytes(d, false);
-  if (d.k == 3)
-    return act == ACT_RELU ? launch_fwd<3, ACT_RELU>(X, xld, c0, mcv, rows, ipb, d, theta, D, J, feat, sF, featT, ldT, smem, s)
-                           : launch_fwd<3, ACT_TANH>(X, xld, c0, mcv, rows, ipb, d, theta, D, J, feat, sF, featT, ldT, smem, s);
-  return act == ACT_RELU ? launch_fwd<5, ACT_RELU>(X, xld, c0, mcv, rows, ipb, d, theta, D, J, feat, sF, featT, ldT, smem, s)
-                         : launch_fwd<5, ACT_TANH>(X, xld, c0, mcv, rows, ipb, d, theta, D, J, feat, sF, featT, ldT, smem, s);
+#define LENET_FWD(KS, ACT) \
+  launch_fwd<KS, ACT>(X, xld, c0, mcv, rows, ipb, d, theta, D, J, feat, sF, featT, ldT, maps, sM, smem, s)
+  if (d.k == 3) return act == ACT_RELU ? LENET_FWD(3, ACT_RELU) : LENET_FWD(3, ACT_TANH);
+  return act == ACT_RELU ? LENET_FWD(5, ACT_RELU) : LENET_FWD(5, ACT_TANH);
+#undef LENET_FWD
 }
 
 hipError_t lenet_bwd_run(const float* X, int64_t xld, int64_t c0, int mcv, int ipb, const LenetDims& d,
-                         const float* theta, int64_t D, int J, int act, const float* dfeat, int64_t sF, float* part,
-                         int part_blocks, float* g, int beta, hipStream_t s) {
+                         const float* theta, int64_t D, int J, int act, const float* dfeat, int64_t sF,
+                         const float* maps, int64_t sM, float* part, int part_blocks, float* g, int beta,
+                         hipStream_t s) {
   if (mcv <= 0 || J <= 0) return hipSuccess;
   const int nblk = (mcv + ipb - 1) / ipb;
-  if (ipb < 1 || nblk > part_blocks || (d.k != 3 && d.k != 5)) return hipErrorInvalidValue;
+  if (ipb < 1 || nblk > part_blocks || !maps || (d.k != 3 && d.k != 5)) return hipErrorInvalidValue;
   const size_t smem = lenet_smem_bytes(d, true);
+#define LENET_BWD(KS, ACT) \
+  launch_bwd<KS, ACT>(X, xld, c0, mcv, ipb, nblk, d, theta, D, J, dfeat, sF, maps, sM, part, smem, s)
   hipError_t e;
-  if (d.k == 3)
-    e = act == ACT_RELU ? launch_bwd<3, ACT_RELU>(X, xld, c0, mcv, ipb, nblk, d, theta, D, J, dfeat, sF, part, smem, s)
-                        : launch_bwd<3, ACT_TANH>(X, xld, c0, mcv, ipb, nblk, d, theta, D, J, dfeat, sF, part, smem, s);
-  else
-    e = act == ACT_RELU ? launch_bwd<5, ACT_RELU>(X, xld, c0, mcv, ipb, nblk, d, theta, D, J, dfeat, sF, part, smem, s)
-                        : launch_bwd<5, ACT_TANH>(X, xld, c0, mcv, ipb, nblk, d, theta, D, J, dfeat, sF, part, smem, s);
+  if (d.k == 3) e = act == ACT_RELU ? LENET_BWD(3, ACT_RELU) : LENET_BWD(3, ACT_TANH);
+  else e = act == ACT_RELU ? LENET_BWD(5, ACT_RELU) : LENET_BWD(5, ACT_TANH);
+#undef LENET_BWD
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(lenet_reduce_kernel, dim3((unsigned)((d.Dconv + 255) / 256), (unsigned)J), dim3(256), 0, s, part,
                      nblk, d.Dconv, g, D, beta);

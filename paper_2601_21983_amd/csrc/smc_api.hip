@@ -180,7 +180,9 @@ struct smc_handle {
   int lenet = 0;
   LenetDims ld;
   float *lfeat = nullptr, *lfeatT = nullptr, *ldfeat = nullptr, *lpart = nullptr;
-  int lpart_blocks = 0;
+  float* lmaps = nullptr;  // [J][mc][Mimg]: each image's activation maps from the forward, for the backward
+  int lpart_blocks = 0;  // capacity of the partials per particle
+  int lbwd_blocks = 0;   // image blocks per particle of the backward: one round of resident workgroups
   int64_t D = 0;
   int64_t n_data = 0, n_pad = 0;
   int ldx = 0;  // padded feature count
@@ -295,6 +297,7 @@ LenetDims lenet_dims(const int32_t* w) {
   // conv1 weight-gradient items (channel pair, input channel, kernel row) replicated over
   // slices of the image rows to fill 256 threads
   d.ns1 = std::max(1, 256 / (((d.C1 + 1) / 2) * d.Cin * d.k));
+  d.Mimg = d.C1 * d.H * d.W + d.C1 * d.Hp * d.Wp + d.C2 * d.H2 * d.W2;
   return d;
 }
 
@@ -474,8 +477,8 @@ int64_t choose_chunk(smc_t h) {
     if (l >= 1) per_sample += u * h->esz;                          // dR
     if (l + 1 < h->L - 1) per_sample += (int64_t)h->J * (h->net.nout[l] + 1) * h->esz;  // actT
   }
-  if (h->lenet)  // features, their transpose and their error; the first dense layer's dR
-    per_sample += (int64_t)h->J * (3 * h->ld.F + 1 + h->net.nout[0]) * 4;
+  if (h->lenet)  // features, their transpose and their error; the first dense layer's dR; the saved maps
+    per_sample += (int64_t)h->J * (3 * h->ld.F + 1 + h->net.nout[0] + h->ld.Mimg) * 4;
   if (per_sample == 0) per_sample = 1;
   int64_t mc = budget / per_sample;
   mc = mc / 256 * 256;
@@ -586,7 +589,10 @@ void alloc_all(smc_t h) {
     h->lfeat = dalloc<float>(h->owned, (int64_t)J * mc * F);
     h->lfeatT = dalloc<float>(h->owned, (int64_t)J * (F + 1) * mc);
     h->ldfeat = dalloc<float>(h->owned, (int64_t)J * mc * F);
+    h->lmaps = dalloc<float>(h->owned, (int64_t)J * mc * h->ld.Mimg);
     h->lpart_blocks = (int)std::min<int64_t>(64, mc);
+    const int resident = lenet_bwd_resident(h->ld, h->cfg.activation);
+    h->lbwd_blocks = std::max(1, std::min(h->lpart_blocks, resident > 0 ? resident / J : h->lpart_blocks));
     h->lpart = dalloc<float>(h->owned, (int64_t)J * h->lpart_blocks * h->ld.Dconv);
     const int64_t tot = (int64_t)J * mc;
     hipLaunchKernelGGL(fill_ones_rows_kernel<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h->stream,
@@ -653,9 +659,14 @@ void gemm(smc_t h, const GemmParams& p, int cls, double flops) {
 }
 
 // LeNet: features of images [c0, c0 + mcv) of the operand Xop (rows up to `rows` zeroed),
-// and their transpose for the first dense layer's weight gradient when with_t.
+// and, when with_t (a gradient pass), their transpose for the first dense layer's weight
+// gradient and the activation maps for the backward.
 double lenet_macs_per_image(const LenetDims& d) {
   return (double)d.H * d.W * d.C1 * d.K1 + (double)d.H2 * d.W2 * d.C2 * d.K2;
+}
+// backward: the conv1 and conv2 weight gradients and the conv2 input error
+double lenet_bwd_macs_per_image(const LenetDims& d) {
+  return (double)d.H * d.W * d.C1 * d.K1 + 2.0 * d.H2 * d.W2 * d.C2 * d.K2;
 }
 
 void lenet_features(smc_t h, const float* theta, const void* Xop, int64_t c0, int mcv, int rows, bool with_t) {
@@ -663,7 +674,8 @@ void lenet_features(smc_t h, const float* theta, const void* Xop, int64_t c0, in
   const int ipb = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)rows * J / 4096));
   timed(h, SMC_K_OTHER, 2.0 * J * mcv * lenet_macs_per_image(h->ld), 0.0, [&]() {
     HIPCHECK(lenet_fwd_run((const float*)Xop, h->xld, c0, mcv, rows, ipb, h->ld, theta, h->D, J, h->cfg.activation,
-                           h->lfeat, h->mc * h->ld.F, with_t ? h->lfeatT : nullptr, h->mc, h->stream));
+                           h->lfeat, h->mc * h->ld.F, with_t ? h->lfeatT : nullptr, h->mc,
+                           with_t ? h->lmaps : nullptr, h->mc * h->ld.Mimg, h->stream));
   });
 }
 
@@ -1216,10 +1228,11 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
         p.out0.sb = h->mc * nin;
         p.out0.rstr = nin;
         gemm(h, p, SMC_K_GEMM_OTHER, 2.0 * J * nout * (double)nin * mcv);
-        const int ipb = (mcv + h->lpart_blocks - 1) / h->lpart_blocks;
-        timed(h, SMC_K_OTHER, 4.0 * J * mcv * lenet_macs_per_image(h->ld), 0.0, [&]() {
+        const int ipb = (mcv + h->lbwd_blocks - 1) / h->lbwd_blocks;
+        timed(h, SMC_K_OTHER, 2.0 * J * mcv * lenet_bwd_macs_per_image(h->ld), 0.0, [&]() {
           HIPCHECK(lenet_bwd_run((const float*)h->X, h->xld, c0, mcv, ipb, h->ld, theta, h->D, J, h->cfg.activation,
-                                 h->ldfeat, h->mc * h->ld.F, h->lpart, h->lpart_blocks, g_out, beta, h->stream));
+                                 h->ldfeat, h->mc * h->ld.F, h->lmaps, h->mc * h->ld.Mimg, h->lpart, h->lpart_blocks,
+                                 g_out, beta, h->stream));
         });
       }
     }
