@@ -234,6 +234,48 @@ __global__ __launch_bounds__(LT) void lenet_fwd_kernel(const float* __restrict__
   }
 }
 
+// Error of the pooled conv1 map: dp1[c][y][x] = sum over taps and o of dz2[o][y - ky][x - kx] w2[o][c][ky][kx],
+// one pooled pixel per lane.  The tap loops run in full for every lane (out-of-range taps read
+// a clamped address and contribute zero), so the weight addresses are uniform and come from the
+// particle's global row (w2g, rows [o][(ky KS + kx) NC + c | bias]) through the scalar cache.
+template <int KS, int NC>
+__device__ __forceinline__ void conv2_input_error(const float* dz2, float* dp1,
+                                                  const __attribute__((address_space(4))) float* w2g, int C2, int H2,
+                                                  int W2, int Hp, int Wp) {
+  constexpr int ROW = KS * KS * NC + 1;
+  const int P1 = Hp * Wp, P2 = H2 * W2;
+  for (int base = 0; base < P1; base += LT) {  // uniform trip count: lanes past P1 repeat the last pixel
+    const int pix = min(base + (int)threadIdx.x, P1 - 1);
+    const int y = pix / Wp, x = pix - y * Wp;
+    float acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0f;
+    for (int o = 0; o < C2; ++o) {
+      const float* eo = dz2 + o * P2;
+      const __attribute__((address_space(4))) float* wo = w2g + o * ROW;
+#pragma unroll
+      for (int ky = 0; ky < KS; ++ky) {
+        const int yy = y - ky;
+        const bool vy = yy >= 0 && yy < H2;
+        const int yc = vy ? yy : 0;
+#pragma unroll
+        for (int kx = 0; kx < KS; ++kx) {
+          const int xx = x - kx;
+          const bool v = vy && xx >= 0 && xx < W2;
+          const float ev = eo[yc * W2 + (v ? xx : 0)];
+          const float e = v ? ev : 0.0f;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[c] = fmaf(e, wo[(ky * KS + kx) * NC + c], acc[c]);
+        }
+      }
+    }
+    if (base + (int)threadIdx.x < P1) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) dp1[c * P1 + pix] = acc[c];
+    }
+  }
+}
+
 template <int KS, int ACT>
 __global__ __launch_bounds__(LT) void lenet_bwd_kernel(const float* __restrict__ X, int64_t xld, int64_t c0, int mcv,
                                                        int ipb, LenetDims d, const float* __restrict__ theta, int64_t D,
@@ -309,45 +351,17 @@ __global__ __launch_bounds__(LT) void lenet_bwd_kernel(const float* __restrict__
         }
       }
     }
-    // error of the pooled conv1 map: dp1[c][y][x] = sum over taps and o of dz2[o][y - ky][x - kx] w2[o][c][ky][kx].
-    // The tap loops run in full for every lane (out-of-range taps read a clamped address and
-    // contribute zero), so their weight addresses are uniform and come from the particle's
-    // global row through the scalar cache.
+    // error of the pooled conv1 map (the channel count is a template parameter, so every weight
+    // offset within a row is a constant)
     {
       typedef const __attribute__((address_space(4))) float* cfloat_p;  // read-only: scalar loads
       const cfloat_p w2g = (cfloat_p)(theta + (int64_t)j * D + C1 * (d.K1 + 1));  // rows [o][tap C1 + c | bias]
-      for (int base = 0; base < P1; base += LT) {  // uniform trip count: lanes past P1 repeat the last pixel
-        const int pix = min(base + tid, P1 - 1);
-        const int y = pix / d.Wp, x = pix - y * d.Wp;
-        float acc[LENET_CMAX];
-#pragma unroll
-        for (int c = 0; c < LENET_CMAX; ++c) acc[c] = 0.0f;
-        for (int o = 0; o < C2; ++o) {
-          const float* eo = dz2 + o * P2;
-          const cfloat_p wo = w2g + o * (d.K2 + 1);
-#pragma unroll
-          for (int ky = 0; ky < KS; ++ky) {
-            const int yy = y - ky;
-            const bool vy = yy >= 0 && yy < d.H2;
-            const int yc = vy ? yy : 0;
-#pragma unroll
-            for (int kx = 0; kx < KS; ++kx) {
-              const int xx = x - kx;
-              const bool v = vy && xx >= 0 && xx < d.W2;
-              const float ev = eo[yc * d.W2 + (v ? xx : 0)];
-              const float e = v ? ev : 0.0f;
-              const cfloat_p wt = wo + (ky * KS + kx) * C1;
-#pragma unroll
-              for (int c = 0; c < LENET_CMAX; ++c)
-                if (c < C1) acc[c] = fmaf(e, wt[c], acc[c]);
-            }
-          }
-        }
-        if (base + tid < P1) {
-#pragma unroll
-          for (int c = 0; c < LENET_CMAX; ++c)
-            if (c < C1) S.dp1[c * P1 + pix] = acc[c];
-        }
+      switch (C1) {
+#define LENET_DP1(NC) \
+  case NC: conv2_input_error<KS, NC>(dz2, S.dp1, w2g, C2, d.H2, d.W2, d.Hp, d.Wp); break;
+        LENET_DP1(1) LENET_DP1(2) LENET_DP1(3) LENET_DP1(4) LENET_DP1(5) LENET_DP1(6) LENET_DP1(7) LENET_DP1(8)
+#undef LENET_DP1
+        default: break;
       }
     }
     __syncthreads();
