@@ -7,17 +7,18 @@
 // followed by dense layers that run on the batched MFMA GEMM and the output-layer kernel
 // like the dense networks' hidden layers.  The channel counts are tiny (1 -> 6 -> 16 for
 // LeNet-5 on MNIST: contractions of length 25 and 150 into 6 and 16 outputs), so the
-// convolutions run as direct FP32 arithmetic with one particle's conv weights (10 KB) and
-// one image at a time in LDS:
-//   lenet_fwd_kernel   per (block of images, particle): the features, row-major [mc x F]
-//                      and transposed [(F+1) x mc] (the dense layer's weight-gradient operand)
-//   lenet_bwd_kernel   per (block of images, particle): recomputes the stack for each image,
-//                      takes the features' error from the dense layers, and accumulates the
-//                      conv weight gradients in registers over the block's images; one FP32
-//                      partial per block
+// convolutions run as direct FP32 arithmetic with one image at a time in LDS:
+//   lenet_fwd_kernel   per (block of images, particle), the particle's conv weights (10 KB)
+//                      in LDS: the features, row-major [mc x F] and transposed [(F+1) x mc]
+//                      (the dense layer's weight-gradient operand), and in a gradient pass
+//                      each image's activation maps for the backward
+//   lenet_bwd_kernel   per (block of images, particle): reads the saved maps, takes the
+//                      features' error from the dense layers, and accumulates the conv weight
+//                      gradients in registers over the block's images; one FP32 partial per
+//                      block.  Its conv2 input error reads the weights through the scalar cache.
 //   lenet_reduce_kernel sums the partials in a fixed order into the gradient rows
-// Work items pair two output channels with one output pixel, pixels fastest across lanes,
-// so a wave's weight reads are LDS broadcasts and its image reads neighbouring pixels.
+// Forward work items pair two output channels with one output pixel, pixels fastest across
+// lanes, so a wave's weight reads are LDS broadcasts and its image reads neighbouring pixels.
 // Parameter layout: theta[j] starts with [C1 x (k k Cin + 1)] then [C2 x (k k C1 + 1)],
 // weight index (ky k + kx) cin + c, bias last in each row.
 #include "kernels.h"
