@@ -20,6 +20,8 @@ CASES = [
     ((12, 12, 1, 5, 3, 4, 8, 8, 3), "relu", 6, 37, 0),
     ((12, 12, 2, 3, 3, 5, 8, 4, 3), "tanh", 5, 20, 0),   # odd C1 and C2, k = 3, two input channels
     ((8, 12, 2, 3, 5, 6, 8, 4, 4), "tanh", 2, 9, 0),
+    (LENET5, "tanh", 1, 1, 0),         # one particle, one image
+    (LENET5, "relu", 2, 257, 1),       # chunks of 256 and 1 image
 ]
 
 
