@@ -454,6 +454,40 @@ def run_lenet_pass(P, dev, J, reps=3):
             "classes": classes}
 
 
+def run_resampling(P, reps=200):
+    """Per-call time of the stateless ancestor computations (Section 2): systematic from one
+    offset and multinomial from J uniforms, both with the exact integer rule and the in-place
+    placement, on normalised random weights (latency-bound: one workgroup)."""
+    import torch
+    from paper_2601_21983_amd import _lib as L
+    out = {"bound": "latency", "unit": "us"}
+    stream = torch.cuda.current_stream()
+    for Jr in (256, 4096):
+        g = torch.Generator(device="cpu").manual_seed(Jr)
+        w = torch.rand(Jr, generator=g, dtype=torch.float64) ** 4
+        w = (w / w.sum()).cuda()
+        u = torch.rand(Jr, generator=g, dtype=torch.float64).cuda()
+        anc = torch.empty(Jr, dtype=torch.int32, device="cuda")
+        place = torch.empty_like(anc)
+        calls = {"systematic": lambda: L.smc_systematic_resample(w.data_ptr(), Jr, 0.37, anc.data_ptr(),
+                                                                  place.data_ptr(), stream.cuda_stream),
+                 "multinomial": lambda: L.smc_multinomial_resample(w.data_ptr(), Jr, u.data_ptr(), anc.data_ptr(),
+                                                                    place.data_ptr(), stream.cuda_stream)}
+        e = {}
+        for name, f in calls.items():
+            for _ in range(5):
+                f()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                f()
+            b.record(stream)
+            b.synchronize()
+            e[f"{name}_us"] = round(a.elapsed_time(b) * 1e3 / reps, 2)
+        out[f"J={Jr}"] = e
+    return out
+
+
 def cpu_baseline(X, y, sizes, budget_s=12.0, J_s=8):
     """The FP64 oracle on the host cores: iterations k = 1, 2, ... of the same schedule
     with J_s particles until about budget_s seconds of work; rate in grad evals/s."""
@@ -520,11 +554,13 @@ def main():
         moves = [m for m in args.table1_moves.split(",") if m]
         print(json.dumps(run_table1(P, dev, args.seed, args.table1_k, moves)), flush=True)
         return
-    # before the legs, so that the headline's timed sampler stays the last one the run creates
+    # before the legs, so that the headline's timed sampler and its kernels come last in the run
     lenet = None
     if not args.no_lenet:
         lenet = run_lenet_pass(P, dev, TABLE1_J)
         log(f"lenet: {json.dumps(lenet)}")
+    resampling = run_resampling(P)
+    log(f"resampling: {json.dumps(resampling)}")
     net, training = None, None
     if any(leg_parts(l)[1] == "learned" for l in legs):
         net, training = train_proposal(P, dev, sizes)
@@ -599,6 +635,7 @@ def main():
         "cnn_config2": cnn,
         "sda": sda,
         "lenet5_pass": lenet,
+        "resampling": resampling,
         "kernels": {l: kernel_table(res[l]["prof"], leg_parts(l)[0]) for l in legs},
     }
     for l in legs[1:]:
