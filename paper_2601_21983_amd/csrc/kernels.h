@@ -121,21 +121,21 @@ struct LenetDims {
   int F = 0;           // Hq Wq C2
   int Dconv = 0;       // C1 (K1 + 1) + C2 (K2 + 1): the conv blocks at the start of each theta row
   int ns1 = 1;         // row slices of the conv1 weight-gradient items
-  int Mimg = 0;        // saved maps per image: a1 [C1][H][W], p1 [C1][Hp][Wp], a2 [C2][H2][W2]
+  int Mimg = 0;        // saved per image for the backward: the conv2 activations a2 [C2][H2][W2]
 };
 size_t lenet_smem_bytes(const LenetDims& d, bool bwd);
 // workgroups of lenet_bwd_kernel resident on the current device at once (0 if unknown)
 int lenet_bwd_resident(const LenetDims& d, int act);
 // feat[j][n][f] (stride sF per particle) and, if featT, featT[j][f][n] ([(F+1) x ldT] per
 // particle, the ones row f = F untouched) for images n < rows of the chunk starting at global
-// row c0 of X; rows mcv <= n < rows are written as zeros.  If maps, also each image's
-// activation maps at maps[j][n][Mimg] (stride sM per particle) for the backward.  ipb images
-// per workgroup.
+// row c0 of X; rows mcv <= n < rows are written as zeros.  If maps, also each image's conv2
+// activations at maps[j][n][Mimg] (stride sM per particle) for the backward.  ipb images per
+// workgroup.
 hipError_t lenet_fwd_run(const float* X, int64_t xld, int64_t c0, int mcv, int rows, int ipb, const LenetDims& d,
                          const float* theta, int64_t D, int J, int act, float* feat, int64_t sF, float* featT,
                          int64_t ldT, float* maps, int64_t sM, hipStream_t s);
-// Conv weight gradients of the chunk from the features' error dfeat[j][n][f] and the maps the
-// forward saved: per-block partials part[j][blk][Dconv] (part_blocks >= ceil(mcv / ipb) per
+// Conv weight gradients of the chunk from the features' error dfeat[j][n][f] and the conv2
+// activations the forward saved (conv1 is recomputed): per-block partials part[j][blk][Dconv] (part_blocks >= ceil(mcv / ipb) per
 // particle), then g[j][0, Dconv) (+)= their sum in block order (beta = 1 accumulates).
 hipError_t lenet_bwd_run(const float* X, int64_t xld, int64_t c0, int mcv, int ipb, const LenetDims& d,
                          const float* theta, int64_t D, int J, int act, const float* dfeat, int64_t sF,

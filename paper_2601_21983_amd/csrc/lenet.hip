@@ -44,9 +44,10 @@ __host__ __device__ inline int lenet_smem_floats(const LenetDims& d, bool bwd, i
     if (offs) offs[q] = n;
     n += (cnt + 3) & ~3;
   };
-  // the backward reads no conv weights from LDS (its conv2 input error takes them through the scalar cache)
-  take(0, bwd ? 0 : d.C1 * d.Cin * kk);
-  take(1, bwd ? 0 : d.C1);
+  // the backward recomputes conv1 from LDS weights; its conv2 input error takes the conv2
+  // weights through the scalar cache
+  take(0, d.C1 * d.Cin * kk);
+  take(1, d.C1);
   take(2, bwd ? 0 : d.C2 * d.C1 * kk);
   take(3, bwd ? 0 : d.C2);
   take(4, Hpd * Wpd * d.Cin);
@@ -89,11 +90,13 @@ __device__ __forceinline__ float actg(float a) {
   else return 1.0f - a * a;
 }
 
-// Particle j's conv blocks (theta layout [out][(ky k + kx) in + c | bias]) into the LDS layout.
-__device__ inline void load_conv_weights(const float* theta, int64_t D, int j, const LenetDims& d, const LenetSmem& S) {
+// Particle j's conv blocks (theta layout [out][(ky k + kx) in + c | bias]) into the LDS layout
+// (conv1 only when !conv2).
+__device__ inline void load_conv_weights(const float* theta, int64_t D, int j, const LenetDims& d, const LenetSmem& S,
+                                         bool conv2 = true) {
   const float* src = theta + (int64_t)j * D;
   const int kk = d.k * d.k, r1 = d.K1 + 1, r2 = d.K2 + 1, n1 = d.C1 * r1;
-  for (int e = threadIdx.x; e < d.Dconv; e += LT) {
+  for (int e = threadIdx.x; e < (conv2 ? d.Dconv : n1); e += LT) {
     const float v = src[e];
     const bool first = e < n1;
     const int cin = first ? d.Cin : d.C1, rl = first ? r1 : r2;
@@ -218,15 +221,12 @@ __global__ __launch_bounds__(LT) void lenet_fwd_kernel(const float* __restrict__
     load_image(X, xld, c0 + n, d, S.xin);
     __syncthreads();
     float* p1 = S.p1;
-    float* mn = maps ? maps + (int64_t)j * sM + (int64_t)n * d.Mimg : nullptr;  // a1 | p1 | a2 of this image
-    const int A1 = d.C1 * d.H * d.W;
-    conv_act_pool<KS, ACT>(S.xin, P0, Wpd, d.Cin, S.w1, S.b1, d.C1, d.Hp, d.Wp, mn,
+    float* mn = maps ? maps + (int64_t)j * sM + (int64_t)n * d.Mimg : nullptr;  // this image's conv2 activations
+    conv_act_pool<KS, ACT>(S.xin, P0, Wpd, d.Cin, S.w1, S.b1, d.C1, d.Hp, d.Wp, nullptr,
                            [&](int q, int c, float v) { p1[c * P1 + q] = v; });
     __syncthreads();
-    if (mn)
-      for (int e = threadIdx.x; e < d.C1 * P1; e += LT) mn[A1 + e] = p1[e];
     const int C2 = d.C2;
-    conv_act_pool<KS, ACT>(p1, P1, d.Wp, d.C1, S.w2, S.b2, d.C2, d.Hq, d.Wq, mn ? mn + A1 + d.C1 * P1 : nullptr,
+    conv_act_pool<KS, ACT>(p1, P1, d.Wp, d.C1, S.w2, S.b2, d.C2, d.Hq, d.Wq, mn,
                            [&](int q, int c, float v) {
       const int f = q * C2 + c;
       fj[(int64_t)n * d.F + f] = v;
@@ -287,6 +287,7 @@ __global__ __launch_bounds__(LT) void lenet_bwd_kernel(const float* __restrict__
   const LenetSmem S = lenet_smem(lsm, d, true);
   const int j = blockIdx.y, tid = threadIdx.x;
   const int n0 = blockIdx.x * ipb, n1 = min(n0 + ipb, mcv);
+  load_conv_weights(theta, D, j, d, S, false);
   const int Wpd = d.W + 2 * d.pad, P0 = (d.H + 2 * d.pad) * Wpd;
   const int HW = d.H * d.W, P1 = d.Hp * d.Wp, P2 = d.H2 * d.W2;
   const int C1 = d.C1, C2 = d.C2, Cin = d.Cin;
@@ -311,16 +312,17 @@ __global__ __launch_bounds__(LT) void lenet_bwd_kernel(const float* __restrict__
   for (int n = n0; n < n1; ++n) {
     __syncthreads();
     load_image(X, xld, c0 + n, d, S.xin);
-    // the activation maps the forward saved
     {
+      // the conv2 activations the forward saved
       const float* mn = maps + (int64_t)j * sM + (int64_t)n * d.Mimg;
-      const int A1 = C1 * HW;
-      for (int e = tid; e < A1; e += LT) S.a1[e] = mn[e];
-      for (int e = tid; e < C1 * P1; e += LT) S.p1[e] = mn[A1 + e];
-      for (int e = tid; e < C2 * P2; e += LT) S.a2[e] = mn[A1 + C1 * P1 + e];
+      for (int e = tid; e < C2 * P2; e += LT) S.a2[e] = mn[e];
     }
     __syncthreads();
     float* p1 = S.p1;
+    // conv1 again (cheaper than saving its full-resolution maps): activations a1 and the pooled p1
+    conv_act_pool<KS, ACT>(S.xin, P0, Wpd, Cin, S.w1, S.b1, C1, d.Hp, d.Wp, S.a1,
+                           [&](int q, int c, float v) { p1[c * P1 + q] = v; });
+    __syncthreads();
     // dz2 = unpool(dfeat) * act'(a2), in place (planar)
     for (int e = tid; e < C2 * P2; e += LT) {
       const int c = e / P2, pix = e - c * P2;

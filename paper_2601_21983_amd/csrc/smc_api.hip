@@ -180,7 +180,7 @@ struct smc_handle {
   int lenet = 0;
   LenetDims ld;
   float *lfeat = nullptr, *lfeatT = nullptr, *ldfeat = nullptr, *lpart = nullptr;
-  float* lmaps = nullptr;  // [J][mc][Mimg]: each image's activation maps from the forward, for the backward
+  float* lmaps = nullptr;  // [J][mc][Mimg]: each image's conv2 activations from the forward, for the backward
   int lpart_blocks = 0;  // capacity of the partials per particle
   int lbwd_blocks = 0;   // image blocks per particle of the backward: one round of resident workgroups
   int64_t D = 0;
@@ -297,7 +297,7 @@ LenetDims lenet_dims(const int32_t* w) {
   // conv1 weight-gradient items (channel pair, input channel, kernel row) replicated over
   // slices of the image rows to fill 256 threads
   d.ns1 = std::max(1, 256 / (((d.C1 + 1) / 2) * d.Cin * d.k));
-  d.Mimg = d.C1 * d.H * d.W + d.C1 * d.Hp * d.Wp + d.C2 * d.H2 * d.W2;
+  d.Mimg = d.C2 * d.H2 * d.W2;
   return d;
 }
 
