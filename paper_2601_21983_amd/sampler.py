@@ -244,7 +244,10 @@ class SMCSampler:
     # ---------------------------------------------------------------- learned proposal
     @property
     def n_groups(self) -> int:
-        return 2 * (3 if self.cfg.model == "cnn" else len(self.cfg.widths) - 1)
+        """Parameter groups of the learned proposal: the weights and the biases of every layer
+        (LeNet's five layers count, although LeNet runs with the fixed proposal)."""
+        layers = {"cnn": 3, "lenet": 5}.get(self.cfg.model, len(self.cfg.widths) - 1)
+        return 2 * layers
 
     def set_proposal_net(self, params: torch.Tensor, h0: float) -> None:
         L.smc_set_proposal_net(self.handle, _dev(params, torch.float32, "params"), params.numel(), float(h0))
