@@ -23,6 +23,8 @@ CASES = [
     ((8, 8, 3, 8, 8, 3), "cnn", "relu", "fp32", 4, 40, 17, 30, 17, 1.0, 0.5, 400_000),
     ((8, 8, 3, 8, 8, 3), "cnn", "relu", "bf16", 4, 40, 17, 30, 17, 1.0, 0.5, 0),
     ((28, 28, 1, 5, 6, 16, 120, 84, 10), "lenet", "tanh", "fp32", 4, 60, 20, 45, 20, 1.0, 0.4, 0),
+    # chunks of 256 and 44 images, the second segment starting inside the second chunk
+    ((28, 28, 1, 5, 6, 16, 120, 84, 10), "lenet", "tanh", "fp32", 3, 320, 100, 300, 280, 1.0, 0.4, 1),
 ]
 
 
