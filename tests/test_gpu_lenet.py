@@ -71,21 +71,24 @@ def test_lenet_loglik_and_gradient_vs_oracle(case):
     s.close()
 
 
-def test_lenet_predictive_vs_oracle():
+@pytest.mark.parametrize("n_test,budget", [(70, 0), (300, 1)])  # 300 test images in chunks of 256 and 44
+def test_lenet_predictive_vs_oracle(n_test, budget):
     cuda()
     P = lib()
     sh = lenet.LeNetShape(*LENET5)
     J = 5
     X, y = _data(LENET5, 16, seed=3)
-    Xt, yt = _data(LENET5, 70, seed=4)
+    Xt, yt = _data(LENET5, n_test, seed=4)
     theta = smc_inputs.prior_draw(7, J, sh.D, 0.2)
-    print_case("lenet-predictive", J=J, n_test=70)
-    s = _sampler(P, LENET5, "tanh", J, X, y, 16, theta)
+    print_case("lenet-predictive", J=J, n_test=n_test, budget=budget)
+    s = _sampler(P, LENET5, "tanh", J, X, y, 16, theta, act_budget_bytes=budget)
+    if budget:
+        assert s.chunk_samples() < n_test
     r = s.predict(to_dev(Xt), to_dev(yt.astype(np.int32)), probs=True)
     lw = s.state()["logw"].cpu().numpy()
     probs, acc, mlpd = smc.predictive(theta.astype(np.float64), lw, Xt, yt, None, "tanh", lenet.Model(sh, "tanh"))
     np.testing.assert_allclose(r["probs"].cpu().numpy(), probs, rtol=1e-4, atol=1e-6)
-    assert abs(r["accuracy"] - acc) <= 1 / 70 + 1e-12
+    assert abs(r["accuracy"] - acc) <= 1 / n_test + 1e-12
     assert abs(r["mean_log_pred"] - mlpd) < 1e-4 * max(1.0, abs(mlpd))
     s.close()
 
