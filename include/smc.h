@@ -34,7 +34,9 @@
  * Parameter layout of one particle (D floats): for each layer l = 1..L with
  * n_{l-1} inputs and n_l outputs, the block [W_l | b_l] of shape
  * [n_l x (n_{l-1} + 1)], row-major: each output unit's n_{l-1} weights
- * followed by its bias.  Populations are [J x D] row-major float32.
+ * followed by its bias.  Populations are [J x D] row-major float32.  The
+ * convolutional network and LeNet-5 (smc_config.model_kind) use the same
+ * per-layer [W | b] blocks with the weight orders given with smc_config.
  */
 #ifndef SMC_H_
 #define SMC_H_
