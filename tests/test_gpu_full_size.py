@@ -37,3 +37,41 @@ def test_full_size_loglik_and_gradient_on_sampled_particles():
         print(f"particle {j}: ll {e_ll:.3g}, grad {e_g:.3g}", flush=True)
         assert e_ll < 1e-4, (j, e_ll)
         assert e_g < 5e-3, (j, e_g)
+
+
+def test_lenet5_full_size_chunking_and_sampled_predictive():
+    """LeNet-5 at the batching-scheme study's size (J = 32, 60,000 images): the gradient over
+    the whole set does not depend on how it is chunked (the per-sample terms are the same, only
+    the FP32 summation order differs), and the posterior predictive of sampled images matches
+    the oracle's."""
+    cuda()
+    P = lib()
+    from oracle import lenet, smc
+    dims, J, M = list(lenet.LENET5_MNIST), 32, 60000
+    sh = lenet.LeNetShape(*dims)
+    X, y = smc_inputs.templates28(M, seed=0)
+    theta = smc_inputs.prior_draw(5, J, sh.D, 0.05)
+    td = to_dev(theta)
+    print_case("lenet-full-size", J=J, M=M)
+    out = []
+    for budget in (0, 256 << 20):  # chunks of the default budget, then of 256 MB
+        cfg = P.SMCConfig(widths=dims, n_particles=J, model="lenet", activation="tanh", act_budget_bytes=budget)
+        s = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=M, lambda0=1.0, theta0=td)
+        ll, g = s.nn_backward(td, M)
+        torch.cuda.synchronize()
+        out.append((s.chunk_samples(), ll.cpu().numpy(), g.cpu().numpy()))
+        if budget == 0:
+            r = s.predict(to_dev(X), to_dev(y.astype(np.int32)), probs=True)
+            probs = r["probs"].cpu().numpy()
+            lw = s.state()["logw"].cpu().numpy()
+        s.close()
+    (mc0, ll0, g0), (mc1, ll1, g1) = out
+    assert mc0 != mc1, (mc0, mc1)
+    assert np.all(np.isfinite(g0)) and np.all(np.isfinite(ll0))
+    d = np.max(np.abs(g0 - g1) / np.max(np.abs(g1), axis=1, keepdims=True))
+    print(f"chunks of {mc0} vs {mc1}: gradient {d:.3g}", flush=True)
+    assert d < 1e-4, d
+    assert np.max(np.abs(ll0 - ll1) / np.abs(ll1)) < 1e-6
+    idx = np.array([0, 12345, 33333, 59999])
+    p_o, _, _ = smc.predictive(theta.astype(np.float64), lw, X[idx], y[idx], None, "tanh", lenet.Model(sh, "tanh"))
+    np.testing.assert_allclose(probs[idx], p_o, rtol=1e-4, atol=1e-6)
