@@ -75,3 +75,33 @@ def test_lenet5_full_size_chunking_and_sampled_predictive():
     idx = np.array([0, 12345, 33333, 59999])
     p_o, _, _ = smc.predictive(theta.astype(np.float64), lw, X[idx], y[idx], None, "tanh", lenet.Model(sh, "tanh"))
     np.testing.assert_allclose(probs[idx], p_o, rtol=1e-4, atol=1e-6)
+
+
+def test_cnn_bench_size_on_sampled_particles():
+    """The convolutional network at the size its benchmark leg runs (J = 128, 1,000-image
+    subsets of the 32x32x3 textures, BF16 operands), checked on particles the oracle evaluates
+    one by one, at the BF16 tolerances of the small cases."""
+    cuda()
+    P = lib()
+    from oracle import cnn
+    dims, J, M = (32, 32, 3, 16, 32, 10), 128, 1000
+    sh = cnn.CNNShape(*dims)
+    X, y = smc_inputs.textures32(M, seed=0)
+    X = X.reshape(M, -1)
+    theta = smc_inputs.prior_draw(6, J, sh.D, 0.05)
+    td = to_dev(theta)
+    print_case("cnn-bench-size", J=J, M=M, prec="bf16")
+    cfg = P.SMCConfig(widths=list(dims), n_particles=J, model="cnn", precision="bf16")
+    s = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=M, lambda0=1.0, theta0=td)
+    ll, g = s.nn_backward(td, M)
+    torch.cuda.synchronize()
+    ll, g = ll.cpu().numpy(), g.cpu().numpy()
+    s.close()
+    assert np.all(np.isfinite(ll)) and np.all(np.isfinite(g))
+    for j in (0, 127):
+        ll_o, g_o = cnn.loglik_grad(theta[j:j + 1].astype(np.float64), X, y, sh)
+        e_ll = abs(ll[j] - ll_o[0]) / abs(ll_o[0])
+        e_g = np.max(np.abs(g[j] - g_o[0])) / np.max(np.abs(g_o[0]))
+        print(f"particle {j}: ll {e_ll:.3g}, grad {e_g:.3g}", flush=True)
+        assert e_ll < 2e-2, (j, e_ll)
+        assert e_g < 1e-1, (j, e_g)
