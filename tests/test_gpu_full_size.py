@@ -105,3 +105,32 @@ def test_cnn_bench_size_on_sampled_particles():
         print(f"particle {j}: ll {e_ll:.3g}, grad {e_g:.3g}", flush=True)
         assert e_ll < 2e-2, (j, e_ll)
         assert e_g < 1e-1, (j, e_g)
+
+
+def test_deep_network_full_size_on_sampled_particles():
+    """The 784-256-256-10 network with J = 1024 particles over all 60,000 samples (BF16 operands,
+    the activation budget splitting the set into chunks with recomputation), checked on
+    particles the oracle evaluates one by one, at the BF16 tolerances of the small cases."""
+    cuda()
+    P = lib()
+    widths, J, M = [784, 256, 256, 10], 1024, 60000
+    X, y = smc_inputs.templates28(M, seed=0)
+    D = mlp.n_params(widths)
+    theta = smc_inputs.prior_draw(8, J, D, 0.05)
+    td = to_dev(theta)
+    print_case("deep-full-size", J=J, M=M, prec="bf16")
+    cfg = P.SMCConfig(widths=widths, n_particles=J, precision="bf16")
+    s = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=M, lambda0=1.0, theta0=td)
+    assert s.chunk_samples() < M
+    ll, g = s.nn_backward(td, M)
+    torch.cuda.synchronize()
+    ll, g = ll.cpu().numpy(), g.cpu().numpy()
+    s.close()
+    assert np.all(np.isfinite(ll)) and np.all(np.isfinite(g))
+    for j in (0, 1023):
+        ll_o, g_o = mlp.loglik_grad(theta[j:j + 1].astype(np.float64), X, y, widths, "relu")
+        e_ll = abs(ll[j] - ll_o[0]) / abs(ll_o[0])
+        e_g = np.max(np.abs(g[j] - g_o[0])) / np.max(np.abs(g_o[0]))
+        print(f"particle {j}: ll {e_ll:.3g}, grad {e_g:.3g}", flush=True)
+        assert e_ll < 2e-2, (j, e_ll)
+        assert e_g < 3e-2, (j, e_g)
