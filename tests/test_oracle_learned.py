@@ -139,3 +139,95 @@ def test_step_size_targets_without_acceptance_pick_the_longest_jump():
     lh1, _ = learned.step_size_targets(s, 128, 1.0, xi, 0.01, accept_power=1.0)
     lh4, _ = learned.step_size_targets(s, 128, 1.0, xi, 0.01, accept_power=4.0)
     assert np.all(lh4 <= logh + 1e-12) and np.all(lh1 <= logh + 1e-12)
+
+
+def _torch_net(blob, G):
+    """The proposal network written independently with torch float64 library layers."""
+    import torch
+    import torch.nn.functional as F
+
+    b = torch.tensor(blob, dtype=torch.float64)
+    n_out = 1 + G
+    sizes = [4, 4, 64 * 4, 64, 64 * 64, 64, n_out * 64, n_out]
+    parts = list(torch.split(b, sizes))
+    mu, sd = parts[0], parts[1]
+    W1, b1 = parts[2].reshape(64, 4).clone().requires_grad_(), parts[3].clone().requires_grad_()
+    W2, b2 = parts[4].reshape(64, 64).clone().requires_grad_(), parts[5].clone().requires_grad_()
+    W3, b3 = parts[6].reshape(n_out, 64).clone().requires_grad_(), parts[7].clone().requires_grad_()
+
+    def fwd(f):
+        u = torch.clamp((torch.as_tensor(f, dtype=torch.float64) - mu) / sd, -3.0, 3.0)
+        return F.linear(torch.tanh(F.linear(torch.tanh(F.linear(u, W1, b1)), W2, b2)), W3, b3)
+
+    return fwd, (W1, b1, W2, b2, W3, b3)
+
+
+def test_net_forward_matches_torch_float64_network_with_active_clip():
+    # standardise, clip to +-3 sd, tanh, tanh, linear; some feature columns lie far outside
+    # the training statistics so that the clip is active in both directions
+    G = 4
+    rng = np.random.default_rng(5)
+    blob = learned.init_blob(G, seed=7, mu=[0.1, -0.2, 0.5, 0.3], sd=[1.5, 0.7, 0.3, 0.4])
+    blob[8:] += 0.1 * rng.standard_normal(blob.shape[0] - 8)  # non-zero biases too
+    f = rng.standard_normal((9, 4))
+    f[0] = [100.0, -100.0, 0.5, 0.3]     # clipped at +3 and -3
+    f[1] = [0.1 + 4.8, -0.2 - 2.0, 0.5 + 0.91, 0.3 - 1.19]  # clipped / inside / clipped / inside
+    fwd, _ = _torch_net(blob, G)
+    o, (u, _, _) = learned.net_forward(blob, f, G)
+    np.testing.assert_allclose(o, fwd(f).detach().numpy(), rtol=1e-12, atol=1e-13)
+    assert u[0].tolist() == [3.0, -3.0, 0.0, 0.0]
+    np.testing.assert_allclose(u[1], [3.0, -2.0 / 0.7, 3.0, -1.19 / 0.4], rtol=1e-12)
+    # without the clip the first row would differ
+    p = learned.unpack_blob(blob, G)
+    u_noclip = (f[0] - p["mu"]) / p["sd"]
+    o_noclip = np.tanh(np.tanh(u_noclip @ p["W1"].T + p["b1"]) @ p["W2"].T + p["b2"]) @ p["W3"].T + p["b3"]
+    assert np.max(np.abs(o_noclip - o[0])) > 1e-3
+
+
+def test_mse_loss_gradient_matches_torch_autograd():
+    import torch
+
+    G = 6
+    rng = np.random.default_rng(11)
+    blob = learned.init_blob(G, seed=2, mu=[-0.3, 0.2, 0.1, 0.6], sd=[0.8, 1.1, 0.5, 0.25])
+    blob[8:] += 0.05 * rng.standard_normal(blob.shape[0] - 8)
+    f = rng.standard_normal((13, 4))
+    f[3] = [50.0, 0.0, -50.0, 0.6]
+    t = rng.standard_normal((13, 1 + G))
+    loss, grad = learned.mse_loss_grad(blob, f, t, G)
+    fwd, params = _torch_net(blob, G)
+    o = fwd(f)
+    tl = 0.5 * ((o - torch.tensor(t)) ** 2).sum() / f.shape[0]
+    tl.backward()
+    ref = np.concatenate([np.zeros(8)] + [p.grad.numpy().ravel() for p in params])
+    np.testing.assert_allclose(loss, tl.item(), rtol=1e-13)
+    np.testing.assert_allclose(grad, ref, rtol=1e-11, atol=1e-14)
+
+
+def test_adam_matches_torch_optim_over_several_steps():
+    # the bias corrections 1 - beta^t for t = 1..7 with gradients that change from step to step
+    import torch
+
+    rng = np.random.default_rng(3)
+    x0 = rng.standard_normal(17)
+    grads = [rng.standard_normal(17) * s for s in (1.0, 0.1, 3.0, 0.5, 2.0, 1e-3, 1.0)]
+    p = torch.tensor(x0.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=0.03, betas=(0.9, 0.999), eps=1e-8)
+    blob = x0.copy()
+    state = (np.zeros(17), np.zeros(17), 0)
+    for g in grads:
+        p.grad = torch.tensor(g)
+        opt.step()
+        blob, state = learned.adam_update(blob, g, state, lr=0.03)
+        np.testing.assert_allclose(blob, p.detach().numpy(), rtol=1e-12, atol=1e-14)
+    assert state[2] == 7
+
+
+def test_features_worked_by_hand():
+    # (log |grad log pi|, LL / M_k, k / K, M_k / N): gradients (3, 4, 0) and (0, 0, 2) have
+    # norms 5 and 2
+    grad = np.array([[3.0, 4.0, 0.0], [0.0, 0.0, 2.0]])
+    ll = np.array([-20.0, -5.0])
+    f = learned.features(ll, grad, m=10, k=3, K=12, N=40)
+    np.testing.assert_allclose(f, [[math.log(5.0), -2.0, 0.25, 0.25],
+                                   [math.log(2.0), -0.5, 0.25, 0.25]], rtol=1e-15)

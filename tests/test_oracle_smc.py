@@ -331,3 +331,49 @@ def test_predictive_ties_take_lowest_class():
     _, acc0, _ = smc.predictive(theta, np.zeros(1), X, np.zeros(3, int), [2, 16, 2], "tanh")
     _, acc1, _ = smc.predictive(theta, np.zeros(1), X, np.ones(3, int), [2, 16, 2], "tanh")
     assert acc0 == 1.0 and acc1 == 0.0
+
+
+def test_predictive_mixture_of_three_particles_worked_by_hand():
+    # Section 2 (posterior estimates): p(y | x) = sum_j w~_j p(y | x, theta_j) and the mean log
+    # predictive is mean_i log sum_j w~_j p(y_i | x_i, theta_j).  A network without hidden
+    # layer, widths [2, 2]: class 0 has weights and bias zero, class 1 weight (a_j, 0) and bias
+    # c_j, so p_j(1 | x) = r / (1 + r) with r = exp(c_j + a_j x_1).  Particle j is chosen with
+    # p_j(1 | x_1 = 0) = P0[j] and p_j(1 | x_1 = 1) = P1[j].
+    P0 = np.array([0.5, 0.2, 0.9])
+    P1 = np.array([0.25, 0.6, 0.1])
+    w = np.array([0.2, 0.3, 0.5])
+    c = np.log(P0 / (1 - P0))
+    a = np.log(P1 / (1 - P1)) - c
+    theta = np.zeros((3, 6))          # rows [w00 w01 b0 | w10 w11 b1]
+    theta[:, 3] = a
+    theta[:, 5] = c
+    X = np.array([[0.0, 7.0], [1.0, -3.0], [0.0, 0.5]])   # x_2 has zero weight everywhere
+    y = np.array([1, 0, 0])
+    probs, acc, mlpd = smc.predictive(theta, np.log(w), X, y, [2, 2], "relu")
+    # mixture probabilities of class 1, worked by hand: 0.2*0.5 + 0.3*0.2 + 0.5*0.9 = 0.61 and
+    # 0.2*0.25 + 0.3*0.6 + 0.5*0.1 = 0.28
+    np.testing.assert_allclose(probs[:, 1], [0.61, 0.28, 0.61], rtol=1e-13)
+    np.testing.assert_allclose(probs.sum(1), 1.0, rtol=1e-14)
+    # labels 1, 0, 0: the arg-max is 1, 0, 1, so two of three are right
+    assert acc == 2.0 / 3.0
+    ref = (math.log(0.61) + math.log(0.72) + math.log(0.39)) / 3.0
+    np.testing.assert_allclose(mlpd, ref, rtol=1e-13)
+    # the two plausible mistakes give other values: averaging log-probabilities over particles
+    # and weighting log p linearly
+    avg_log = np.mean([np.mean(np.log(p)) for p in ([0.5, 0.2, 0.9], [0.75, 0.4, 0.9], [0.5, 0.8, 0.1])])
+    lin_log = np.mean([w @ np.log(p) for p in ([0.5, 0.2, 0.9], [0.75, 0.4, 0.9], [0.5, 0.8, 0.1])])
+    assert abs(mlpd - avg_log) > 0.05 and abs(mlpd - lin_log) > 0.05
+
+
+def test_predictive_weights_are_used_as_normalised_log_weights():
+    # the same mixture with the weights supplied as log w~ of unequal particles in another
+    # order: the estimate does not depend on the particles' order
+    P0 = np.array([0.9, 0.5, 0.2])
+    w = np.array([0.5, 0.2, 0.3])
+    theta = np.zeros((3, 6))
+    theta[:, 5] = np.log(P0 / (1 - P0))
+    X = np.zeros((2, 2))
+    probs, acc, mlpd = smc.predictive(theta, np.log(w), X, np.array([1, 1]), [2, 2], "tanh")
+    np.testing.assert_allclose(probs[:, 1], 0.61, rtol=1e-13)
+    assert acc == 1.0
+    np.testing.assert_allclose(mlpd, math.log(0.61), rtol=1e-13)
