@@ -209,9 +209,12 @@ SMC_API smc_status smc_segment_moments(smc_t h, double* out4);
  *   u         host pointer to the offset u in [0, 1), or NULL to draw it on the device.
  *   resampled (host, nullable) receives 1 if the population was resampled.
  *   ancestors_host (host, nullable) [J] receives the sorted systematic ancestors
- *             (identity if not resampled).  Non-null host outputs synchronise.
+ *             (identity if not resampled).
  * Survivors keep their slot; dead slots receive the surplus copies (in-place).
- * Weights are reset to 1/J after resampling.
+ * Weights are reset to 1/J after resampling.  Synchronises the stream (the
+ * device flags are read on every call).  SMC_ERR_NONFINITE if every particle's
+ * log-weight is non-finite, also when the step that made them so returned no
+ * statistics; the population is then left unchanged.
  */
 SMC_API smc_status smc_resample(smc_t h, int32_t mode, const double* u, int32_t* resampled, int32_t* ancestors_host);
 

@@ -1638,9 +1638,12 @@ void resample_impl(smc_t h, int32_t mode, int scheme, const double* u, const dou
       HIPCHECK(gather_rows_run(h->J, h->D, h->place, h->theta, h->g, h->stream));
       if (!h->w_dirty) HIPCHECK(cast_run(h->net, h->theta, h->place, h->stream));
     });
-    if (resampled || ancestors_host) {
+    {
+      // the flags are read on every call, so that a population whose weights all became
+      // non-finite in a step that returned no statistics is reported here
       double st[8];
       read_stats(h, st);
+      if (st[ST_ALLBAD] != 0.0) fail(SMC_ERR_NONFINITE, "every particle has a non-finite log-weight: not resampled");
       if (resampled) *resampled = st[ST_RESAMPLED] != 0.0 ? 1 : 0;
       if (ancestors_host) {
         HIPCHECK(hipMemcpyAsync(ancestors_host, h->anc, (size_t)h->J * 4, hipMemcpyDeviceToHost, h->stream));

@@ -414,7 +414,10 @@ __global__ __launch_bounds__(1024) void resample_kernel(const ResampleArgs a) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int J = a.J, tid = threadIdx.x;
   const double ess = a.stats[ST_ESS];
-  const bool doit = a.mode == 1 || (a.mode == 0 && ess < a.ess_frac * (double)J);
+  // a population whose every log-weight is non-finite has no weights to resample from: it is
+  // left as it is (and stays flagged), the host reports the error
+  const bool allbad = a.stats[ST_ALLBAD] != 0.0;
+  const bool doit = !allbad && (a.mode == 1 || (a.mode == 0 && ess < a.ess_frac * (double)J));
   if (!doit) {
     for (int k = tid; k < J; k += blockDim.x) {
       a.ancestors[k] = k;

@@ -122,3 +122,30 @@ def test_device_drawn_uniforms_are_reproducible_and_binomial():
     mean = counts / 300
     se = np.sqrt(J * w * (1 - w) / 300)
     assert np.all(np.abs(mean - J * w) <= 5 * se + 1e-9), (mean, J * w)
+
+
+def test_all_nonfinite_population_is_not_resampled():
+    """Every particle's parameters non-finite: the step without statistics leaves every log-weight
+    at -inf; resampling must report SMC_ERR_NONFINITE instead of turning the population into
+    copies of one particle with uniform weights (Section 2: the normalised weights of Eq.
+    normalise do not exist), and the population stays as it was."""
+    cuda()
+    P = lib()
+    widths, J, N = [2, 4, 2], 8, 64
+    X, y = smc_inputs.blobs(N, seed=40)
+    D = mlp.n_params(widths)
+    th0 = smc_inputs.prior_draw(41, J, D, 1.0)
+    print_case("resample-all-nonfinite", J=J)
+    cfg = P.SMCConfig(widths=widths, n_particles=J, activation="tanh", seed=5, step_size=0.01)
+    g = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=N, lambda0=1.0, theta0=to_dev(th0))
+    bad = np.full((J, D), np.nan, np.float32)
+    g.set_state(to_dev(bad))
+    g.step(N, 1.0, info=False)  # returns no statistics, so it does not check
+    for scheme in ("systematic", "multinomial"):
+        for mode in ("if_needed", "always"):
+            with pytest.raises(P.SMCError) as e:
+                g.resample(mode, scheme=scheme)
+            assert e.value.status == 5  # SMC_ERR_NONFINITE
+    st = g.state()
+    assert np.all(np.isneginf(st["logw"].cpu().numpy()) | np.isnan(st["logw"].cpu().numpy()))
+    g.close()
