@@ -361,6 +361,25 @@ SMC_API smc_status smc_mlp_train(float* params_dev, float* adam_dev, const float
                                  int64_t R, int32_t n_groups, int32_t first_step, int32_t n_steps, double lr,
                                  double* loss, void* hip_stream);
 
+/*
+ * Allocation-free variant of smc_mlp_train, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same kernels and arithmetic as smc_mlp_train (identical results); the
+ * per-tile gradient and loss partials of each Adam step live in a fixed 10 MiB device
+ * array that the library holds on every device it runs on until the process ends.
+ *   R <= 32768 rows and 1 <= n_groups <= 8, else SMC_ERR_ARG (the scratch limit).
+ *   loss_dev (device float64, nullable) receives the last step's loss.
+ * Enqueues on hip_stream (the current device's stream) and returns without
+ * synchronising; it calls no hipMalloc/hipFree and copies nothing to the host.
+ * The scratch keeps the last call's contents; every value a call reads from it is
+ * written by that call first, so nothing needs clearing.  All calls on one device
+ * share that device's scratch: calls that overlap on one device (other streams or
+ * threads) race and must be serialised by the caller.
+ */
+SMC_API smc_status smc_mlp_train_noalloc(float* params_dev, float* adam_dev, const float* feat_dev,
+                                         const float* target_dev, int64_t R, int32_t n_groups, int32_t first_step,
+                                         int32_t n_steps, double lr, double* loss_dev, void* hip_stream);
+
 /* ---------------------------------------------------------------- kernel timing */
 /*
  * Kernel classes timed by the profiling hook.  FLOP and byte counts are the

@@ -32,6 +32,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1381,6 +1382,56 @@ void mlp_steps(float* params, float* adam, const float* feat, const float* tgt, 
   if (loss_host) *loss_host = loss;
 }
 
+// ------------------------------------------------------------------ allocation-free training
+// smc_mlp_train_noalloc keeps the per-tile gradient partials and loss partials of one Adam
+// step in a fixed file-scope device array instead of hipMalloc'd buffers.  Every device the
+// library runs on holds its own copy until the process ends.  In host code the array's name
+// is only a stand-in for its device address, which hipGetSymbolAddress returns once per
+// device (with that device current); kernels receive that address.
+constexpr int64_t NOALLOC_MAX_ROWS = 32768;
+constexpr int NOALLOC_MAX_GROUPS = 8;
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)10 << 20;  // 10 MiB
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+inline size_t noalloc_grad_bytes(int64_t ntiles, int Pn) { return (size_t)round_up(ntiles * Pn * 4, 256); }
+
+// device address of the current device's scratch array (looked up on the first call per device)
+char* noalloc_scratch() {
+  int dev = -1;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) fail(SMC_ERR_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(SMC_ERR_DEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+void mlp_steps_noalloc(float* params, float* adam, const float* feat, const float* tgt, int64_t R, int G,
+                       int first_step, int n_steps, double lr, double* loss_dev, hipStream_t st) {
+  if (R < 1 || R > NOALLOC_MAX_ROWS) fail(SMC_ERR_ARG, "R must be in [1, 32768] for the allocation-free call");
+  if (G < 1 || G > NOALLOC_MAX_GROUPS) fail(SMC_ERR_ARG, "n_groups must be in [1, 8] for the allocation-free call");
+  const int Pn = mlp_n_params(G);
+  const int64_t ntiles = (R + 63) / 64;
+  const size_t gbytes = noalloc_grad_bytes(ntiles, Pn);
+  if (gbytes + (size_t)ntiles * 8 > NOALLOC_SCRATCH_BYTES) fail(SMC_ERR_ARG, "scratch too small for this call");
+  char* base = noalloc_scratch();
+  HIPCHECK(mlp_set_smem_limits());
+  float* gp = (float*)base;
+  double* lp = (double*)(base + gbytes);
+  for (int i = 0; i < n_steps; ++i)
+    HIPCHECK(mlp_train_step_run(params, adam, feat, tgt, R, G, gp, lp, first_step + i, (float)lr, nullptr,
+                                i == n_steps - 1 ? loss_dev : nullptr, st));
+}
+
 smc_status guard(void (*body)(void*), void* ctx) {
   try {
     g_last_error.clear();
@@ -1952,6 +2003,17 @@ smc_status smc_mlp_train(float* params_dev, float* adam_dev, const float* feat_d
     if (first_step < 1 || n_steps < 1 || !(lr > 0)) fail(SMC_ERR_ARG, "first_step, n_steps >= 1 and lr > 0");
     mlp_steps(params_dev, adam_dev, feat_dev, target_dev, R, n_groups, first_step, n_steps, lr, nullptr, loss,
               (hipStream_t)hip_stream);
+  });
+}
+
+smc_status smc_mlp_train_noalloc(float* params_dev, float* adam_dev, const float* feat_dev, const float* target_dev,
+                                 int64_t R, int32_t n_groups, int32_t first_step, int32_t n_steps, double lr,
+                                 double* loss_dev, void* hip_stream) {
+  return run([&]() {
+    if (!params_dev || !adam_dev || !feat_dev || !target_dev) fail(SMC_ERR_ARG, "null argument");
+    if (first_step < 1 || n_steps < 1 || !(lr > 0)) fail(SMC_ERR_ARG, "first_step, n_steps >= 1 and lr > 0");
+    mlp_steps_noalloc(params_dev, adam_dev, feat_dev, target_dev, R, n_groups, first_step, n_steps, lr, loss_dev,
+                      (hipStream_t)hip_stream);
   });
 }
 
