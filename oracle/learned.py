@@ -198,7 +198,7 @@ def learned_step(s: Sampler, m, lam, xi, blob, h0, k, K, N):
     return s
 
 
-def step_size_targets(s: Sampler, m, lam, xi, h0, grid=tuple(range(-3, 4)), accept_power=1.0):
+def step_size_targets(s: Sampler, m, lam, xi, h0, grid=tuple(range(-3, 4)), accept_power=1.0, return_scores=False):
     """Per-particle training targets from one replayed sampler state.
 
     For every step h = h0 2^e on the grid, one preconditioning-free Langevin
@@ -209,7 +209,8 @@ def step_size_targets(s: Sampler, m, lam, xi, h0, grid=tuple(range(-3, 4)), acce
     larger p prefers steps whose increments stay near zero).  The
     target for log h is the best grid value.  The mass targets are the log
     RMS gradient per parameter group, centred over the groups.
-    Returns (log h* [J], log m* [J x G]).
+    Returns (log h* [J], log m* [J x G]), and with return_scores also the score of
+    every grid step [J x len(grid)].
     """
     m, lam = int(m), float(lam)
     if (m, lam) != (s.m, s.lam):
@@ -221,6 +222,7 @@ def step_size_targets(s: Sampler, m, lam, xi, h0, grid=tuple(range(-3, 4)), acce
     xi = np.asarray(xi, dtype=np.float64)
     best = np.full(theta.shape[0], -np.inf)
     best_h = np.full(theta.shape[0], math.log(h0))
+    all_scores = []
     for e in grid:
         h = h0 * 2.0 ** e
         theta1 = theta + 0.5 * h * h * g + h * xi
@@ -231,6 +233,7 @@ def step_size_targets(s: Sampler, m, lam, xi, h0, grid=tuple(range(-3, 4)), acce
         d = lp1 - lp0 + log_l - log_q
         score = np.sum((theta1 - theta) ** 2, axis=1) * np.exp(accept_power * np.minimum(d, 0.0))
         score = np.where(np.isfinite(score), score, -np.inf)
+        all_scores.append(score)
         better = score > best
         best = np.where(better, score, best)
         best_h = np.where(better, math.log(h), best_h)
@@ -239,6 +242,8 @@ def step_size_targets(s: Sampler, m, lam, xi, h0, grid=tuple(range(-3, 4)), acce
     rms = np.stack([np.sqrt(np.mean(g[:, gid == q] ** 2, axis=1)) for q in range(G)], axis=1)
     logm = np.log(rms)
     logm = logm - logm.mean(axis=1, keepdims=True)
+    if return_scores:
+        return best_h, logm, np.stack(all_scores, axis=1)
     return best_h, logm
 
 

@@ -158,12 +158,21 @@ def test_proposal_targets_match_oracle(power):
     g.set_noise(to_dev(xi))
     print_case("proposal-targets", J=32, accept_power=power)
     feat, tgt = g.proposal_targets(256, 1.0, grid, 0.0, power)
-    logh, logm = olearned.step_size_targets(o, 256, 1.0, xi, 0.01, accept_power=power)
+    logh, logm, scores = olearned.step_size_targets(o, 256, 1.0, xi, 0.01, accept_power=power,
+                                                    return_scores=True)
     ref = olearned.output_targets(logh, logm, 0.01)
     t = tgt.cpu().numpy()
-    # the argmax over the grid agrees except where two grid scores tie to rounding
+    # the arg-max over the grid agrees, except where the step the GPU chose scores within
+    # TIE of the best score in the FP64 oracle (FP32 log-likelihoods move the Metropolis
+    # exponent D by ~1e-4 absolute, i.e. a score by ~p 1e-4 relative)
+    TIE = 1e-3 * power
     agree = np.isclose(t[:, 0], ref[:, 0], atol=1e-5)
-    assert agree.mean() >= 0.9, agree
+    grid = np.arange(-3, 4)
+    for j in np.flatnonzero(~agree):
+        e_gpu = int(round(np.tanh(t[j, 0]) * np.log(8.0) / np.log(2.0)))  # target -> grid exponent
+        s_gpu, s_best = scores[j, e_gpu - grid[0]], scores[j].max()
+        assert s_gpu >= s_best * (1.0 - TIE), (j, e_gpu, scores[j])
+    print(f"[measured] {int((~agree).sum())} of {len(agree)} step targets differ, all within ties", flush=True)
     assert rel_err(t[:, 1:], ref[:, 1:]) < 1e-3
     fo = olearned.features(*o.loglik_grad(o.theta, 256, 1.0), 256, 0, 10, 256)
     assert np.max(np.abs(feat.cpu().numpy()[:, :2] - fo[:, :2])) < 1e-4 * np.max(np.abs(fo[:, :2]))
