@@ -296,6 +296,17 @@ SMC_API smc_status smc_set_noise(smc_t h, const float* momenta_dev);
 SMC_API smc_status smc_set_proposal_net(smc_t h, const float* params_dev, int32_t n_params, double h0);
 
 /*
+ * Switch the move of the following iterations between the fixed-step move
+ * (SMC_PROPOSAL_FIXED) and the learned-scale Langevin move (SMC_PROPOSAL_LEARNED,
+ * which needs leapfrog_steps == 1 and a network set with smc_set_proposal_net).
+ * Both moves reweight with the L-kernel of their own step (Section 2.1, Eq.
+ * weight_update), so the population stays properly weighted across a switch; this is
+ * how the run-level fallback to the fixed step is applied.  Errors: SMC_ERR_ARG,
+ * SMC_ERR_STATE (learned without a network).
+ */
+SMC_API smc_status smc_set_proposal(smc_t h, int32_t proposal);
+
+/*
  * Per-particle features of the learned proposal at the current state,
  * [J x 4] float64: (log |grad log pi|, LL / M_k, k / K, M_k / N) with
  * k_over_K and m_over_N supplied by the caller.

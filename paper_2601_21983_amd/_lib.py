@@ -113,6 +113,7 @@ _SIGS = {
     "smc_mlp_forward": (_i32, [_vp, _vp, _i64, _i32, _vp, _i32, _d, _i32, _vp]),
     "smc_mlp_grad": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, C.POINTER(_d), _vp]),
     "smc_mlp_train": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32, _d, C.POINTER(_d), _vp]),
+    "smc_set_proposal": (_i32, [_handle, _i32]),
     "smc_mlp_train_noalloc": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32, _d, _vp, _vp]),
     "smc_profile": (_i32, [_handle, _i32]),
     "smc_profile_read": (_i32, [_handle, C.POINTER(_d), C.POINTER(_i64), C.POINTER(_d), C.POINTER(_d)]),
@@ -327,3 +328,7 @@ def smc_mlp_train_noalloc(params_dev, adam_dev, feat_dev, target_dev, R: int, n_
     _check(lib.smc_mlp_train_noalloc(_opt(params_dev), _opt(adam_dev), _opt(feat_dev), _opt(target_dev), R,
                                      n_groups, first_step, n_steps, lr, _opt(loss_dev), _opt(stream)),
            "smc_mlp_train_noalloc")
+
+
+def smc_set_proposal(h, proposal: int) -> None:
+    _check(lib.smc_set_proposal(h, proposal), "smc_set_proposal")

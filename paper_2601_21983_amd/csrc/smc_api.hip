@@ -1890,6 +1890,18 @@ smc_status smc_set_proposal_net(smc_t h, const float* params_dev, int32_t n_para
   });
 }
 
+smc_status smc_set_proposal(smc_t h, int32_t proposal) {
+  return run([&]() {
+    if (!h) fail(SMC_ERR_ARG, "null handle");
+    if (proposal != SMC_PROPOSAL_FIXED && proposal != SMC_PROPOSAL_LEARNED) fail(SMC_ERR_ARG, "proposal");
+    if (proposal == SMC_PROPOSAL_LEARNED) {
+      if (h->cfg.leapfrog_steps != 1) fail(SMC_ERR_ARG, "the learned proposal is a Langevin move (leapfrog_steps 1)");
+      if (!h->pnet) fail(SMC_ERR_STATE, "no proposal network set");
+    }
+    h->cfg.proposal = proposal;
+  });
+}
+
 smc_status smc_proposal_features(smc_t h, double kk, double mm, double* feat_dev) {
   return run([&]() {
     if (!h || !feat_dev) fail(SMC_ERR_ARG, "null argument");

@@ -123,6 +123,7 @@ class SMCSampler:
         self._h = None
         self._h = L.smc_init(cfg.to_c(), xp, yp, self.N, tp, int(m0), float(lambda0), self.stream.cuda_stream)
         self.m = int(m0)
+        self.proposal = cfg.proposal
 
     # ---------------------------------------------------------------- lifecycle
     def close(self) -> None:
@@ -251,6 +252,11 @@ class SMCSampler:
 
     def set_proposal_net(self, params: torch.Tensor, h0: float) -> None:
         L.smc_set_proposal_net(self.handle, _dev(params, torch.float32, "params"), params.numel(), float(h0))
+
+    def set_proposal(self, proposal: str) -> None:
+        """Switch the move of the following iterations: "fixed" or "learned"."""
+        L.smc_set_proposal(self.handle, _PROP[proposal])
+        self.proposal = proposal
 
     def proposal_features(self, k_over_K: float, m_over_N: float) -> torch.Tensor:
         out = torch.empty((self.J, 4), dtype=torch.float64, device="cuda")
