@@ -65,6 +65,7 @@ def parse():
     ap.add_argument("--no-cnn", action="store_true", help="skip the convolutional-network workload")
     ap.add_argument("--cnn-steps", type=int, default=8)
     ap.add_argument("--no-sda", action="store_true", help="skip the smooth-data-annealing run")
+    ap.add_argument("--no-deep", action="store_true", help="skip the 784-256-256-10, J = 1024 workload")
     ap.add_argument("--no-lenet", action="store_true", help="skip the LeNet-5 gradient-pass measurement")
     ap.add_argument("--table1", action="store_true",
                     help="instead of the benchmark: the batching-scheme study on LeNet-5 (six schemes x LD/HMC)")
@@ -490,6 +491,68 @@ def run_lenet_pass(P, dev, J, reps=3):
             "classes": classes}
 
 
+CFG3_WIDTHS = [784, 256, 256, 10]
+CFG3_J = 1024
+CFG3_PRIOR = 0.05  # as for the other deep MNIST-shaped runs: with N(0, 1) the 256-wide layers give logits ~1e3
+
+
+def run_config3(P, dev, seed, n_lead=4, n_full=2):
+    """The deep network at scale: 784-256-256-10 ReLU, J = 1024, BF16 operands, iterations
+    k = 1..n_lead of the Linear 1000 -> 60,000 schedule followed by n_full iterations on all
+    60,000 samples (the schedule's end).  The subset is processed in chunks that fit the default
+    8 GiB activation budget, each chunk's backward working from its own recomputed forward.
+    One run without instrumentation gives the rate; a second run of the same iterations with
+    HIP events on every launch gives the kernel classes (layer-1 forward, layer-1 weight
+    gradient, layer-2 forward/error/weight-gradient GEMMs, output layer)."""
+    import torch
+    from paper_2601_21983_amd import schedules
+    sizes = schedules.sizes("linear", K_FULL, N_TRAIN, C0, KAPPA)
+    run_sizes = sizes[: n_lead + 1] + [N_TRAIN] * n_full
+    cfg = P.SMCConfig(widths=CFG3_WIDTHS, n_particles=CFG3_J, activation="relu", precision="bf16",
+                      step_size=STEP, prior_std=CFG3_PRIOR, seed=seed)
+    out = {}
+    for profiled in (False, True):
+        s = P.SMCSampler(cfg, dev["X"], dev["y"], m0=run_sizes[0], lambda0=N_TRAIN / run_sizes[0])
+        s.resample()
+        if profiled:
+            s.profile(True)
+            s.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evals, ess = 0, []
+        for k in range(1, len(run_sizes)):
+            info = s.step(run_sizes[k], N_TRAIN / run_sizes[k])
+            evals += info["grad_evals"]
+            ess.append(info["ess"])
+            s.resample()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if profiled:
+            out["prof"] = s.profile_read()
+        else:
+            out.update({"seconds": dt, "evals": evals, "ess": ess, "chunk": s.chunk_samples()})
+        s.close()
+    prof = out["prof"]
+    gemms = {}
+    for name in ("gemm_fwd1", "gemm_dw1", "gemm_other", "head"):
+        ms, n, fl, _ = prof[name]
+        if n:
+            ach = fl / (ms * 1e-3) / 1e12
+            gemms[name] = {"total_ms": round(ms, 3), "launches": n, "avg_us": round(1e3 * ms / n, 1),
+                           "achieved": round(ach, 2), "unit": "TFLOP/s", "peak": PEAK["bf16"],
+                           "frac": round(ach / PEAK["bf16"], 4)}
+    return {"value": round(out["evals"] / out["seconds"], 1), "unit": "grad-evals/s",
+            "ms_per_step": round(1e3 * out["seconds"] / (len(run_sizes) - 1), 2),
+            "subset_sizes": run_sizes[1:], "chunk_samples": out["chunk"],
+            "mean_ess": round(float(np.mean(out["ess"])), 2),
+            "config": {"workload": f"MNIST-shaped synthetic templates 60000/10000, MLP 784-256-256-10 ReLU (D=269322), "
+                                   f"J={CFG3_J}, BF16 operands, prior N(0, {CFG3_PRIOR}^2), Langevin h=0.002, iterations "
+                                   f"1-{n_lead} of the Linear schedule C=kappa=1000 then {n_full} on all {N_TRAIN} samples, "
+                                   f"chunks of {out['chunk']} samples with activation recomputation",
+                       "particles": CFG3_J, "precision": "bf16"},
+            "roofline": roofline(prof, "bf16", len(run_sizes) - 1, False), "kernel_classes": gemms}
+
+
 def run_resampling(P, reps=200):
     """Per-call time of the stateless ancestor computations (Section 2): systematic from one
     offset and multinomial from J uniforms, both with the exact integer rule and the in-place
@@ -656,6 +719,11 @@ def main():
         cnn = run_cnn(P, max(1, args.cnn_steps), args.seed)
         log(f"cnn: {json.dumps(cnn)}")
 
+    deep = None
+    if not args.no_deep:
+        deep = run_config3(P, dev, args.seed)
+        log(f"deep: {json.dumps(deep)}")
+
     sda = None
     if not args.no_sda:
         sda = run_sda(P, dev, args.seed, max(1, args.sda_iters))
@@ -698,6 +766,7 @@ def main():
         "time_to_accuracy": tta,
         "proposal_network": training,
         "cnn_config2": cnn,
+        "deep_config3": deep,
         "sda": sda,
         "lenet5_pass": lenet,
         "resampling": resampling,
