@@ -64,6 +64,7 @@ def parse():
                     help="comma list of precision[-learned]; the first is the headline")
     ap.add_argument("--no-cnn", action="store_true", help="skip the convolutional-network workload")
     ap.add_argument("--cnn-steps", type=int, default=8)
+    ap.add_argument("--cnn-precision", default="bf16", help="operand precision of the convolutional workload")
     ap.add_argument("--no-sda", action="store_true", help="skip the smooth-data-annealing run")
     ap.add_argument("--no-deep", action="store_true", help="skip the 784-256-256-10, J = 1024 workload")
     ap.add_argument("--no-lenet", action="store_true", help="skip the LeNet-5 gradient-pass measurement")
@@ -283,7 +284,7 @@ CNN_J, CNN_N, CNN_NTEST, CNN_KAPPA, CNN_TOL = 128, 50000, 2000, 1000, 1e-2
 CNN_PRIOR = 0.05  # prior sd of every CNN weight: with sd 1 the 8192-input linear layer gives logits ~1e4
 
 
-def run_cnn(P, steps, seed):
+def run_cnn(P, steps, seed, precision="bf16"):
     """CIFAR-shaped workload: conv3x3(16) -> conv3x3(32) -> avgpool -> linear(10), J = 128, BF16,
     subset grown by kappa = 1000 when the posterior mean's relative change is below 1e-2."""
     import torch
@@ -299,7 +300,7 @@ def run_cnn(P, steps, seed):
     Xd, yd = torch.from_numpy(np.ascontiguousarray(X)).to(cuda), torch.from_numpy(y).to(cuda)
     Xtd = torch.from_numpy(np.ascontiguousarray(Xt.reshape(CNN_NTEST, -1))).to(cuda)
     ytd = torch.from_numpy(yt.astype(np.int32)).to(cuda)
-    cfg = P.SMCConfig(widths=CNN_DIMS, n_particles=CNN_J, model="cnn", precision="bf16", step_size=STEP,
+    cfg = P.SMCConfig(widths=CNN_DIMS, n_particles=CNN_J, model="cnn", precision=precision, step_size=STEP,
                       prior_std=CNN_PRIOR, seed=seed)
     s = P.SMCSampler(cfg, Xd, yd, m0=CNN_KAPPA, lambda0=CNN_N / CNN_KAPPA)
     s.resample()
@@ -326,10 +327,10 @@ def run_cnn(P, steps, seed):
             "steps": steps, "subset_sizes": sizes, "mean_ess": round(float(np.mean(ess)), 2),
             "test_accuracy": round(r["accuracy"], 4), "test_mean_log_pred": round(r["mean_log_pred"], 5),
             "config": {"workload": "CIFAR-shaped synthetic textures 50000/2000 (32x32x3), CNN conv3x3(16)-"
-                                   "conv3x3(32)-avgpool2-FC10 ReLU, J=128, BF16 operands, prior N(0, 0.05^2), Langevin h=0.002, "
-                                   "subset grown by 1000 when the posterior mean changes by < 1e-2",
-                       "particles": CNN_J, "precision": "bf16"},
-            "roofline": roofline(prof, "bf16", steps, False), "kernels": kernel_table(prof, "bf16"),
+                                   f"conv3x3(32)-avgpool2-FC10 ReLU, J=128, {precision} operands, prior N(0, 0.05^2), "
+                                   "Langevin h=0.002, subset grown by 1000 when the posterior mean changes by < 1e-2",
+                       "particles": CNN_J, "precision": precision},
+            "roofline": roofline(prof, precision, steps, False), "kernels": kernel_table(prof, precision),
             "host_seconds_incl_schedule": round(dt, 3)}
 
 
@@ -716,7 +717,7 @@ def main():
 
     cnn = None
     if not args.no_cnn:
-        cnn = run_cnn(P, max(1, args.cnn_steps), args.seed)
+        cnn = run_cnn(P, max(1, args.cnn_steps), args.seed, args.cnn_precision)
         log(f"cnn: {json.dumps(cnn)}")
 
     deep = None
