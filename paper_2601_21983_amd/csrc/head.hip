@@ -200,11 +200,17 @@ __device__ __forceinline__ void head_weights(const HeadArgs& a, const HeadLayout
   }
 }
 
-// Steps 1-4 on the 64-sample activation tile staged in As (and AsLo) whose first sample
-// (within the chunk) is s0.  Every thread of the workgroup calls it (it synchronises).
-template <typename T, int MODE, int NQ, bool SPL>
+// Steps 1-4 on the 64-sample activation tile staged in As (and AsLo): tile samples 0-31 are
+// chunk samples s0.., tile samples 32-63 chunk samples s1.. (s1 = s0 + 32 for a contiguous
+// tile).  Every thread of the workgroup calls it (it synchronises).
+// TRN (ReLU networks, staged layout): the tile's activations also sit transposed in the St
+// region ([unit][sample], written by the caller; rows H.. hold the ones column and zeros), the
+// hidden error is computed sample-major (each lane ends with four consecutive samples of one
+// unit) and stored straight to dT as one 4-sample vector, and the output-layer weight gradient
+// reads its activation operand as vectors from the transposed copy.
+template <typename T, int MODE, int NQ, bool SPL, bool TRN = false>
 __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& Lo, const HeadSmem<T>& S, int j, int s0,
-                                          float lam, float lam_b, bool alo, double& llacc, double& llacc_b,
+                                          int s1, float lam, float lam_b, bool alo, double& llacc, double& llacc_b,
                                           f32x4 (&dacc)[NQ]) {
   T *Wc = S.Wc, *Wt = S.Wt, *As = S.As, *WcLo = S.WcLo, *WtLo = S.WtLo, *AsLo = S.AsLo, *Dt = S.Dt, *St = S.St;
   const int H = a.H, C = a.C, Hp = Lo.Hp, AS = Lo.AS, WT = Lo.WT, DS = Lo.DS, SS = Lo.SS;
@@ -230,7 +236,7 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
 
   // ---- 2. likelihood and output error (sample cl, classes 4g + i)
   const int sl = w * 16 + cl;           // sample within the tile
-  const int sg = s0 + sl;               // sample within the chunk
+  const int sg = sl < 32 ? s0 + sl : s1 + (sl - 32);  // sample within the chunk
   const bool valid = sg < a.m_valid;
   const bool segb = a.c0 + sg >= a.m_split;  // second segment of a two-segment target
   const float lm = segb ? lam_b : lam;
@@ -284,7 +290,51 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
     }
   }
 
-  if (MODE == HEAD_TRAIN) {
+  if (MODE == HEAD_TRAIN && TRN) {
+    // ---- 3. delta_{L-1} = delta W (times act'), sample-major: lane (g, cl) ends with samples
+    // w*16 + 4g .. +3 of unit hb*16 + cl and stores them as one vector (ReLU: act' = [a > 0])
+    const T* AsT = St;
+    const int sl0 = w * 16 + 4 * g;                            // 4 samples, never across the halves
+    const int sg0 = sl0 < 32 ? s0 + sl0 : s1 + (sl0 - 32);
+    if (a.dT || a.dR) {
+      const typename V4<T>::type bd = pack4<T>(d);
+      for (int hb = 0; hb < NHB; ++hb) {
+        f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (SPL) v = mma16(bd, ld4(WtLo + (hb * 16 + cl) * WT + 4 * g), v);
+        v = mma16(bd, ld4(Wt + (hb * 16 + cl) * WT + 4 * g), v);
+        const int h = hb * 16 + cl;
+        if (h < H) {
+          const typename V4<T>::type ah = ld4(AsT + h * SS + sl0);
+          float dv[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) dv[i] = v4_at<T>(ah, i) > 0.0f ? v[i] : 0.0f;
+          if (a.dT)
+            *(typename V4<T>::type*)((T*)a.dT + (int64_t)j * a.sdTj + (int64_t)h * a.sdTh + sg0) = pack4<T>(dv);
+          if (a.dR) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              ((T*)a.dR)[(int64_t)j * a.sdRj + (int64_t)(sg0 + i) * a.sdRm + h] = cvt_out<T>(dv[i]);
+          }
+        }
+      }
+    }
+    // delta^T to LDS for the dW_L product
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Dt[(4 * g + i) * DS + sl] = cvt_out<T>(d[i]);
+    __syncthreads();
+    // ---- 4. dW_L += delta^T [A | 1] with the activation operand read from the transposed copy
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int hb = w + 4 * q;
+      if (hb >= NHB) break;
+#pragma unroll
+      for (int kb = 0; kb < HT / 16; ++kb) {
+        const typename V4<T>::type av = ld4(Dt + cl * DS + kb * 16 + 4 * g);
+        const typename V4<T>::type bv = ld4(AsT + (hb * 16 + cl) * SS + kb * 16 + 4 * g);
+        dacc[q] = mma16(av, bv, dacc[q]);
+      }
+    }
+  } else if (MODE == HEAD_TRAIN) {
     // ---- 3. delta_{L-1}^T = W^T delta^T (times act'), staged for sample-contiguous stores
     if (a.dT) {
       const typename V4<T>::type bd = pack4<T>(d);
@@ -316,12 +366,15 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
     for (int i = 0; i < 4; ++i) Dt[(4 * g + i) * DS + sl] = cvt_out<T>(d[i]);
     __syncthreads();
     if (a.dT && Lo.stage) {
-      // rows h < H of 64 samples each, 16-byte vectors
-      constexpr int VPR = HT * (int)sizeof(T) / 16;  // vectors per row
+      // rows h < H of 64 samples each (two runs of 32: s0.., s1..), 16-byte vectors
+      constexpr int EPV = 16 / (int)sizeof(T);       // elements per vector
+      constexpr int VPR = HT / EPV;                   // vectors per row
       for (int e = tid; e < H * VPR; e += HTHREADS) {
         const int h = e / VPR, v = e - h * VPR;
-        const u32x4 val = *(const u32x4*)(St + h * SS + v * (16 / (int)sizeof(T)));
-        *(u32x4*)((T*)a.dT + (int64_t)j * a.sdTj + (int64_t)h * a.sdTh + s0 + v * (16 / (int)sizeof(T))) = val;
+        const int t = v * EPV;                        // first tile sample of the vector
+        const int dst = t < 32 ? s0 + t : s1 + (t - 32);
+        const u32x4 val = *(const u32x4*)(St + h * SS + t);
+        *(u32x4*)((T*)a.dT + (int64_t)j * a.sdTj + (int64_t)h * a.sdTh + dst) = val;
       }
     }
     // ---- 4. dW_L += delta^T [A | 1]: this wave owns h-blocks w, w+4, ...  Like the other weight
@@ -513,7 +566,7 @@ __global__ __launch_bounds__(HTHREADS) void head_kernel(const HeadArgs a, const 
     stage(t);
     __syncthreads();
     if (t + 1 < t1) prefetch(t + 1);
-    head_tile<T, MODE, NQ, SPL>(a, Lo, S, j, t * HT, lam, lam_b, alo, llacc, llacc_b, dacc);
+    head_tile<T, MODE, NQ, SPL>(a, Lo, S, j, t * HT, t * HT + 32, lam, lam_b, alo, llacc, llacc_b, dacc);
   }
   head_finish<T, MODE, NQ>(a, Lo, S, j, split, llacc, llacc_b, dacc);
 }
@@ -535,7 +588,11 @@ __device__ __forceinline__ float fused_act(float v) {
 
 constexpr int FBM = 256, FBN = 128;  // tile: samples x (one particle's padded units)
 
-template <int MODE, bool SPL, int ACT>
+// Pass q of the output-layer work takes row block q of both wave rows: tile samples 0-31 are
+// chunk samples m0 + 32q.., tile samples 32-63 are m0 + 128 + 32q.., so all four waves stage
+// activations in every pass.  TRN (ReLU): the activations' hi plane is also written transposed
+// into the St region for the sample-major backward of head_tile.
+template <int MODE, bool SPL, int ACT, bool TRN>
 __global__ __launch_bounds__(HTHREADS, 2) void fwd_head_kernel(const GemmParams p, const HeadArgs a,
                                                                 const HeadLayout Lo) {
   typedef __bf16 T;
@@ -553,7 +610,14 @@ __global__ __launch_bounds__(HTHREADS, 2) void fwd_head_kernel(const GemmParams 
   const HeadSmem<T> S = head_smem<T>(fsm, Lo);
   head_weights<T, MODE, SPL>(a, Lo, S, jp);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-  const int H = a.H, Hp = Lo.Hp, AS = Lo.AS;
+  const int H = a.H, Hp = Lo.Hp, AS = Lo.AS, SS = Lo.SS;
+  if (TRN && MODE == HEAD_TRAIN) {
+    // constant rows of the transposed copy: the ones column (unit H) and zero padding
+    for (int e = tid; e < (Hp - H) * HT; e += HTHREADS) {
+      const int u = H + e / HT, sl = e % HT;
+      S.St[u * SS + sl] = to_bf16(u == H ? 1.0f : 0.0f);
+    }
+  }
   const float lam = a.scale ? (float)a.scale[jp] : (float)a.lambda;
   const float lam_b = a.scale ? lam : (float)a.lambda_b;
   const float* b1 = p.bias + (int64_t)jp * H;
@@ -561,39 +625,46 @@ __global__ __launch_bounds__(HTHREADS, 2) void fwd_head_kernel(const GemmParams 
   f32x4 dacc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) dacc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  const bool odd = lane & 1;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    // samples m0 + 64q .. +63 sit in accumulator blocks 2(q&1), 2(q&1)+1 of the waves with wm = q/2
-    if (wm == (q >> 1)) {
+    // block q of this wave: tile rows wm*32 + (0..31), units wn*64 + jj*32 + lane%32
+#pragma unroll
+    for (int jj = 0; jj < FN; ++jj) {
+      const int u = wn * WN + jj * 32 + (lane & 31);
+      if (u >= Hp) continue;  // Hp is a multiple of 16: pairs agree
+      const float bias = u < H ? b1[u] : 0.0f;
+      const f32x16& ac = acc[q][jj];
       // lane pairs (units u, u+1) trade one value per row pair (r, r+1) over DPP, so that
       // the even lane writes row r and the odd lane row r+1, each as one 4-byte store
-      const bool odd = lane & 1;
 #pragma unroll
-      for (int ii = 0; ii < 2; ++ii)
+      for (int e = 0; e < 16; e += 2) {
+        const int r = wm * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        const float v0 = u < H ? fused_act<ACT>(ac[e] + bias) : (u == H ? 1.0f : 0.0f);      // row r
+        const float v1 = u < H ? fused_act<ACT>(ac[e + 1] + bias) : (u == H ? 1.0f : 0.0f);  // row r + 1
+        const float recv = __builtin_bit_cast(
+            float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, odd ? v0 : v1), 0xB1, 0xF, 0xF, false));
+        const float c0 = odd ? recv : v0;  // unit u & ~1
+        const float c1 = odd ? v1 : recv;  // unit u | 1
+        const int off = (odd ? r + 1 : r) * AS + (u & ~1);
+        const __bf16 h0 = to_bf16(c0), h1 = to_bf16(c1);
+        *(uint32_t*)(S.As + off) = pack2(h0, h1);
+        if (SPL) *(uint32_t*)(S.AsLo + off) = pack2(to_bf16(c0 - from_bf16(h0)), to_bf16(c1 - from_bf16(h1)));
+      }
+      if (TRN && MODE == HEAD_TRAIN && u < H) {
+        // four consecutive tile rows of unit u per 8-byte store
 #pragma unroll
-        for (int jj = 0; jj < FN; ++jj) {
-          const int u = wn * WN + jj * 32 + (lane & 31);
-          if (u >= Hp) continue;  // Hp is a multiple of 16: pairs agree
-          const float bias = u < H ? b1[u] : 0.0f;
+        for (int ee = 0; ee < 4; ++ee) {
+          float v4[4];
 #pragma unroll
-          for (int e = 0; e < 16; e += 2) {
-            const int r = ii * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-            const f32x16& ac = acc[2 * (q & 1) + ii][jj];
-            const float v0 = u < H ? fused_act<ACT>(ac[e] + bias) : (u == H ? 1.0f : 0.0f);      // row r
-            const float v1 = u < H ? fused_act<ACT>(ac[e + 1] + bias) : (u == H ? 1.0f : 0.0f);  // row r + 1
-            const float recv = __builtin_bit_cast(
-                float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, odd ? v0 : v1), 0xB1, 0xF, 0xF, false));
-            const float c0 = odd ? recv : v0;  // unit u & ~1
-            const float c1 = odd ? v1 : recv;  // unit u | 1
-            const int off = (odd ? r + 1 : r) * AS + (u & ~1);
-            const __bf16 h0 = to_bf16(c0), h1 = to_bf16(c1);
-            *(uint32_t*)(S.As + off) = pack2(h0, h1);
-            if (SPL) *(uint32_t*)(S.AsLo + off) = pack2(to_bf16(c0 - from_bf16(h0)), to_bf16(c1 - from_bf16(h1)));
-          }
+          for (int t = 0; t < 4; ++t) v4[t] = fused_act<ACT>(ac[4 * ee + t] + bias);
+          *(typename V4<T>::type*)(S.St + u * SS + wm * 32 + 8 * ee + 4 * (lane >> 5)) = pack4<T>(v4);
         }
+      }
     }
     __syncthreads();
-    head_tile<T, MODE, NQ, SPL>(a, Lo, S, jp, m0 + 64 * q, lam, lam_b, SPL, llacc, llacc_b, dacc);
+    head_tile<T, MODE, NQ, SPL, TRN>(a, Lo, S, jp, m0 + 32 * q, m0 + 128 + 32 * q, lam, lam_b, SPL, llacc, llacc_b,
+                                     dacc);
     __syncthreads();
   }
   head_finish<T, MODE, NQ>(a, Lo, S, jp, tm, llacc, llacc_b, dacc);
@@ -694,11 +765,13 @@ hipError_t fwd_head_run(const GemmParams& p, const HeadArgs& a, int mode, int sp
   const int stage = split ? gcore::stage_bytes<FBM, FBN, true>() : gcore::stage_bytes<FBM, FBN, false>();
   const size_t smem = (size_t)std::max(stage, L.total);
   const dim3 grid((unsigned)(nM * a.J));
-#define FH_LAUNCH(MODE, SPL, ACT) hipLaunchKernelGGL((fwd_head_kernel<MODE, SPL, ACT>), grid, dim3(HTHREADS), smem, s, p, a, L)
-#define FH_ACT(MODE, SPL)                                      \
-  do {                                                         \
-    if (act == ACT_RELU) FH_LAUNCH(MODE, SPL, ACT_RELU);       \
-    else FH_LAUNCH(MODE, SPL, ACT_TANH);                       \
+#define FH_LAUNCH(MODE, SPL, ACT, TRN) \
+  hipLaunchKernelGGL((fwd_head_kernel<MODE, SPL, ACT, TRN>), grid, dim3(HTHREADS), smem, s, p, a, L)
+#define FH_ACT(MODE, SPL)                                          \
+  do {                                                             \
+    if (act == ACT_RELU && L.stage) FH_LAUNCH(MODE, SPL, ACT_RELU, true); \
+    else if (act == ACT_RELU) FH_LAUNCH(MODE, SPL, ACT_RELU, false); \
+    else FH_LAUNCH(MODE, SPL, ACT_TANH, false);                    \
   } while (0)
 #define FH_MODE(SPL)                                           \
   do {                                                         \
@@ -736,13 +809,14 @@ hipError_t head_set_smem_limits() {
   HEAD_ATTR3(__bf16, HEAD_PREDICT, true);
 #undef HEAD_ATTR3
 #undef HEAD_ATTR
-#define FH_ATTR(MODE, SPL, ACT)                                                                        \
-  if ((e = hipFuncSetAttribute((const void*)fwd_head_kernel<MODE, SPL, ACT>,                             \
+#define FH_ATTR(MODE, SPL, ACT, TRN)                                                                   \
+  if ((e = hipFuncSetAttribute((const void*)fwd_head_kernel<MODE, SPL, ACT, TRN>,                        \
                                hipFuncAttributeMaxDynamicSharedMemorySize, LDS_LIMIT)) != hipSuccess) \
   return e
-#define FH_ATTR2(MODE, SPL) \
-  FH_ATTR(MODE, SPL, ACT_RELU); \
-  FH_ATTR(MODE, SPL, ACT_TANH)
+#define FH_ATTR2(MODE, SPL)            \
+  FH_ATTR(MODE, SPL, ACT_RELU, true);  \
+  FH_ATTR(MODE, SPL, ACT_RELU, false); \
+  FH_ATTR(MODE, SPL, ACT_TANH, false)
   FH_ATTR2(HEAD_TRAIN, false);
   FH_ATTR2(HEAD_FORWARD, false);
   FH_ATTR2(HEAD_PREDICT, false);
