@@ -82,34 +82,36 @@ def parse():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mnist_shaped_bf16x3_learned_hbm_traffic.json")
 TRAFFIC_LEG = "bf16x3-learned"
-TRAFFIC_SOURCES = ["paper_2601_21983_amd/csrc/gemm.hip", "paper_2601_21983_amd/csrc/gemm_core.h",
-                   "paper_2601_21983_amd/csrc/head.hip", "paper_2601_21983_amd/csrc/smc_kernels.hip",
-                   "paper_2601_21983_amd/csrc/learned.hip", "paper_2601_21983_amd/csrc/smc_api.hip",
-                   "paper_2601_21983_amd/csrc/kernels.h", "paper_2601_21983_amd/csrc/common.h",
-                   "paper_2601_21983_amd/csrc/gemm.h"]
 
 
-def source_digest():
+def source_digest(files):
     import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel, steps):
-    """HBM bytes per launch of `kernel` from the committed PMC profile, if it was taken
-    on the current kernel sources and the same number of steps; else None."""
+def measured_traffic(kernel, m_mean):
+    """HBM bytes per launch of `kernel` at a mean of m_mean samples per launch (padded to 256),
+    from the committed PMC fit (fetch and write, each a + b*M), if the fit was taken on the
+    current sources of that kernel; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != source_digest() or rec.get("steps") != steps:
+    try:
+        if rec.get("source_sha256") != source_digest(rec["source_files"]):
+            return None
+    except (OSError, KeyError):
         return None
     k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+    if k is None or "fetch_bytes" not in k:
+        return None
+    (fa, fb), (wa, wb) = k["fetch_bytes"], k["write_bytes"]
+    return round(fa + fb * m_mean + wa + wb * m_mean)
 
 
 N_VAL = 2000  # held-out samples of the proposal judge (a third seed, disjoint from train and test)
@@ -127,6 +129,13 @@ def make_data():
 def passes(sizes, k):
     """gradient passes of iteration k: one for the grown subset (if it grew) + one per leapfrog step"""
     return 1 + (1 if sizes[k] != sizes[k - 1] else 0)
+
+
+def pass_mean_m(sizes, steps):
+    """Mean samples per gradient pass over iterations 1..steps, each padded to the fused kernel's
+    256-sample tiles (the unit of the traffic fit)."""
+    tot = sum(passes(sizes, k) * ((sizes[k] + 255) // 256 * 256) for k in range(1, steps + 1))
+    return tot / sum(passes(sizes, k) for k in range(1, steps + 1))
 
 
 def leg_parts(leg):
@@ -260,10 +269,12 @@ def kernel_table(prof, prec):
     return out
 
 
-def roofline(prof, prec, steps, with_traffic):
-    # dominant kernel class by total time
+def roofline(prof, prec, m_mean=None):
+    """The dominant kernel class (by total time) against its roofline; with m_mean (the mean
+    samples per launch of the timed gradient passes, padded to 256) the HBM traffic per launch
+    from the committed PMC fit."""
     name, (ms, n, fl, by) = max(prof.items(), key=lambda kv: kv[1][0])
-    traffic = measured_traffic(name, steps) if with_traffic else None
+    traffic = measured_traffic(name, m_mean) if m_mean is not None else None
     if fl > 0 and name.startswith("gemm"):
         ach = fl / (ms * 1e-3) / 1e12
         peak = PEAK[prec]
@@ -330,7 +341,7 @@ def run_cnn(P, steps, seed, precision="bf16"):
                                    f"conv3x3(32)-avgpool2-FC10 ReLU, J=128, {precision} operands, prior N(0, 0.05^2), "
                                    "Langevin h=0.002, subset grown by 1000 when the posterior mean changes by < 1e-2",
                        "particles": CNN_J, "precision": precision},
-            "roofline": roofline(prof, precision, steps, False), "kernels": kernel_table(prof, precision),
+            "roofline": roofline(prof, precision), "kernels": kernel_table(prof, precision),
             "host_seconds_incl_schedule": round(dt, 3)}
 
 
@@ -551,7 +562,7 @@ def run_config3(P, dev, seed, n_lead=4, n_full=2):
                                    f"1-{n_lead} of the Linear schedule C=kappa=1000 then {n_full} on all {N_TRAIN} samples, "
                                    f"chunks of {out['chunk']} samples with activation recomputation",
                        "particles": CFG3_J, "precision": "bf16"},
-            "roofline": roofline(prof, "bf16", len(run_sizes) - 1, False), "kernel_classes": gemms}
+            "roofline": roofline(prof, "bf16"), "kernel_classes": gemms}
 
 
 def run_resampling(P, reps=200):
@@ -762,7 +773,7 @@ def main():
                   "iterations with every launch bracketed by HIP events on the library's stream",
         "seconds_profiled_run": round(b["seconds_profiled"], 4),
         "proposal_judge": b.get("judge"),
-        "roofline": roofline(b["prof"], hprec, steps, head == TRAFFIC_LEG),
+        "roofline": roofline(b["prof"], hprec, pass_mean_m(sizes, steps) if head == TRAFFIC_LEG else None),
         "cpu_baseline": cpu,
         "time_to_accuracy": tta,
         "proposal_network": training,
@@ -777,7 +788,7 @@ def main():
         r = res[l]
         line[l.replace("-", "_") + ("" if leg_parts(l)[1] == "learned" else "_plain")] = {
             "value": round(r["rate"], 1), "unit": "grad-evals/s", "ms_per_step": round(1e3 * r["seconds"] / steps, 4),
-            "roofline": roofline(r["prof"], leg_parts(l)[0], steps, False), "proposal_judge": r.get("judge")}
+            "roofline": roofline(r["prof"], leg_parts(l)[0]), "proposal_judge": r.get("judge")}
     print(json.dumps(line), flush=True)
 
 
