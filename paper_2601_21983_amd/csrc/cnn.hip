@@ -322,6 +322,142 @@ __global__ void slice_sum_kernel(const float* __restrict__ part, int S, int M, i
   *dst = beta ? *dst + acc : acc;
 }
 
+// ------------------------------------------------------------------ implicit conv2 (BF16)
+// For 32-pixel-wide images with C1 = 16 and C2 = 32 channels, conv2 and its input error run as
+// implicit GEMMs: one workgroup per (8-row band, image, particle) stages the band's activation
+// (or error) halo in LDS and contracts it tap by tap on the matrix cores, so no patch matrix is
+// written.  A halo pixel's 16-byte channel chunks are stored at slot c ^ f(col), which puts the
+// 16 consecutive pixels a half-wave reads at one chunk on 16 distinct bank groups.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short s16x4_t;
+constexpr int IB = 8;            // output rows per workgroup
+constexpr int IHR = IB + 2;      // halo rows
+constexpr int IHC = 32 + 2;      // halo columns
+
+// act2 = ReLU(conv2(act1) + b2) and pooled = its 2x2 average, for one particle, image and band.
+// Wave w computes rows 2w, 2w+1 of the band (one 32x32 MFMA block each: 32 pixels x 32 output
+// channels); K runs over the nine taps, one v_mfma_f32_32x32x16_bf16 per tap (16 channels), in
+// the same order as the explicit GEMM over the patch row.  The epilogue writes act2 (one pixel's
+// 32 channels per 32 lanes) and the pool from the rounded values in pool_kernel's order.
+__global__ __launch_bounds__(256) void conv2_fwd_implicit_kernel(const __bf16* __restrict__ act1, int64_t sA1,
+                                                                 const __bf16* __restrict__ w2, int64_t ldw,
+                                                                 const float* __restrict__ b2, __bf16* __restrict__ act2,
+                                                                 int64_t sA2, __bf16* __restrict__ pooled, int64_t sP,
+                                                                 CnnDims d) {
+  __shared__ __attribute__((aligned(16))) char halo[IHR * IHC * 32];
+  const int j = blockIdx.z, n = blockIdx.y, y0 = blockIdx.x * IB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const __bf16* a1 = act1 + (int64_t)j * sA1 + (int64_t)n * d.HW * 16;
+  for (int e = tid; e < IHR * IHC * 2; e += 256) {
+    const int row = e / (IHC * 2), rem = e - row * (IHC * 2), col = rem >> 1, c = rem & 1;
+    const int yy = y0 - 1 + row, xx = col - 1;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (yy >= 0 && yy < d.H && xx >= 0 && xx < 32) v = *(const u32x4*)(a1 + (yy * 32 + xx) * 16 + c * 8);
+    *(u32x4*)(halo + (row * IHC + col) * 32 + ((c ^ ((col >> 3) & 1)) << 4)) = v;
+  }
+  // B fragments of the nine taps: lane l holds W2[l % 32][tap * 16 + 8 (l / 32) .. +7]
+  const __bf16* wj = w2 + ((int64_t)j * 32 + (lane & 31)) * ldw + 8 * (lane >> 5);
+  u32x4 bfr[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) bfr[t] = *(const u32x4*)(wj + t * 16);
+  __syncthreads();
+  f32x16 acc[2];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[ib][q] = 0.0f;
+    const int r = 2 * w + ib;  // band row of this block
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int ky = t / 3, kx = t % 3;
+      const int col = (lane & 31) + kx, c = lane >> 5;
+      const u32x4 av = *(const u32x4*)(halo + ((r + ky) * IHC + col) * 32 + ((c ^ ((col >> 3) & 1)) << 4));
+      acc[ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, av),
+                                                        __builtin_bit_cast(bf16x8_t, bfr[t]), acc[ib], 0, 0, 0);
+    }
+  }
+  // epilogue: lane l holds output channel c2 = l % 32 of pixels x = 8 (q / 4) + 4 (l / 32) + q % 4
+  const int c2 = lane & 31;
+  const float bias = b2[(int64_t)j * 32 + c2];
+  __bf16* o2 = act2 + (int64_t)j * sA2 + (int64_t)n * d.HW * 32;
+  __bf16 v[2][16];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib) {
+    const int y = y0 + 2 * w + ib;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int x = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+      v[ib][q] = to_bf16(fmaxf(acc[ib][q] + bias, 0.0f));
+      o2[(y * 32 + x) * 32 + c2] = v[ib][q];
+    }
+  }
+  // 2x2 average pooling: rows y0 + 2w and +1 are this wave's two blocks, pixel pairs (x, x+1)
+  // are registers q, q+1 with q % 4 in {0, 2}
+  const int py = (y0 + 2 * w) >> 1;
+  __bf16* po = pooled + (int64_t)j * sP + (int64_t)n * d.F3;
+#pragma unroll
+  for (int q = 0; q < 16; q += 2) {
+    const int x = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+    const float sum = from_bf16(v[0][q]) + from_bf16(v[0][q + 1]) + from_bf16(v[1][q]) + from_bf16(v[1][q + 1]);
+    po[(py * d.Wp + (x >> 1)) * 32 + c2] = to_bf16(0.25f * sum);
+  }
+}
+
+// d1t[j C1 + c][r] = 1{act1[r][c] > 0} sum over taps t and channels c2 of d2[r - off(t)][c2] W2[c2][t C1 + c]
+// (the error at the conv1 output; off(t) = (ky - 1, kx - 1)) for one particle, image and band.
+// Wave w computes band rows 2w, 2w+1 as four 16-pixel blocks; per block one
+// v_mfma_f32_16x16x32_bf16 per tap (K = the 32 channels of d2), B from the transposed weight
+// copy wT[j][t C1 + c][c2].  Lane l ends with four consecutive pixels of channel l % 16 and
+// writes them as one 8-byte vector.
+__global__ __launch_bounds__(256) void conv2_dgrad_implicit_kernel(const __bf16* __restrict__ d2, int64_t sA2,
+                                                                   const __bf16* __restrict__ wT, int64_t ldwT,
+                                                                   const __bf16* __restrict__ act1, int64_t sA1,
+                                                                   __bf16* __restrict__ d1t, int64_t ld, CnnDims d) {
+  __shared__ __attribute__((aligned(16))) char halo[IHR * IHC * 64];
+  __shared__ __attribute__((aligned(16))) __bf16 a1s[IB * 32 * 16];
+  const int j = blockIdx.z, n = blockIdx.y, y0 = blockIdx.x * IB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const __bf16* e2 = d2 + (int64_t)j * sA2 + (int64_t)n * d.HW * 32;
+  for (int e = tid; e < IHR * IHC * 4; e += 256) {
+    const int row = e / (IHC * 4), rem = e - row * (IHC * 4), col = rem >> 2, c = rem & 3;
+    const int yy = y0 - 1 + row, xx = col - 1;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (yy >= 0 && yy < d.H && xx >= 0 && xx < 32) v = *(const u32x4*)(e2 + (yy * 32 + xx) * 32 + c * 8);
+    *(u32x4*)(halo + (row * IHC + col) * 64 + ((c ^ ((col >> 2) & 3)) << 4)) = v;
+  }
+  const __bf16* a1 = act1 + (int64_t)j * sA1 + ((int64_t)n * d.HW + y0 * 32) * 16;
+  for (int e = tid; e < IB * 32 * 2; e += 256) *(u32x4*)(a1s + e * 8) = *(const u32x4*)(a1 + e * 8);
+  // B fragments: lane l holds W2[c2 = 8 (l / 16) .. +7][t C1 + l % 16] from wT row t C1 + l % 16
+  const __bf16* wj = wT + ((int64_t)j * d.K2 + (lane & 15)) * ldwT + 8 * (lane >> 4);
+  u32x4 bfr[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) bfr[t] = *(const u32x4*)(wj + (int64_t)t * 16 * ldwT);
+  __syncthreads();
+  const int c = lane & 15;
+  for (int mb = 0; mb < 4; ++mb) {
+    const int r = 2 * w + (mb >> 1), x0 = 16 * (mb & 1);  // band row and first pixel of the block
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int ky = t / 3, kx = t % 3;
+      const int hrow = r - ky + 2, col = x0 + (lane & 15) - kx + 2, ch = lane >> 4;
+      const u32x4 av = *(const u32x4*)(halo + (hrow * IHC + col) * 64 + ((ch ^ ((col >> 2) & 3)) << 4));
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, av),
+                                                    __builtin_bit_cast(bf16x8_t, bfr[t]), acc, 0, 0, 0);
+    }
+    // rows 4 (l / 16) + i of the block: pixels x0 + 4 (l / 16) + i, channel c
+    const int xb = x0 + 4 * (lane >> 4);
+    s16x4_t o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float m = from_bf16(a1s[(r * 32 + xb + i) * 16 + c]);
+      o[i] = __builtin_bit_cast(short, to_bf16(m > 0.0f ? acc[i] : 0.0f));
+    }
+    const int64_t rr = (int64_t)n * d.HW + (y0 + r) * 32 + xb;
+    *(s16x4_t*)(d1t + ((int64_t)j * 16 + c) * ld + rr) = o;
+  }
+}
+
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // the kernels index pixels of a chunk (mcv * HW) and positions inside one image in 32 bits,
@@ -331,6 +467,33 @@ bool grid_ok(int mcv, const CnnDims& d, int64_t per_image) {
 }
 
 }  // namespace
+
+bool cnn_implicit_supported(const CnnDims& d, int bf16) {
+  return bf16 && d.W == 32 && d.H % IB == 0 && d.C1 == 16 && d.C2 == 32 && d.K2 == 144 && d.Hp * 2 == d.H &&
+         d.Wp * 2 == d.W;
+}
+
+hipError_t cnn_conv2_fwd_implicit_run(const void* act1, int64_t sA1, const void* w2, int64_t ldw, const float* b2,
+                                      void* act2, int64_t sA2, void* pooled, int64_t sP, int mcv, const CnnDims& d,
+                                      int J, hipStream_t s) {
+  if (!cnn_implicit_supported(d, 1) || mcv < 1 || mcv > 65535 || J < 1 || J > 65535) return hipErrorInvalidValue;
+  if (((uintptr_t)act1 | (uintptr_t)w2 | (uintptr_t)act2) & 15 || ldw % 8 || sA1 % 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(conv2_fwd_implicit_kernel, dim3(d.H / IB, mcv, J), dim3(256), 0, s, (const __bf16*)act1, sA1,
+                     (const __bf16*)w2, ldw, b2, (__bf16*)act2, sA2, (__bf16*)pooled, sP, d);
+  return hipGetLastError();
+}
+
+hipError_t cnn_conv2_dgrad_implicit_run(const void* d2, int64_t sA2, const void* wT, int64_t ldwT, const void* act1,
+                                        int64_t sA1, void* d1t, int64_t ld, int mcv, const CnnDims& d, int J,
+                                        hipStream_t s) {
+  if (!cnn_implicit_supported(d, 1) || mcv < 1 || mcv > 65535 || J < 1 || J > 65535) return hipErrorInvalidValue;
+  if (((uintptr_t)d2 | (uintptr_t)wT | (uintptr_t)act1 | (uintptr_t)d1t) & 15 || ldwT % 8 || sA2 % 8 || sA1 % 8 ||
+      ld % 4)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(conv2_dgrad_implicit_kernel, dim3(d.H / IB, mcv, J), dim3(256), 0, s, (const __bf16*)d2, sA2,
+                     (const __bf16*)wT, ldwT, (const __bf16*)act1, sA1, (__bf16*)d1t, ld, d);
+  return hipGetLastError();
+}
 
 hipError_t cnn_im2col_x_run(const void* X, int64_t xld, int64_t c0, int mcv, const CnnDims& d, void* p1, int bf16,
                             hipStream_t s) {

@@ -835,6 +835,13 @@ void cnn_forward_chunk(smc_t h, const void* Xop, int64_t c0, int mcv) {
     p.out0.rstr = d.C1;
     gemm(h, p, SMC_K_GEMM_FWD1, 2.0 * R * J * d.C1 * d.K1);
   }
+  if (cnn_implicit_supported(d, bf)) {
+    // conv2 as an implicit GEMM over the activation halo, with the 2x2 pooling in its epilogue
+    timed(h, SMC_K_GEMM_FWD1, 2.0 * R * J * d.C2 * d.K2, 0.0, [&]() {
+      HIPCHECK(cnn_conv2_fwd_implicit_run(b.act1, b.s_act1, h->net.w[1], h->net.ldw[1], h->net.bias[1], b.act2,
+                                          b.s_act2, b.pooled, b.s_pool, mcv, d, J, h->stream));
+    });
+  } else {
   timed(h, SMC_K_OTHER, 0.0, (double)J * R * d.K2 * h->esz,
         [&]() { HIPCHECK(cnn_im2col_a_run(b.act1, b.s_act1, mcv, d, J, b.big, b.s_big, bf, h->stream)); });
   {
@@ -861,6 +868,7 @@ void cnn_forward_chunk(smc_t h, const void* Xop, int64_t c0, int mcv) {
   }
   timed(h, SMC_K_OTHER, 0.0, (double)J * R * d.C2 * h->esz * 1.25,
         [&]() { HIPCHECK(cnn_pool_run(b.act2, b.s_act2, mcv, d, J, b.pooled, b.s_pool, bf, h->stream)); });
+  }
   {
     // linear layer, batched over particles; FP32 outputs (the bias is added with the softmax)
     GemmParams p;
@@ -988,6 +996,13 @@ void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const doubl
       p.out0.rstr = d.K2 + 1;
       gemm(h, p, SMC_K_GEMM_DW1, 2.0 * R * J * d.C2 * (d.K2 + 1));
     }
+    if (cnn_implicit_supported(d, bf)) {
+      // the error at the conv1 output as an implicit GEMM over the d2 halo (transposed conv2)
+      timed(h, SMC_K_GEMM_OTHER, 2.0 * R * J * d.C2 * d.K2, 0.0, [&]() {
+        HIPCHECK(cnn_conv2_dgrad_implicit_run(b.d2, b.s_act2, b.wT[1], b.ldwT[1], b.act1, b.s_act1, b.d1t, b.RP, mcv,
+                                              d, J, h->stream));
+      });
+    } else {
     {
       // patch errors d2 [R x C2] . W2 [C2 x K2] (B operand: W2^T rows)
       GemmParams p;
@@ -1015,6 +1030,7 @@ void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const doubl
     timed(h, SMC_K_OTHER, 0.0, (double)J * R * (d.K2 + 2 * d.C1) * h->esz, [&]() {
       HIPCHECK(cnn_col2im_run(b.big, b.s_big, b.act1, b.s_act1, mcv, d, J, b.RP, b.d1t, bf, h->stream));
     });
+    }
     timed(h, SMC_K_OTHER, 0.0, (double)R * (d.K1 + 1) * h->esz,
           [&]() { HIPCHECK(cnn_im2col_xt_run(h->X, h->xld, c0, mcv, d, b.RP, b.p1t, bf, h->stream)); });
     {
