@@ -16,6 +16,8 @@
 // tap = ky * 3 + kx; output pixel (y, x) reads input pixel (y + ky - 1, x + kx - 1).
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace smc {
 
 namespace {
@@ -458,6 +460,102 @@ __global__ __launch_bounds__(256) void conv2_dgrad_implicit_kernel(const __bf16*
   }
 }
 
+// [W2 | b2] gradient of particle j as an implicit GEMM over pixels: out[c2][t C1 + c] =
+// sum_r d2[r][c2] act1[r + off(t)][c], out[c2][K2] = sum_r d2[r][c2].  M = the 32 output
+// channels, N = the 145 columns in five 32-wide blocks (taps 2b, 2b+1; the last block holds tap
+// 8, the ones column at 144 and zeros), K = 16 pixels per v_mfma_f32_32x32x16_bf16.  The error
+// operand comes from d2t[j C2 + c2][r] (eight consecutive pixels per lane); the activation
+// operand from three copies of the band's halo, channel-major and shifted by kx, so every
+// eight-pixel read is aligned.  Workgroup (g, j) takes bands g, g + G, ...; wave w the 16-pixel
+// steps 4w .. 4w + 3 of each band, and each wave writes its own FP32 partial
+// part[j][g][w][32][145], summed in a fixed order by conv2_wgrad_sum_kernel.
+constexpr int WG_COLS = 145;
+__global__ __launch_bounds__(256) void conv2_wgrad_implicit_kernel(const __bf16* __restrict__ d2t, int64_t ld,
+                                                                   const __bf16* __restrict__ act1, int64_t sA1,
+                                                                   int mcv, CnnDims d, int G, float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) __bf16 a1T[3][16][IHR][32];
+  const int g = blockIdx.x, j = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int bands = mcv * (d.H / IB);
+  f32x16 acc[5];
+#pragma unroll
+  for (int b = 0; b < 5; ++b)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[b][q] = 0.0f;
+  // the ones column (bias) of block 4 and its zero columns beyond
+  u32x4 ones;
+  {
+    const int col = 128 + (lane & 31);
+    const uint32_t one2 = (uint32_t)__builtin_bit_cast(uint16_t, to_bf16(1.0f)) * 0x10001u;
+    const uint32_t v = col == 144 ? one2 : 0u;
+    ones = u32x4{v, v, v, v};
+  }
+  const __bf16* a1 = act1 + (int64_t)j * sA1;
+  for (int band = g; band < bands; band += G) {
+    const int n = band / (d.H / IB), y0 = (band - n * (d.H / IB)) * IB;
+    __syncthreads();  // the previous band's reads of a1T are done
+    for (int e = tid; e < IHR * IHC * 2; e += 256) {
+      const int row = e / (IHC * 2), rem = e - row * (IHC * 2), hc = rem >> 1, c8 = (rem & 1) * 8;
+      const int yy = y0 - 1 + row, xx = hc - 1;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (yy >= 0 && yy < d.H && xx >= 0 && xx < 32)
+        v = *(const u32x4*)(a1 + ((int64_t)n * d.HW + yy * 32 + xx) * 16 + c8);
+      const __bf16* vv = (const __bf16*)&v;
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        const int p = hc - kx;  // copy kx holds halo column p + kx at position p
+        if (p >= 0 && p < 32) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) a1T[kx][c8 + i][row][p] = vv[i];
+        }
+      }
+    }
+    __syncthreads();
+    const int64_t rb = (int64_t)n * d.HW + y0 * 32;  // first pixel of the band
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int ks = 4 * w + s;                      // 16-pixel step of the band
+      const int r = ks >> 1, x0 = (ks & 1) * 16 + 8 * (lane >> 5);
+      const u32x4 av = *(const u32x4*)(d2t + ((int64_t)j * 32 + (lane & 31)) * ld + rb + r * 32 + x0);
+#pragma unroll
+      for (int b = 0; b < 5; ++b) {
+        const int col = b * 32 + (lane & 31);
+        u32x4 bv;
+        if (b < 4 || col < 144) {
+          const int t = col >> 4, c = col & 15, ky = t / 3, kx = t % 3;
+          bv = *(const u32x4*)&a1T[kx][c][r + ky][x0];
+        } else {
+          bv = ones;
+        }
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, av),
+                                                         __builtin_bit_cast(bf16x8_t, bv), acc[b], 0, 0, 0);
+      }
+    }
+  }
+  // rows (c2) 8 (q / 4) + 4 (l / 32) + q % 4, column b * 32 + l % 32
+  float* o = part + (((int64_t)j * G + g) * 4 + w) * (32 * WG_COLS);
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    const int col = b * 32 + (lane & 31);
+    if (col >= WG_COLS) continue;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) o[(8 * (q >> 2) + 4 * (lane >> 5) + (q & 3)) * WG_COLS + col] = acc[b][q];
+  }
+}
+
+// g[j][off + e] (+)= sum over the 4 G partials of particle j in order, e < 32 * 145
+__global__ void conv2_wgrad_sum_kernel(const float* __restrict__ part, int G, float* g, int64_t D, int64_t off,
+                                       int beta) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (e >= 32 * WG_COLS) return;
+  const float* p = part + (int64_t)j * G * 4 * (32 * WG_COLS) + e;
+  float acc = 0.0f;
+  for (int k = 0; k < 4 * G; ++k) acc += p[(int64_t)k * (32 * WG_COLS)];
+  float* dst = g + (int64_t)j * D + off + e;
+  *dst = beta ? *dst + acc : acc;
+}
+
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // the kernels index pixels of a chunk (mcv * HW) and positions inside one image in 32 bits,
@@ -480,6 +578,23 @@ hipError_t cnn_conv2_fwd_implicit_run(const void* act1, int64_t sA1, const void*
   if (((uintptr_t)act1 | (uintptr_t)w2 | (uintptr_t)act2) & 15 || ldw % 8 || sA1 % 8) return hipErrorInvalidValue;
   hipLaunchKernelGGL(conv2_fwd_implicit_kernel, dim3(d.H / IB, mcv, J), dim3(256), 0, s, (const __bf16*)act1, sA1,
                      (const __bf16*)w2, ldw, b2, (__bf16*)act2, sA2, (__bf16*)pooled, sP, d);
+  return hipGetLastError();
+}
+
+int cnn_wgrad_groups(int mcv, const CnnDims& d) { return std::min(CNN_WGRAD_GROUPS, mcv * (d.H / IB)); }
+
+hipError_t cnn_conv2_wgrad_implicit_run(const void* d2t, int64_t ld, const void* act1, int64_t sA1, int mcv,
+                                        const CnnDims& d, int J, float* part, float* g, int64_t D, int64_t off,
+                                        int beta, hipStream_t s) {
+  if (!cnn_implicit_supported(d, 1) || mcv < 1 || J < 1 || J > 65535) return hipErrorInvalidValue;
+  if (((uintptr_t)d2t | (uintptr_t)act1) & 15 || ld % 8 || sA1 % 8) return hipErrorInvalidValue;
+  const int G = cnn_wgrad_groups(mcv, d);
+  hipLaunchKernelGGL(conv2_wgrad_implicit_kernel, dim3(G, J), dim3(256), 0, s, (const __bf16*)d2t, ld,
+                     (const __bf16*)act1, sA1, mcv, d, G, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(conv2_wgrad_sum_kernel, dim3(nb(32 * WG_COLS, 256), J), dim3(256), 0, s, part, G, g, D, off,
+                     beta);
   return hipGetLastError();
 }
 

@@ -114,6 +114,13 @@ bool cnn_implicit_supported(const CnnDims& d, int bf16);
 hipError_t cnn_conv2_fwd_implicit_run(const void* act1, int64_t sA1, const void* w2, int64_t ldw, const float* b2,
                                       void* act2, int64_t sA2, void* pooled, int64_t sP, int mcv, const CnnDims& d,
                                       int J, hipStream_t s);
+// the [W2 | b2] gradient as an implicit GEMM over the chunk's pixels: FP32 partials part [J][G][4][32 x 145]
+// (G = cnn_wgrad_groups, at most CNN_WGRAD_GROUPS) summed in a fixed order into g[j][off ..] (beta: accumulate)
+constexpr int CNN_WGRAD_GROUPS = 16;
+int cnn_wgrad_groups(int mcv, const CnnDims& d);
+hipError_t cnn_conv2_wgrad_implicit_run(const void* d2t, int64_t ld, const void* act1, int64_t sA1, int mcv,
+                                        const CnnDims& d, int J, float* part, float* g, int64_t D, int64_t off,
+                                        int beta, hipStream_t s);
 hipError_t cnn_conv2_dgrad_implicit_run(const void* d2, int64_t sA2, const void* wT, int64_t ldwT, const void* act1,
                                         int64_t sA1, void* d1t, int64_t ld, int mcv, const CnnDims& d, int J,
                                         hipStream_t s);

@@ -159,6 +159,8 @@ struct CnnBufs {
   void *d2 = nullptr, *d2t = nullptr;           // [J][RP][C2], [J][C2][RP]
   void* d1t = nullptr;                          // [J*C1][RP]
   float* dw1part = nullptr;                     // [kslices][J*C1][K1+1] split-K partials of the conv1 gradient
+  float* dw2part = nullptr;                     // [J][groups][4][C2 x (K2+1)] partials of the implicit conv2 gradient
+  int implicit = 0;                             // conv2 runs as implicit GEMMs (no patch matrices)
   int kslices = 1;                              // their capacity
   float* logits = nullptr;                      // [J][mc][ncls]
   void* wT[3] = {nullptr, nullptr, nullptr};    // transposed copies of layers 1, 2: [J][nin][ldwT]
@@ -465,7 +467,8 @@ int64_t choose_chunk(smc_t h) {
     // images per chunk from the bytes one image occupies across all particles
     const CnnDims& d = h->cb.d;
     const int64_t J = h->J, e = (int64_t)h->esz;
-    const int64_t per_image = J * d.HW * (int64_t)(2 * d.C1 + (d.K2 + 1) + 3 * d.C2) * e +
+    const int64_t patches = cnn_implicit_supported(d, h->bf16) ? 0 : d.K2 + 1;  // explicit conv2 only
+    const int64_t per_image = J * d.HW * (int64_t)(2 * d.C1 + patches + 3 * d.C2) * e +
                               J * (int64_t)(2 * d.F3 + 16) * e + J * d.ncls * 4 +
                               (int64_t)d.HW * (d.K1p + d.K1 + 1) * e;
     int64_t mc = std::max<int64_t>(1, budget / per_image);
@@ -500,7 +503,11 @@ void alloc_cnn(smc_t h) {
   b.p1 = dalloc<char>(h->owned, b.RP * d.K1p * e);
   b.p1t = dalloc<char>(h->owned, b.RP * (d.K1 + 1) * e);
   b.act1 = dalloc<char>(h->owned, J * b.s_act1 * e);
-  b.big = dalloc<char>(h->owned, J * b.s_big * e);
+  b.implicit = cnn_implicit_supported(d, h->bf16) ? 1 : 0;
+  if (b.implicit)
+    b.dw2part = dalloc<float>(h->owned, J * CNN_WGRAD_GROUPS * 4 * d.C2 * (int64_t)(d.K2 + 1));
+  else
+    b.big = dalloc<char>(h->owned, J * b.s_big * e);
   b.act2 = dalloc<char>(h->owned, J * b.s_act2 * e);
   b.pooled = dalloc<char>(h->owned, J * b.s_pool * e);
   b.d3 = dalloc<char>(h->owned, J * mc * 16 * e);
@@ -835,7 +842,7 @@ void cnn_forward_chunk(smc_t h, const void* Xop, int64_t c0, int mcv) {
     p.out0.rstr = d.C1;
     gemm(h, p, SMC_K_GEMM_FWD1, 2.0 * R * J * d.C1 * d.K1);
   }
-  if (cnn_implicit_supported(d, bf)) {
+  if (b.implicit) {
     // conv2 as an implicit GEMM over the activation halo, with the 2x2 pooling in its epilogue
     timed(h, SMC_K_GEMM_FWD1, 2.0 * R * J * d.C2 * d.K2, 0.0, [&]() {
       HIPCHECK(cnn_conv2_fwd_implicit_run(b.act1, b.s_act1, h->net.w[1], h->net.ldw[1], h->net.bias[1], b.act2,
@@ -973,6 +980,13 @@ void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const doubl
     timed(h, SMC_K_OTHER, 0.0, (double)J * R * d.C2 * h->esz * 3.25, [&]() {
       HIPCHECK(cnn_unpool_run(b.dpool, b.s_pool, b.act2, b.s_act2, mcv, d, J, b.RP, b.d2, b.d2t, bf, h->stream));
     });
+    if (b.implicit) {
+      // conv2 weight gradient [W2 | b2] as an implicit GEMM over the chunk's pixels
+      timed(h, SMC_K_GEMM_DW1, 2.0 * R * J * d.C2 * (d.K2 + 1), 0.0, [&]() {
+        HIPCHECK(cnn_conv2_wgrad_implicit_run(b.d2t, b.RP, b.act1, b.s_act1, mcv, d, J, b.dw2part, g_out, h->D,
+                                              h->net.off[1], beta, h->stream));
+      });
+    } else {
     timed(h, SMC_K_OTHER, 0.0, (double)J * R * (d.K2 + 1) * h->esz, [&]() {
       HIPCHECK(cnn_im2col_at_run(b.act1, b.s_act1, mcv, d, J, b.RP, b.big, b.s_big, bf, h->stream));
     });
@@ -996,7 +1010,8 @@ void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const doubl
       p.out0.rstr = d.K2 + 1;
       gemm(h, p, SMC_K_GEMM_DW1, 2.0 * R * J * d.C2 * (d.K2 + 1));
     }
-    if (cnn_implicit_supported(d, bf)) {
+    }
+    if (b.implicit) {
       // the error at the conv1 output as an implicit GEMM over the d2 halo (transposed conv2)
       timed(h, SMC_K_GEMM_OTHER, 2.0 * R * J * d.C2 * d.K2, 0.0, [&]() {
         HIPCHECK(cnn_conv2_dgrad_implicit_run(b.d2, b.s_act2, b.wT[1], b.ldwT[1], b.act1, b.s_act1, b.d1t, b.RP, mcv,
