@@ -336,6 +336,22 @@ constexpr int IB = 8;            // output rows per workgroup
 constexpr int IHR = IB + 2;      // halo rows
 constexpr int IHC = 32 + 2;      // halo columns
 
+// Eight channels (8c .. 8c+7) of the conv2 output error at pixel (y, x) of image n, from the
+// pooled-feature error and the ReLU mask: 1{act2 > 0} dpool / 4 (the adjoint of the 2x2 average,
+// rounded as unpool_kernel rounds it)
+__device__ __forceinline__ u32x4 d2_chunk(const __bf16* __restrict__ act2n, const __bf16* __restrict__ dpooln,
+                                          const CnnDims& d, int y, int x, int c) {
+  const u32x4 av = *(const u32x4*)(act2n + (y * 32 + x) * 32 + c * 8);
+  const u32x4 pv = *(const u32x4*)(dpooln + ((y >> 1) * d.Wp + (x >> 1)) * 32 + c * 8);
+  const __bf16* a = (const __bf16*)&av;
+  const __bf16* pp = (const __bf16*)&pv;
+  u32x4 ov;
+  __bf16* o = (__bf16*)&ov;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) o[t] = to_bf16(from_bf16(a[t]) > 0.0f ? 0.25f * from_bf16(pp[t]) : 0.0f);
+  return ov;
+}
+
 // act2 = ReLU(conv2(act1) + b2) and pooled = its 2x2 average, for one particle, image and band.
 // Wave w computes rows 2w, 2w+1 of the band (one 32x32 MFMA block each: 32 pixels x 32 output
 // channels); K runs over the nine taps, one v_mfma_f32_32x32x16_bf16 per tap (16 channels), in
@@ -406,12 +422,14 @@ __global__ __launch_bounds__(256) void conv2_fwd_implicit_kernel(const __bf16* _
 }
 
 // d1t[j C1 + c][r] = 1{act1[r][c] > 0} sum over taps t and channels c2 of d2[r - off(t)][c2] W2[c2][t C1 + c]
-// (the error at the conv1 output; off(t) = (ky - 1, kx - 1)) for one particle, image and band.
+// (the error at the conv1 output; off(t) = (ky - 1, kx - 1)) for one particle, image and band;
+// the conv2 output error d2 is formed in the halo from act2 and the pooled-feature error.
 // Wave w computes band rows 2w, 2w+1 as four 16-pixel blocks; per block one
 // v_mfma_f32_16x16x32_bf16 per tap (K = the 32 channels of d2), B from the transposed weight
 // copy wT[j][t C1 + c][c2].  Lane l ends with four consecutive pixels of channel l % 16 and
 // writes them as one 8-byte vector.
-__global__ __launch_bounds__(256) void conv2_dgrad_implicit_kernel(const __bf16* __restrict__ d2, int64_t sA2,
+__global__ __launch_bounds__(256) void conv2_dgrad_implicit_kernel(const __bf16* __restrict__ act2, int64_t sA2,
+                                                                   const __bf16* __restrict__ dpool, int64_t sP,
                                                                    const __bf16* __restrict__ wT, int64_t ldwT,
                                                                    const __bf16* __restrict__ act1, int64_t sA1,
                                                                    __bf16* __restrict__ d1t, int64_t ld, CnnDims d) {
@@ -419,12 +437,13 @@ __global__ __launch_bounds__(256) void conv2_dgrad_implicit_kernel(const __bf16*
   __shared__ __attribute__((aligned(16))) __bf16 a1s[IB * 32 * 16];
   const int j = blockIdx.z, n = blockIdx.y, y0 = blockIdx.x * IB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const __bf16* e2 = d2 + (int64_t)j * sA2 + (int64_t)n * d.HW * 32;
+  const __bf16* a2n = act2 + (int64_t)j * sA2 + (int64_t)n * d.HW * 32;
+  const __bf16* dpn = dpool + (int64_t)j * sP + (int64_t)n * d.F3;
   for (int e = tid; e < IHR * IHC * 4; e += 256) {
     const int row = e / (IHC * 4), rem = e - row * (IHC * 4), col = rem >> 2, c = rem & 3;
     const int yy = y0 - 1 + row, xx = col - 1;
     u32x4 v = {0u, 0u, 0u, 0u};
-    if (yy >= 0 && yy < d.H && xx >= 0 && xx < 32) v = *(const u32x4*)(e2 + (yy * 32 + xx) * 32 + c * 8);
+    if (yy >= 0 && yy < d.H && xx >= 0 && xx < 32) v = d2_chunk(a2n, dpn, d, yy, xx, c);
     *(u32x4*)(halo + (row * IHC + col) * 64 + ((c ^ ((col >> 2) & 3)) << 4)) = v;
   }
   const __bf16* a1 = act1 + (int64_t)j * sA1 + ((int64_t)n * d.HW + y0 * 32) * 16;
@@ -470,10 +489,13 @@ __global__ __launch_bounds__(256) void conv2_dgrad_implicit_kernel(const __bf16*
 // steps 4w .. 4w + 3 of each band, and each wave writes its own FP32 partial
 // part[j][g][w][32][145], summed in a fixed order by conv2_wgrad_sum_kernel.
 constexpr int WG_COLS = 145;
-__global__ __launch_bounds__(256) void conv2_wgrad_implicit_kernel(const __bf16* __restrict__ d2t, int64_t ld,
+constexpr int D2S = IB * 32 + 8;  // row stride of the band's channel-major error copy
+__global__ __launch_bounds__(256) void conv2_wgrad_implicit_kernel(const __bf16* __restrict__ act2, int64_t sA2,
+                                                                   const __bf16* __restrict__ dpool, int64_t sP,
                                                                    const __bf16* __restrict__ act1, int64_t sA1,
                                                                    int mcv, CnnDims d, int G, float* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) __bf16 a1T[3][16][IHR][32];
+  __shared__ __attribute__((aligned(16))) __bf16 d2s[32][D2S];
   const int g = blockIdx.x, j = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int bands = mcv * (d.H / IB);
@@ -510,13 +532,24 @@ __global__ __launch_bounds__(256) void conv2_wgrad_implicit_kernel(const __bf16*
         }
       }
     }
+    {
+      // the band's conv2 output error, channel-major: d2s[c2][band pixel]
+      const __bf16* a2n = act2 + (int64_t)j * sA2 + (int64_t)n * d.HW * 32;
+      const __bf16* dpn = dpool + (int64_t)j * sP + (int64_t)n * d.F3;
+      for (int e = tid; e < IB * 32 * 4; e += 256) {
+        const int p = e >> 2, c = e & 3;
+        const u32x4 v = d2_chunk(a2n, dpn, d, y0 + (p >> 5), p & 31, c);
+        const __bf16* vv = (const __bf16*)&v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) d2s[c * 8 + i][p] = vv[i];
+      }
+    }
     __syncthreads();
-    const int64_t rb = (int64_t)n * d.HW + y0 * 32;  // first pixel of the band
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int ks = 4 * w + s;                      // 16-pixel step of the band
       const int r = ks >> 1, x0 = (ks & 1) * 16 + 8 * (lane >> 5);
-      const u32x4 av = *(const u32x4*)(d2t + ((int64_t)j * 32 + (lane & 31)) * ld + rb + r * 32 + x0);
+      const u32x4 av = *(const u32x4*)&d2s[lane & 31][r * 32 + x0];
 #pragma unroll
       for (int b = 0; b < 5; ++b) {
         const int col = b * 32 + (lane & 31);
@@ -583,14 +616,15 @@ hipError_t cnn_conv2_fwd_implicit_run(const void* act1, int64_t sA1, const void*
 
 int cnn_wgrad_groups(int mcv, const CnnDims& d) { return std::min(CNN_WGRAD_GROUPS, mcv * (d.H / IB)); }
 
-hipError_t cnn_conv2_wgrad_implicit_run(const void* d2t, int64_t ld, const void* act1, int64_t sA1, int mcv,
-                                        const CnnDims& d, int J, float* part, float* g, int64_t D, int64_t off,
-                                        int beta, hipStream_t s) {
+hipError_t cnn_conv2_wgrad_implicit_run(const void* act2, int64_t sA2, const void* dpool, int64_t sP,
+                                        const void* act1, int64_t sA1, int mcv, const CnnDims& d, int J, float* part,
+                                        float* g, int64_t D, int64_t off, int beta, hipStream_t s) {
   if (!cnn_implicit_supported(d, 1) || mcv < 1 || J < 1 || J > 65535) return hipErrorInvalidValue;
-  if (((uintptr_t)d2t | (uintptr_t)act1) & 15 || ld % 8 || sA1 % 8) return hipErrorInvalidValue;
+  if (((uintptr_t)act2 | (uintptr_t)dpool | (uintptr_t)act1) & 15 || sA2 % 8 || sP % 8 || sA1 % 8 || d.F3 % 8)
+    return hipErrorInvalidValue;
   const int G = cnn_wgrad_groups(mcv, d);
-  hipLaunchKernelGGL(conv2_wgrad_implicit_kernel, dim3(G, J), dim3(256), 0, s, (const __bf16*)d2t, ld,
-                     (const __bf16*)act1, sA1, mcv, d, G, part);
+  hipLaunchKernelGGL(conv2_wgrad_implicit_kernel, dim3(G, J), dim3(256), 0, s, (const __bf16*)act2, sA2,
+                     (const __bf16*)dpool, sP, (const __bf16*)act1, sA1, mcv, d, G, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(conv2_wgrad_sum_kernel, dim3(nb(32 * WG_COLS, 256), J), dim3(256), 0, s, part, G, g, D, off,
@@ -598,15 +632,15 @@ hipError_t cnn_conv2_wgrad_implicit_run(const void* d2t, int64_t ld, const void*
   return hipGetLastError();
 }
 
-hipError_t cnn_conv2_dgrad_implicit_run(const void* d2, int64_t sA2, const void* wT, int64_t ldwT, const void* act1,
-                                        int64_t sA1, void* d1t, int64_t ld, int mcv, const CnnDims& d, int J,
-                                        hipStream_t s) {
+hipError_t cnn_conv2_dgrad_implicit_run(const void* act2, int64_t sA2, const void* dpool, int64_t sP, const void* wT,
+                                        int64_t ldwT, const void* act1, int64_t sA1, void* d1t, int64_t ld, int mcv,
+                                        const CnnDims& d, int J, hipStream_t s) {
   if (!cnn_implicit_supported(d, 1) || mcv < 1 || mcv > 65535 || J < 1 || J > 65535) return hipErrorInvalidValue;
-  if (((uintptr_t)d2 | (uintptr_t)wT | (uintptr_t)act1 | (uintptr_t)d1t) & 15 || ldwT % 8 || sA2 % 8 || sA1 % 8 ||
-      ld % 4)
+  if (((uintptr_t)act2 | (uintptr_t)dpool | (uintptr_t)wT | (uintptr_t)act1 | (uintptr_t)d1t) & 15 || ldwT % 8 ||
+      sA2 % 8 || sP % 8 || sA1 % 8 || d.F3 % 8 || ld % 4)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(conv2_dgrad_implicit_kernel, dim3(d.H / IB, mcv, J), dim3(256), 0, s, (const __bf16*)d2, sA2,
-                     (const __bf16*)wT, ldwT, (const __bf16*)act1, sA1, (__bf16*)d1t, ld, d);
+  hipLaunchKernelGGL(conv2_dgrad_implicit_kernel, dim3(d.H / IB, mcv, J), dim3(256), 0, s, (const __bf16*)act2, sA2,
+                     (const __bf16*)dpool, sP, (const __bf16*)wT, ldwT, (const __bf16*)act1, sA1, (__bf16*)d1t, ld, d);
   return hipGetLastError();
 }
 

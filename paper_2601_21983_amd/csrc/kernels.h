@@ -108,8 +108,9 @@ hipError_t cnn_unpool_run(const void* dpool, int64_t sP, const void* act2, int64
                           int J, int64_t ld, void* d2, void* d2t, int bf16, hipStream_t s);
 // implicit-GEMM conv2 for BF16 networks on 32-pixel-wide images with C1 = 16, C2 = 32 (no patch
 // matrices): the forward writes act2 [j][r][C2] and the 2x2-pooled features [j][n][F3]; the
-// input error writes d1t [j C1 + c][ld] masked by 1{act1 > 0}, from d2 [j][r][C2] and the
-// transposed weight copy
+// backward kernels form the conv2 output error from act2 and the pooled-feature error dpool
+// [j][n][F3] themselves; the input error writes d1t [j C1 + c][ld] masked by 1{act1 > 0}, using
+// the transposed weight copy
 bool cnn_implicit_supported(const CnnDims& d, int bf16);
 hipError_t cnn_conv2_fwd_implicit_run(const void* act1, int64_t sA1, const void* w2, int64_t ldw, const float* b2,
                                       void* act2, int64_t sA2, void* pooled, int64_t sP, int mcv, const CnnDims& d,
@@ -118,12 +119,12 @@ hipError_t cnn_conv2_fwd_implicit_run(const void* act1, int64_t sA1, const void*
 // (G = cnn_wgrad_groups, at most CNN_WGRAD_GROUPS) summed in a fixed order into g[j][off ..] (beta: accumulate)
 constexpr int CNN_WGRAD_GROUPS = 16;
 int cnn_wgrad_groups(int mcv, const CnnDims& d);
-hipError_t cnn_conv2_wgrad_implicit_run(const void* d2t, int64_t ld, const void* act1, int64_t sA1, int mcv,
-                                        const CnnDims& d, int J, float* part, float* g, int64_t D, int64_t off,
-                                        int beta, hipStream_t s);
-hipError_t cnn_conv2_dgrad_implicit_run(const void* d2, int64_t sA2, const void* wT, int64_t ldwT, const void* act1,
-                                        int64_t sA1, void* d1t, int64_t ld, int mcv, const CnnDims& d, int J,
-                                        hipStream_t s);
+hipError_t cnn_conv2_wgrad_implicit_run(const void* act2, int64_t sA2, const void* dpool, int64_t sP,
+                                        const void* act1, int64_t sA1, int mcv, const CnnDims& d, int J, float* part,
+                                        float* g, int64_t D, int64_t off, int beta, hipStream_t s);
+hipError_t cnn_conv2_dgrad_implicit_run(const void* act2, int64_t sA2, const void* dpool, int64_t sP, const void* wT,
+                                        int64_t ldwT, const void* act1, int64_t sA1, void* d1t, int64_t ld, int mcv,
+                                        const CnnDims& d, int J, hipStream_t s);
 hipError_t cnn_col2im_run(const void* dp2, int64_t sB, const void* act1, int64_t sA, int mcv, const CnnDims& d, int J,
                           int64_t ld, void* d1t, int bf16, hipStream_t s);
 

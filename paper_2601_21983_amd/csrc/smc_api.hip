@@ -467,8 +467,10 @@ int64_t choose_chunk(smc_t h) {
     // images per chunk from the bytes one image occupies across all particles
     const CnnDims& d = h->cb.d;
     const int64_t J = h->J, e = (int64_t)h->esz;
-    const int64_t patches = cnn_implicit_supported(d, h->bf16) ? 0 : d.K2 + 1;  // explicit conv2 only
-    const int64_t per_image = J * d.HW * (int64_t)(2 * d.C1 + patches + 3 * d.C2) * e +
+    // explicit conv2 only: the patch matrix and the conv2 output error in both layouts
+    const bool impl = cnn_implicit_supported(d, h->bf16);
+    const int64_t patches = impl ? 0 : d.K2 + 1, c2bufs = impl ? 1 : 3;
+    const int64_t per_image = J * d.HW * (int64_t)(2 * d.C1 + patches + c2bufs * d.C2) * e +
                               J * (int64_t)(2 * d.F3 + 16) * e + J * d.ncls * 4 +
                               (int64_t)d.HW * (d.K1p + d.K1 + 1) * e;
     int64_t mc = std::max<int64_t>(1, budget / per_image);
@@ -512,8 +514,10 @@ void alloc_cnn(smc_t h) {
   b.pooled = dalloc<char>(h->owned, J * b.s_pool * e);
   b.d3 = dalloc<char>(h->owned, J * mc * 16 * e);
   b.dpool = dalloc<char>(h->owned, J * b.s_pool * e);
-  b.d2 = dalloc<char>(h->owned, J * b.s_act2 * e);
-  b.d2t = dalloc<char>(h->owned, J * b.s_act2 * e);
+  if (!b.implicit) {
+    b.d2 = dalloc<char>(h->owned, J * b.s_act2 * e);
+    b.d2t = dalloc<char>(h->owned, J * b.s_act2 * e);
+  }
   b.d1t = dalloc<char>(h->owned, J * b.s_act1 * e);
   b.logits = dalloc<float>(h->owned, J * mc * d.ncls);
   // the conv1 weight gradient is one GEMM with J*C1 output rows over all pixels of the chunk:
@@ -977,14 +981,15 @@ void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const doubl
       p.out0.rstr = d.F3;
       gemm(h, p, SMC_K_GEMM_OTHER, 2.0 * mcv * J * d.ncls * d.F3);
     }
-    timed(h, SMC_K_OTHER, 0.0, (double)J * R * d.C2 * h->esz * 3.25, [&]() {
-      HIPCHECK(cnn_unpool_run(b.dpool, b.s_pool, b.act2, b.s_act2, mcv, d, J, b.RP, b.d2, b.d2t, bf, h->stream));
-    });
+    if (!b.implicit)  // the implicit kernels form the conv2 output error from act2 and dpool themselves
+      timed(h, SMC_K_OTHER, 0.0, (double)J * R * d.C2 * h->esz * 3.25, [&]() {
+        HIPCHECK(cnn_unpool_run(b.dpool, b.s_pool, b.act2, b.s_act2, mcv, d, J, b.RP, b.d2, b.d2t, bf, h->stream));
+      });
     if (b.implicit) {
       // conv2 weight gradient [W2 | b2] as an implicit GEMM over the chunk's pixels
       timed(h, SMC_K_GEMM_DW1, 2.0 * R * J * d.C2 * (d.K2 + 1), 0.0, [&]() {
-        HIPCHECK(cnn_conv2_wgrad_implicit_run(b.d2t, b.RP, b.act1, b.s_act1, mcv, d, J, b.dw2part, g_out, h->D,
-                                              h->net.off[1], beta, h->stream));
+        HIPCHECK(cnn_conv2_wgrad_implicit_run(b.act2, b.s_act2, b.dpool, b.s_pool, b.act1, b.s_act1, mcv, d, J,
+                                              b.dw2part, g_out, h->D, h->net.off[1], beta, h->stream));
       });
     } else {
     timed(h, SMC_K_OTHER, 0.0, (double)J * R * (d.K2 + 1) * h->esz, [&]() {
@@ -1014,8 +1019,8 @@ void cnn_pass(smc_t h, const float* theta, int64_t m, double lambda, const doubl
     if (b.implicit) {
       // the error at the conv1 output as an implicit GEMM over the d2 halo (transposed conv2)
       timed(h, SMC_K_GEMM_OTHER, 2.0 * R * J * d.C2 * d.K2, 0.0, [&]() {
-        HIPCHECK(cnn_conv2_dgrad_implicit_run(b.d2, b.s_act2, b.wT[1], b.ldwT[1], b.act1, b.s_act1, b.d1t, b.RP, mcv,
-                                              d, J, h->stream));
+        HIPCHECK(cnn_conv2_dgrad_implicit_run(b.act2, b.s_act2, b.dpool, b.s_pool, b.wT[1], b.ldwT[1], b.act1,
+                                              b.s_act1, b.d1t, b.RP, mcv, d, J, h->stream));
       });
     } else {
     {
