@@ -63,8 +63,9 @@ def parse():
     ap.add_argument("--legs", default="bf16x3-learned,fp32,bf16x3,bf16",
                     help="comma list of precision[-learned]; the first is the headline")
     ap.add_argument("--no-cnn", action="store_true", help="skip the convolutional-network workload")
-    ap.add_argument("--cnn-steps", type=int, default=8)
+    ap.add_argument("--cnn-steps", type=int, default=30)
     ap.add_argument("--cnn-precision", default="bf16", help="operand precision of the convolutional workload")
+    ap.add_argument("--cnn-tol", type=float, default=CNN_TOL, help="relative posterior-mean change that appends kappa")
     ap.add_argument("--no-sda", action="store_true", help="skip the smooth-data-annealing run")
     ap.add_argument("--no-deep", action="store_true", help="skip the 784-256-256-10, J = 1024 workload")
     ap.add_argument("--no-lenet", action="store_true", help="skip the LeNet-5 gradient-pass measurement")
@@ -291,13 +292,19 @@ def roofline(prof, prec, m_mean=None):
 
 
 CNN_DIMS = [32, 32, 3, 16, 32, 10]
-CNN_J, CNN_N, CNN_NTEST, CNN_KAPPA, CNN_TOL = 128, 50000, 2000, 1000, 1e-2
+CNN_J, CNN_N, CNN_NTEST, CNN_KAPPA = 128, 50000, 2000, 1000
+# growth tolerance: above the criterion's noise floor.  With one particle carrying the weight the
+# weighted mean moves by the Langevin noise alone, h sqrt(D) / (sigma_p sqrt(D)) = h / sigma_p = 4%
+# per iteration, so a tolerance below that never appends
+CNN_TOL = 5e-2
+CNN_EVAL_EVERY = 5
 CNN_PRIOR = 0.05  # prior sd of every CNN weight: with sd 1 the 8192-input linear layer gives logits ~1e4
 
 
-def run_cnn(P, steps, seed, precision="bf16"):
+def run_cnn(P, steps, seed, precision="bf16", tol=None):
     """CIFAR-shaped workload: conv3x3(16) -> conv3x3(32) -> avgpool -> linear(10), J = 128, BF16,
-    subset grown by kappa = 1000 when the posterior mean's relative change is below 1e-2."""
+    subset grown by kappa = 1000 when the posterior mean's relative change is below tol (5e-2);
+    test accuracy every CNN_EVAL_EVERY iterations, its evaluation time left out of the timing."""
     import torch
     import smc_inputs
     from paper_2601_21983_amd.schedules import PosteriorMeanSchedule
@@ -315,13 +322,15 @@ def run_cnn(P, steps, seed, precision="bf16"):
                       prior_std=CNN_PRIOR, seed=seed)
     s = P.SMCSampler(cfg, Xd, yd, m0=CNN_KAPPA, lambda0=CNN_N / CNN_KAPPA)
     s.resample()
-    sched = PosteriorMeanSchedule(CNN_KAPPA, CNN_KAPPA, CNN_TOL, CNN_N)
+    tol = CNN_TOL if tol is None else tol
+    sched = PosteriorMeanSchedule(CNN_KAPPA, CNN_KAPPA, tol, CNN_N)
     sched.start(s)
     s.profile(True)
     s.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     m, evals, sizes, ess = CNN_KAPPA, 0, [], []
+    trace, t_eval = [], 0.0
     for k in range(1, steps + 1):
         info = s.step(m, CNN_N / m)
         evals += info["grad_evals"]
@@ -329,17 +338,28 @@ def run_cnn(P, steps, seed, precision="bf16"):
         s.resample()
         sizes.append(m)
         m = sched.next(s)
+        if k % CNN_EVAL_EVERY == 0:
+            # test accuracy every few iterations; the evaluation's own time is left out
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            r = s.predict(Xtd, ytd)
+            torch.cuda.synchronize()
+            trace.append({"iteration": k, "seconds": round(te - t0 - t_eval, 3), "subset": sizes[-1],
+                          "accuracy": round(r["accuracy"], 4), "mean_log_pred": round(r["mean_log_pred"], 5)})
+            t_eval += time.perf_counter() - te
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt = time.perf_counter() - t0 - t_eval
     prof = s.profile_read()
     r = s.predict(Xtd, ytd)
     s.close()
     return {"value": round(evals / dt, 1), "unit": "grad-evals/s", "ms_per_step": round(1e3 * dt / steps, 3),
             "steps": steps, "subset_sizes": sizes, "mean_ess": round(float(np.mean(ess)), 2),
             "test_accuracy": round(r["accuracy"], 4), "test_mean_log_pred": round(r["mean_log_pred"], 5),
+            "accuracy_trace": trace,
+            "seconds_to_90pct": next((e["seconds"] for e in trace if e["accuracy"] >= 0.9), None),
             "config": {"workload": "CIFAR-shaped synthetic textures 50000/2000 (32x32x3), CNN conv3x3(16)-"
                                    f"conv3x3(32)-avgpool2-FC10 ReLU, J=128, {precision} operands, prior N(0, 0.05^2), "
-                                   "Langevin h=0.002, subset grown by 1000 when the posterior mean changes by < 1e-2",
+                                   f"Langevin h=0.002, subset grown by 1000 when the posterior mean changes by < {tol:g}",
                        "particles": CNN_J, "precision": precision},
             "roofline": roofline(prof, precision), "kernels": kernel_table(prof, precision),
             "host_seconds_incl_schedule": round(dt, 3)}
@@ -728,7 +748,7 @@ def main():
 
     cnn = None
     if not args.no_cnn:
-        cnn = run_cnn(P, max(1, args.cnn_steps), args.seed, args.cnn_precision)
+        cnn = run_cnn(P, max(1, args.cnn_steps), args.seed, args.cnn_precision, args.cnn_tol)
         log(f"cnn: {json.dumps(cnn)}")
 
     deep = None

@@ -176,6 +176,9 @@ struct smc_handle {
   std::vector<void*> owned;
   int J = 0, L = 0, F = 0, C = 0, bf16 = 0, split = 0, cnn = 0;
   int fused = 0;  // one hidden layer, BF16 operands: layer 1 and the output layer in one kernel
+  // the current pass's log-likelihood enters no weight (it only supplies a gradient): split-BF16
+  // networks run its forward on the hi operands alone
+  bool grad_only = false;
   CnnBufs cb;
   // LeNet-5: a convolution stack (lenet.hip) whose F features feed the dense layers in place
   // of X; per chunk lfeat [J][mc][F], lfeatT [J][(F+1)][mc] (ones row F), ldfeat [J][mc][F]
@@ -1116,9 +1119,17 @@ void fused_chunk(smc_t h, const void* Xop, int64_t c0, int mcv, int mode, HeadAr
   a.nsplit = (rows + 255) / 256;
   const double H = h->net.nout[0], flops = 2.0 * mcv * (double)h->J * H * h->F +
                                            (mode == HEAD_TRAIN ? 6.0 : 2.0) * a.C * H * h->J * mcv;
+  const int split = h->split && !h->grad_only;  // the weight copy keeps its [w_hi | w_lo] rows either way
   timed(h, SMC_K_GEMM_FWD1, flops, 0.0,
-        [&]() { HIPCHECK(fwd_head_run(p, a, mode, h->split, h->cfg.activation, h->stream)); });
+        [&]() { HIPCHECK(fwd_head_run(p, a, mode, split, h->cfg.activation, h->stream)); });
 }
+
+// Marks the passes of its scope as gradient-only (see smc_handle::grad_only).
+struct GradOnlyScope {
+  smc_t h;
+  GradOnlyScope(smc_t h_, bool on) : h(h_) { h->grad_only = on; }
+  ~GradOnlyScope() { h->grad_only = false; }
+};
 
 // One pass over the subset [0, m): log-likelihoods ll_out[j] (FP64) and, when
 // g_out is given, g_out[j] = scale_j * d LL_j / d theta_j (the lambda-scaled
@@ -1597,6 +1608,10 @@ void step_impl(smc_t h, int64_t m_k, int64_t split, double lambda_k, double lamb
       h->lam = lambda_k;
       h->seg_split = split;
       h->lam_b = lambda_b;
+      // with the fixed-step move only the gradient of this pass is used: the weight's denominator
+      // is the cached log pi_{k-1}(theta_{k-1}), its numerator comes from the move's last pass
+      // (the learned move's features read this pass's log-likelihood)
+      GradOnlyScope go(h, h->cfg.proposal == SMC_PROPOSAL_FIXED);
       grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g, target_seg(h));
     }
     h->rng_iter += 1;
@@ -1644,7 +1659,10 @@ void step_impl(smc_t h, int64_t m_k, int64_t split, double lambda_k, double lamb
           [&]() { HIPCHECK(move_run(ma, h->stream)); });
     h->noise_pending = false;
     for (int s = 1; s <= S; ++s) {
-      grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g, target_seg(h));
+      {
+        GradOnlyScope go(h, s < S);  // intermediate leapfrog positions: gradient only
+        grad_pass(h, h->theta, m_k, lambda_k, nullptr, h->ll, h->g, target_seg(h));
+      }
       MoveArgs mb = move_args(h, s < S ? MOVE_MID : MOVE_LAST);
       // MID: read theta, g, P; write P, theta, copy.  LAST: read P, g, theta
       timed(h, SMC_K_MOVE, 0.0, nd * (s < S ? 20.0 + h->esz : 12.0), [&]() { HIPCHECK(move_run(mb, h->stream)); });
