@@ -94,10 +94,10 @@ def source_digest(files):
     return h.hexdigest()
 
 
-def measured_traffic(kernel, m_mean):
-    """HBM bytes per launch of `kernel` at a mean of m_mean samples per launch (padded to 256),
-    from the committed PMC fit (fetch and write, each a + b*M), if the fit was taken on the
-    current sources of that kernel; else None."""
+def measured_traffic(kernel, launches):
+    """Mean HBM bytes per launch of `kernel` over `launches` [(mode, M)] (M the launch's samples
+    padded to 256, mode "split" or "plain"), from the committed PMC fits (fetch and write, each
+    a + b*M per mode), if they were taken on the current sources of that kernel; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -108,11 +108,14 @@ def measured_traffic(kernel, m_mean):
             return None
     except (OSError, KeyError):
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    if k is None or "fetch_bytes" not in k:
+    fits = rec.get("kernels", {}).get(kernel, {}).get("fits")
+    if not fits or not launches or any(mode not in fits for mode, _ in launches):
         return None
-    (fa, fb), (wa, wb) = k["fetch_bytes"], k["write_bytes"]
-    return round(fa + fb * m_mean + wa + wb * m_mean)
+    tot = 0.0
+    for mode, m in launches:
+        (fa, fb), (wa, wb) = fits[mode]["fetch_bytes"], fits[mode]["write_bytes"]
+        tot += fa + fb * m + wa + wb * m
+    return round(tot / len(launches))
 
 
 N_VAL = 2000  # held-out samples of the proposal judge (a third seed, disjoint from train and test)
@@ -132,11 +135,17 @@ def passes(sizes, k):
     return 1 + (1 if sizes[k] != sizes[k - 1] else 0)
 
 
-def pass_mean_m(sizes, steps):
-    """Mean samples per gradient pass over iterations 1..steps, each padded to the fused kernel's
-    256-sample tiles (the unit of the traffic fit)."""
-    tot = sum(passes(sizes, k) * ((sizes[k] + 255) // 256 * 256) for k in range(1, steps + 1))
-    return tot / sum(passes(sizes, k) for k in range(1, steps + 1))
+def fused_launches(sizes, steps, learned_through):
+    """(mode, M padded to 256) of every fused-kernel launch in iterations 1..steps: the move's last
+    pass runs split BF16; the gradient-only pass of an iteration whose subset grew runs the plain
+    forward while the fixed-step move runs (iterations after learned_through), split before."""
+    out = []
+    for k in range(1, steps + 1):
+        mp = (sizes[k] + 255) // 256 * 256
+        if sizes[k] != sizes[k - 1]:
+            out.append(("split" if k <= learned_through else "plain", mp))
+        out.append(("split", mp))
+    return out
 
 
 def leg_parts(leg):
@@ -178,15 +187,21 @@ def train_proposal(P, dev, sizes, seeds=(11, 12), every=2, steps=600):
     return params, ref, info
 
 
-def drive(s, leg, sizes, steps, judge=None, on_step=None):
+def drive(s, leg, sizes, steps, judge=None, on_step=None, profiled=False):
     """Iterations 1..steps of the schedule on sampler s; the learned leg reports each step's
-    ESS to its run-level judge (which may switch the sampler to the fixed step)."""
+    ESS to its run-level judge (which may switch the sampler to the fixed step).  In a profiled
+    run the judge's held-out predictions are left out of the kernel table, which then holds
+    the sampler's own launches only."""
     learned = leg_parts(leg)[1] == "learned"
     for k in range(1, steps + 1):
         want = learned or on_step is not None
         info = s.step(sizes[k], N_TRAIN / sizes[k], info=want)
         if learned and judge is not None:
+            if profiled:
+                s.profile(False)
             judge.after_step(s, k, info["ess"])
+            if profiled:
+                s.profile(True)
         s.resample()
         if on_step is not None:
             on_step(k, info)
@@ -213,7 +228,7 @@ def run_timed(P, dev, leg, sizes, steps, warmup, seed, net=None, ref=None):
             s.profile_read()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        drive(s, leg, sizes, steps, judge)
+        drive(s, leg, sizes, steps, judge, profiled=profiled)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if profiled:
@@ -270,12 +285,13 @@ def kernel_table(prof, prec):
     return out
 
 
-def roofline(prof, prec, m_mean=None):
-    """The dominant kernel class (by total time) against its roofline; with m_mean (the mean
-    samples per launch of the timed gradient passes, padded to 256) the HBM traffic per launch
-    from the committed PMC fit."""
+def roofline(prof, prec, launches=None):
+    """The dominant kernel class (by total time) against its roofline; with `launches` (the fused
+    kernel's (mode, M) launches of the timed iterations) the mean HBM traffic per launch from the
+    committed PMC fits."""
     name, (ms, n, fl, by) = max(prof.items(), key=lambda kv: kv[1][0])
-    traffic = measured_traffic(name, m_mean) if m_mean is not None else None
+    # the launch list must be the timed fused launches one for one
+    traffic = measured_traffic(name, launches) if launches is not None and len(launches) == n else None
     if fl > 0 and name.startswith("gemm"):
         ach = fl / (ms * 1e-3) / 1e12
         peak = PEAK[prec]
@@ -790,10 +806,12 @@ def main():
                    "particles": J, "iterations": steps, "schedule_iterations": K_FULL, "max_subset": m_last,
                    "proposal": hprop, "precision": hprec},
         "timing": "value from a run without instrumentation; roofline and kernels from a second run of the same "
-                  "iterations with every launch bracketed by HIP events on the library's stream",
+                  "iterations with every launch bracketed by HIP events on the library's stream (the proposal "
+                  "judge's held-out predictions not bracketed)",
         "seconds_profiled_run": round(b["seconds_profiled"], 4),
         "proposal_judge": b.get("judge"),
-        "roofline": roofline(b["prof"], hprec, pass_mean_m(sizes, steps) if head == TRAFFIC_LEG else None),
+        "roofline": roofline(b["prof"], hprec, fused_launches(
+            sizes, steps, (b["judge"]["iteration"] or steps) if b.get("judge") else 0) if head == TRAFFIC_LEG else None),
         "cpu_baseline": cpu,
         "time_to_accuracy": tta,
         "proposal_network": training,

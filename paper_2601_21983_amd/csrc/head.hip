@@ -671,28 +671,67 @@ __global__ __launch_bounds__(HTHREADS, 2) void fwd_head_kernel(const GemmParams 
 }
 
 // Sum the per-split partials of one chunk in a fixed order and fold them into the
-// running totals: ll_acc[j] (+)= sum, grad[j][offL + e] (+)= sum.
-__global__ void head_reduce_kernel(const HeadArgs a, int beta, int with_grad) {
+// running totals: ll_acc[j] (+)= sum, grad[j][offL + e] (+)= sum.  Block (j, y) takes
+// particle j and columns [64 y, 64 y + 64) of the output-layer gradient; its four waves
+// sum the splits k = w (mod 4) with four FP64 accumulators (so each lane keeps several
+// loads in flight), and wave 0 adds the four waves' sums in order.  Block (j, 0) also sums
+// the log-likelihood partials (lanes over k, then a butterfly).
+constexpr int HR_COLS = 64, HR_WAVES = 4;
+
+__device__ double wave_sum_f64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(HR_COLS * HR_WAVES) void head_reduce_kernel(const HeadArgs a, int beta, int with_grad) {
   const int j = blockIdx.x;
-  const int npair = a.C * (a.H + 1);
-  if (threadIdx.x == 0) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (blockIdx.y == 0 && w == 0) {
+    const double* lp = a.llpart + (int64_t)j * a.nsplit;
     double s = 0.0;
-    for (int k = 0; k < a.nsplit; ++k) s += a.llpart[(int64_t)j * a.nsplit + k];
-    a.ll_acc[j] = beta ? a.ll_acc[j] + s : s;
+    for (int k = lane; k < a.nsplit; k += 64) s += lp[k];
+    s = wave_sum_f64(s);
+    if (lane == 0) a.ll_acc[j] = beta ? a.ll_acc[j] + s : s;
     if (a.ll_acc_b) {
+      const double* lb = a.llpart_b + (int64_t)j * a.nsplit;
       double sb = 0.0;
-      for (int k = 0; k < a.nsplit; ++k) sb += a.llpart_b[(int64_t)j * a.nsplit + k];
-      a.ll_acc_b[j] = beta ? a.ll_acc_b[j] + sb : sb;
+      for (int k = lane; k < a.nsplit; k += 64) sb += lb[k];
+      sb = wave_sum_f64(sb);
+      if (lane == 0) a.ll_acc_b[j] = beta ? a.ll_acc_b[j] + sb : sb;
     }
   }
   if (!with_grad) return;
-  const float* src = a.dWpart + (int64_t)j * a.nsplit * npair;
-  float* gr = a.grad + (int64_t)j * a.D + a.offL;
-  for (int e = threadIdx.x; e < npair; e += blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < a.nsplit; ++k) s += (double)src[(int64_t)k * npair + e];
-    gr[e] = beta ? gr[e] + (float)s : (float)s;
+  __shared__ double part[HR_WAVES][HR_COLS];
+  const int npair = a.C * (a.H + 1);
+  const int e = blockIdx.y * HR_COLS + lane;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (e < npair) {
+    const float* src = a.dWpart + (int64_t)j * a.nsplit * npair + e;
+    const int64_t st = (int64_t)HR_WAVES * npair;
+    int k = w;
+    for (; k + 3 * HR_WAVES < a.nsplit; k += 4 * HR_WAVES) {
+      const float* q = src + (int64_t)k * npair;
+      s0 += (double)q[0];
+      s1 += (double)q[st];
+      s2 += (double)q[2 * st];
+      s3 += (double)q[3 * st];
+    }
+    for (; k < a.nsplit; k += HR_WAVES) s0 += (double)src[(int64_t)k * npair];
   }
+  part[w][lane] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (w == 0 && e < npair) {
+    const double t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    float* gr = a.grad + (int64_t)j * a.D + a.offL;
+    gr[e] = beta ? gr[e] + (float)t : (float)t;
+  }
+}
+
+hipError_t head_reduce_run(const HeadArgs& a, int mode, hipStream_t s) {
+  const int with_grad = mode == HEAD_TRAIN ? 1 : 0;
+  const int ncol = with_grad ? (a.C * (a.H + 1) + HR_COLS - 1) / HR_COLS : 1;
+  hipLaunchKernelGGL(head_reduce_kernel, dim3(a.J, ncol), dim3(HR_COLS * HR_WAVES), 0, s, a, a.beta, with_grad);
+  return hipGetLastError();
 }
 
 constexpr int LDS_LIMIT = 160 * 1024;
@@ -745,8 +784,7 @@ hipError_t head_run(const HeadArgs& a, int mode, int type, hipStream_t s) {
 #undef HEAD_LAUNCH
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || mode == HEAD_PREDICT) return e;
-  hipLaunchKernelGGL(head_reduce_kernel, dim3(a.J), dim3(256), 0, s, a, a.beta, mode == HEAD_TRAIN ? 1 : 0);
-  return hipGetLastError();
+  return head_reduce_run(a, mode, s);
 }
 
 bool fwd_head_supported(int H, int C) {
@@ -786,8 +824,7 @@ hipError_t fwd_head_run(const GemmParams& p, const HeadArgs& a, int mode, int sp
 #undef FH_LAUNCH
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || mode == HEAD_PREDICT) return e;
-  hipLaunchKernelGGL(head_reduce_kernel, dim3(a.J), dim3(256), 0, s, a, a.beta, mode == HEAD_TRAIN ? 1 : 0);
-  return hipGetLastError();
+  return head_reduce_run(a, mode, s);
 }
 
 hipError_t head_set_smem_limits() {
