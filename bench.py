@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--table1-moves", default="LD,HMC", help="moves of the study: LD, HMC or both")
     ap.add_argument("--lenet-pass", action="store_true",
                     help="instead of the benchmark: LeNet-5 gradient passes over the training set at J = 32 and 256")
+    ap.add_argument("--library-gemm", action="store_true",
+                    help="instead of the benchmark: the layer-1 products of this library against torch.matmul "
+                         "(hipBLASLt) on the same shapes")
     ap.add_argument("--sda-iters", type=int, default=SDA_MAX_ITERS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference kernel for HBM counters)")
@@ -678,6 +681,64 @@ def cpu_baseline(X, y, sizes, budget_s=4.0, J_s=8, reps=3):
             "runs": [round(x, 1) for x in rates]}
 
 
+def run_library_gemm(P, dev, reps=5):
+    """The layer-1 products of one BF16 gradient pass (J = 256, 784-100-10, M samples) in this
+    library and in torch.matmul (hipBLASLt) on the same shapes: the weight gradient
+    [J*H x M] . [M x (F+1)] and the forward [M x F] . [F x J*H] (the library's fused kernel also
+    runs the output layer and its backward).  FLOP counts are 2 * rows * cols * depth."""
+    import torch
+    J, H, F = 256, 100, 784
+    out = {"metric": "layer-1 products: library against torch.matmul (hipBLASLt)", "unit": "TFLOP/s",
+           "J": J, "widths": [F, H, 10], "dtype": "bf16", "cases": []}
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for M in (30720, N_TRAIN):
+        cfg = P.SMCConfig(widths=[F, H, 10], n_particles=J, activation="relu", precision="bf16", step_size=0.002)
+        s = P.SMCSampler(cfg, dev["X"], dev["y"], m0=M, lambda0=N_TRAIN / M)
+        th = s.state()["theta"]
+        for _ in range(2):
+            s.nn_backward(th, M)
+        torch.cuda.synchronize()
+        s.profile(True)
+        s.profile_read()
+        for _ in range(reps):
+            s.nn_backward(th, M)
+        prof = s.profile_read()
+        s.close()
+        dw_ms = prof["gemm_dw1"][0] / prof["gemm_dw1"][1]
+        fw_ms = prof["gemm_fwd1"][0] / prof["gemm_fwd1"][1]
+        a = torch.randn(J * H, M, device="cuda", dtype=torch.bfloat16)
+        b = torch.randn(M, F + 1, device="cuda", dtype=torch.bfloat16)
+        t_dw = timed(lambda: a @ b)
+        del a, b
+        x = torch.randn(M, F, device="cuda", dtype=torch.bfloat16)
+        w = torch.randn(F, J * H, device="cuda", dtype=torch.bfloat16)
+        t_fw = timed(lambda: x @ w)
+        del x, w
+        fl_dw = 2.0 * J * H * (F + 1) * M
+        fl_fw = 2.0 * M * F * J * H
+        out["cases"].append({
+            "M": M,
+            "weight_gradient": {"library_ms": round(dw_ms, 4), "library_tflops": round(fl_dw / dw_ms / 1e9, 1),
+                                "hipblaslt_ms": round(t_dw, 4), "hipblaslt_tflops": round(fl_dw / t_dw / 1e9, 1)},
+            "forward": {"library_fused_ms": round(fw_ms, 4), "library_fused_layer1_tflops": round(fl_fw / fw_ms / 1e9, 1),
+                        "hipblaslt_layer1_only_ms": round(t_fw, 4),
+                        "hipblaslt_tflops": round(fl_fw / t_fw / 1e9, 1)}})
+        log(f"library gemm M={M}: {json.dumps(out['cases'][-1])}")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -709,6 +770,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.library_gemm:
+        print(json.dumps(run_library_gemm(P, dev)), flush=True)
+        return
     if args.lenet_pass:
         for Jl in (TABLE1_J, 256):
             print(json.dumps(run_lenet_pass(P, dev, Jl)), flush=True)
