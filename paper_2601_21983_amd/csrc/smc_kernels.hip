@@ -36,34 +36,60 @@ __global__ __launch_bounds__(256) void cast_kernel(const NetShape n, const float
                                                    const int32_t* __restrict__ placement) {
   const int j = blockIdx.y;
   if (placement && placement[j] == j) return;
-  const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + 4 * threadIdx.x;
+  // consecutive lanes take consecutive parameters (coalesced loads and copy stores)
+  const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + threadIdx.x;
   const float* th = theta + (int64_t)j * n.D;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t e = e0 + i;
+    const int64_t e = e0 + 256 * i;
     if (e < n.D) cast_any(n, j, e, th[e]);
   }
 }
 
 // ------------------------------------------------------------------ move
+// Lane t of workgroup b handles parameters e = 1024 b + t + 256 i (i = 0..3), so that each
+// load and store instruction covers 64 consecutive parameters.  The momentum of parameter e
+// is normal (e mod 4) of the Philox block e / 4 of its particle.  The four parameters of lane
+// (q, s) = (t / 4, t mod 4) lie in the blocks 256 b + 64 i + q, all at position s: lane
+// (q, r) draws block 256 b + 64 r + q, and a 4x4 transpose inside the lane quad hands
+// every lane its four normals.
+__device__ __forceinline__ float pick4(const f32x4& v, int k) {
+  return k == 0 ? v[0] : (k == 1 ? v[1] : (k == 2 ? v[2] : v[3]));
+}
+
 __global__ __launch_bounds__(256) void move_kernel(const MoveArgs a) {
   __shared__ double red[3][4];
   const int j = blockIdx.y;
   const int64_t D = a.net.D;
-  const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + 4 * threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + threadIdx.x;
   float* th = a.theta + (int64_t)j * D;
   float* P = a.P + (int64_t)j * D;
   const float* g = a.g + (int64_t)j * D;
   float s_xi = 0.0f, s_th = 0.0f, s_pe = 0.0f;
-  f32x4 nz = {0.0f, 0.0f, 0.0f, 0.0f};
-  if (a.mode == MOVE_FIRST && !a.noise && e0 < D) {
-    const u32x4 c = {(uint32_t)(e0 >> 2), (uint32_t)j, a.ctr_iter, (uint32_t)TAG_MOMENTUM};
-    nz = normal4(philox4x32_10(c, a.key0, a.key1));
+  float nz[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (a.mode == MOVE_FIRST && !a.noise) {
+    const int q = (threadIdx.x & 63) >> 2, r = threadIdx.x & 3, w = threadIdx.x >> 6;
+    // this lane's draw: block (1024 b + 256 r + 64 w + 4 q) / 4 of particle j
+    const uint32_t blk = (uint32_t)(((int64_t)blockIdx.x * MOVE_ELEMS + 256 * r + 64 * w + 4 * q) >> 2);
+    const u32x4 c = {blk, (uint32_t)j, a.ctr_iter, (uint32_t)TAG_MOMENTUM};
+    const f32x4 mine = normal4(philox4x32_10(c, a.key0, a.key1));
+    // round k: lane (q, s) receives normal s of the block drawn by lane (q, (s - k) & 3), which
+    // belongs to its parameter i = (s - k) & 3; the sender offers its normal (r + k) & 3
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float offer = pick4(mine, (r + k) & 3);
+      const float got = k == 0 ? offer : __shfl(offer, (r - k) & 3, 4);
+      const int i = (r - k) & 3;
+      nz[0] = i == 0 ? got : nz[0];
+      nz[1] = i == 1 ? got : nz[1];
+      nz[2] = i == 2 ? got : nz[2];
+      nz[3] = i == 3 ? got : nz[3];
+    }
   }
   const float h = a.h, hh = 0.5f * a.h;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t e = e0 + i;
+    const int64_t e = e0 + 256 * i;
     if (e >= D) break;
     float t = th[e];
     const float gf = g[e] - t * a.inv_prior_var;
@@ -474,10 +500,10 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(int64_t D, const int32
   const int j = blockIdx.y;
   const int p = placement[j];
   if (p == j) return;
-  const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + 4 * threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + threadIdx.x;  // coalesced, as in cast_kernel
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t e = e0 + i;
+    const int64_t e = e0 + 256 * i;
     if (e >= D) break;
     a0[(int64_t)j * D + e] = a0[(int64_t)p * D + e];
     if (a1) a1[(int64_t)j * D + e] = a1[(int64_t)p * D + e];
