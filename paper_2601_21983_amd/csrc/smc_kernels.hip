@@ -174,7 +174,26 @@ __global__ __launch_bounds__(1024) void weight_kernel(const WeightArgs a) {
       const double* p0 = a.part + (int64_t)j * a.nblk;
       const double* p1 = a.part + ((int64_t)J + j) * a.nblk;
       const double* p2 = a.part + ((int64_t)2 * J + j) * a.nblk;
-      for (int b = 0; b < a.nblk; ++b) { k0 += p0[b]; kt += p1[b]; k1 += p2[b]; }
+      // eight independent accumulators per sum keep 24 loads in flight (a plain running sum
+      // waits for each load in turn); fixed order, so the result is reproducible
+      double s0[8] = {0, 0, 0, 0, 0, 0, 0, 0}, st[8] = {0, 0, 0, 0, 0, 0, 0, 0}, s1[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int b = 0;
+      for (; b + 8 <= a.nblk; b += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          s0[u] += p0[b + u];
+          st[u] += p1[b + u];
+          s1[u] += p2[b + u];
+        }
+      }
+      for (int u = 0; b < a.nblk; ++b, ++u) {
+        s0[u] += p0[b];
+        st[u] += p1[b];
+        s1[u] += p2[b];
+      }
+      k0 += ((s0[0] + s0[1]) + (s0[2] + s0[3])) + ((s0[4] + s0[5]) + (s0[6] + s0[7]));
+      kt += ((st[0] + st[1]) + (st[2] + st[3])) + ((st[4] + st[5]) + (st[6] + st[7]));
+      k1 += ((s1[0] + s1[1]) + (s1[2] + s1[3])) + ((s1[4] + s1[5]) + (s1[6] + s1[7]));
       if (a.no_kinetic) { k0 = 0.0; k1 = 0.0; }
     }
     const double ll = a.ll[j];
