@@ -290,3 +290,50 @@ def test_posterior_mean_criterion_drives_adaptive_growth():
     s.set_state(st["theta"])
     assert s.posterior_mean_change() == float("inf")
     s.close()
+
+
+def test_device_momenta_follow_the_philox_blocks():
+    # The move's own momenta: parameter e of particle j takes normal (e mod 4) of the Philox
+    # block (e div 4, j, iteration counter, tag 1) under the key (seed low word, seed high word),
+    # Box-Muller on the block's two uniform pairs.  Recovered from one Langevin half step from
+    # the cached gradient and checked for every parameter against the published generator:
+    # D = 1,261 spans two move workgroups (the second ragged) and ends inside a Philox block.
+    cuda()
+    P = lib()
+    from oracle.philox import philox4x32
+    J, h, prior, seed, noise = 3, 0.01, 1.0, 0x1234_5678_9ABC, 0.5
+    X, yv, _ = smc_inputs.linreg(64, 40, seed=5, noise_std=noise)
+    # FP32 operands and a small likelihood scale keep the drift term, which the recovery
+    # subtracts, far below the momenta
+    cfg = P.SMCConfig(widths=[40, 30, 1], n_particles=J, activation="tanh", likelihood="gaussian",
+                      noise_std=noise, step_size=h, prior_std=prior, seed=seed, precision="fp32")
+    s = P.SMCSampler(cfg, to_dev(X), to_dev(yv.astype(np.float32)), m0=64, lambda0=0.01)
+    print_case("device-momenta", J=J, D=s.D)
+    st0 = s.state()
+    s.step(64, 0.01, info=False)  # the same target: the move starts from the cached gradient
+    st1 = s.state()
+    s.close()
+    th0 = st0["theta"].cpu().numpy().astype(np.float64)
+    g0 = st0["grad"].cpu().numpy().astype(np.float64)
+    th1 = st1["theta"].cpu().numpy().astype(np.float64)
+    xi = (th1 - th0) / h - 0.5 * h * g0  # the state's gradient is the log target's (prior included)
+    ctr = (st0["rng_counter"] + 1) & 0xFFFFFFFF
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    D = th0.shape[1]
+    assert D == 1261
+    want = np.empty((J, D))
+    for j in range(J):
+        for b in range((D + 3) // 4):
+            r = philox4x32((b, j, ctr, 1), key)
+            for t in range(4):
+                e = 4 * b + t
+                if e >= D:
+                    break
+                u1 = ((r[2 * (t // 2)] >> 8) + 1) / 2.0 ** 24
+                u2 = (r[2 * (t // 2) + 1] >> 8) / 2.0 ** 24
+                rad = math.sqrt(-2.0 * math.log(u1))
+                want[j, e] = rad * (math.cos(2 * math.pi * u2) if t % 2 == 0 else math.sin(2 * math.pi * u2))
+    err = np.abs(xi - want)
+    print(f"[measured] max |xi - philox normal| {np.max(err):.2e}, drift term up to "
+          f"{0.5 * h * np.max(np.abs(g0)):.2e}", flush=True)
+    assert np.max(err) < 1e-3, (np.unravel_index(np.argmax(err), err.shape), np.max(err))
