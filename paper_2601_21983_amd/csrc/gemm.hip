@@ -44,12 +44,20 @@ __device__ __forceinline__ float act_deriv(float a) {
 // ACT: activation of the FWD epilogue / derivative of the DELTA epilogue (-1: none)
 // F32O: the FWD epilogue stores FP32 values (BF16 operands only)
 template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT, bool F32O>
-__global__ __launch_bounds__(THREADS, tile_minb(BM, BN, (int)sizeof(T))) void gemm_nt(const GemmParams p) {
+// the second bound is waves per SIMD: tile_minb workgroups per CU of NT / 256 waves per SIMD each
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64,
+                             tile_minb(BM, BN, (int)sizeof(T)) * (BM / WM) * (BN / WN) / 4) void gemm_nt(
+    const GemmParams p) {
+  constexpr int NT = (BM / WM) * (BN / WN) * 64;  // one wave per WM x WN sub-tile
   constexpr int NWN = BN / WN;
   constexpr int FM = WM / 32, FN = WN / 32;
   constexpr int STAGE = (BM + BN) * LDS_ROW;
   constexpr int NBUF = tile_nbuf(BM, BN, (int)sizeof(T));
-  __shared__ __attribute__((aligned(16))) char smem[NBUF * STAGE];
+  // the staged epilogue's slab ([BM/WM * 32 rows][BN + pad] floats plus row and column tables) may
+  // need more than the main loop's stages when the waves are stacked four deep
+  constexpr int SLAB_NEED = (BM / WM) * 32 * (BN + 4) * 4 + ((BM / WM) * 32 + BN) * 8;
+  constexpr int SMEM = NBUF * STAGE > SLAB_NEED ? NBUF * STAGE : SLAB_NEED;
+  __shared__ __attribute__((aligned(16))) char smem[SMEM];
 
   const int b = blockIdx.y;
   int tm, tn;
@@ -73,7 +81,7 @@ __global__ __launch_bounds__(THREADS, tile_minb(BM, BN, (int)sizeof(T))) void ge
     O* slab = (O*)smem;                 // [NWM*32][SROW]
     constexpr int NWM = BM / WM;
     constexpr int SLAB_BYTES = NWM * 32 * SROW * OS;
-    static_assert(SLAB_BYTES + (NWM * 32 + BN) * 8 <= NBUF * STAGE, "slab does not fit in LDS");
+    static_assert(SLAB_BYTES + (NWM * 32 + BN) * 8 <= SMEM, "slab does not fit in LDS");
     int64_t* rowaddr = (int64_t*)(smem + SLAB_BYTES);
     int64_t* colpart = rowaddr + NWM * 32;
     const OutDesc& d = p.out0;
@@ -82,7 +90,7 @@ __global__ __launch_bounds__(THREADS, tile_minb(BM, BN, (int)sizeof(T))) void ge
              d.sb % ve == 0 && d.sC % ve == 0 && d.cs % ve == 0;
     };
     const int vw = aligned(16 / OS) ? 16 / OS : (aligned(8 / OS) ? 8 / OS : 1);
-    for (int lc = tid; lc < BN; lc += THREADS) {
+    for (int lc = tid; lc < BN; lc += NT) {
       const int col = n0 + lc;
       colpart[lc] = col < N ? (int64_t)(col / d.cs) * d.sC + (col % d.cs) : -1;
     }
@@ -110,7 +118,7 @@ __global__ __launch_bounds__(THREADS, tile_minb(BM, BN, (int)sizeof(T))) void ge
       }
       __syncthreads();
       const int vpr = BN / vw;  // vectors per slab row
-      for (int e = tid; e < NWM * 32 * vpr; e += THREADS) {
+      for (int e = tid; e < NWM * 32 * vpr; e += NT) {
         const int lr = e / vpr, lc = (e - lr * vpr) * vw;
         const int64_t ra = rowaddr[lr];
         const int col = n0 + lc;
@@ -194,13 +202,14 @@ template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT>
 hipError_t launch_one(const GemmParams& p, dim3 grid, hipStream_t s) {
   if constexpr (EPI == EPI_FWD && std::is_same<T, __bf16>::value) {
     if (p.out_f32) {
-      hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI, ACT, true>), grid, dim3(THREADS), 0, s, p);
+      hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI, ACT, true>), grid, dim3((BM / WM) * (BN / WN) * 64), 0, s,
+                         p);
       return hipGetLastError();
     }
   } else if (EPI != EPI_FWD) {
     if (p.out_f32) return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI, ACT, false>), grid, dim3(THREADS), 0, s, p);
+  hipLaunchKernelGGL((gemm_nt<T, BM, BN, WM, WN, EPI, ACT, false>), grid, dim3((BM / WM) * (BN / WN) * 64), 0, s, p);
   return hipGetLastError();
 }
 
@@ -241,6 +250,12 @@ hipError_t gemm_run(const GemmParams& p, int type, hipStream_t stream) {
   if (type == GEMM_BF16) {
     if (p.N <= 32) return launch_cfg<__bf16, 256, 32, 64, 32>(p, stream);
     if (p.M <= 32) return launch_cfg<__bf16, 32, 128, 32, 32>(p, stream);
+    // weight gradients (long K) run the large tile as eight waves of 64x64 (118 VGPRs, four waves
+    // per SIMD with two workgroups per CU) rather than four of 128x64 (244 VGPRs, two per SIMD):
+    // more waves to cover the K-step barriers and LDS round trips (layer-1 weight gradient at
+    // 30,000 samples 1.61 -> 1.47 ms, at J = 1024 and 2,560 samples 2.18 -> 1.64 ms).  The
+    // forward (K = 784) lost 17% that way and keeps four waves.
+    if (big && p.epi == EPI_GRAD) return launch_cfg<__bf16, 256, 128, 64, 64>(p, stream);
     return big ? launch_cfg<__bf16, 256, 128, 128, 64>(p, stream) : launch_cfg<__bf16, 128, 128, 64, 64>(p, stream);
   }
   if (p.N <= 32) return launch_cfg<float, 256, 32, 64, 32>(p, stream);

@@ -1,7 +1,7 @@
 // Matrix-core main loop shared by the batched GEMM (gemm.hip) and the fused
 // layer-1 + output-layer kernel (head.hip).
 //
-// Tiling: a 256-thread workgroup (4 wave64s) computes a BM x BN tile; each wave
+// Tiling: a workgroup of 4 or 8 wave64s computes a BM x BN tile; each wave
 // owns a WM x WN sub-tile made of 32x32 MFMA blocks.  Every K step stages a
 // 128-byte-deep slice of A and B (64 bf16 or 32 fp32) in LDS with a 16-byte row
 // pad (row stride 144 B, so the 16-byte fragment reads of 16 consecutive rows hit
@@ -98,12 +98,13 @@ __device__ __forceinline__ void mainloop(const T* __restrict__ A, const T* __res
   constexpr int BKE = ROW_BYTES / (int)sizeof(T);
   constexpr int NWN = BN / WN;
   constexpr int FM = WM / 32, FN = WN / 32;
-  constexpr int AV = BM * ROWV / THREADS;
-  constexpr int BV = BN * ROWV / THREADS;
+  constexpr int NT = (BM / WM) * (BN / WN) * 64;  // threads: one wave per WM x WN sub-tile
+  constexpr int AV = BM * ROWV / NT;
+  constexpr int BV = BN * ROWV / NT;
   constexpr int STAGE = stage_bytes<BM, BN, SB>();
   constexpr int NBV = SB ? 2 * BV : BV;  // B vectors per thread per stage (both planes)
-  static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
-  static_assert(AV >= 1 && BV >= 1, "tile too small");
+  static_assert(NT == 256 || NT == 512, "four or eight waves per workgroup");
+  static_assert(AV >= 1 && BV >= 1 && BM * ROWV % NT == 0 && BN * ROWV % NT == 0, "tile too small");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / NWN, wn = wave % NWN;
 
@@ -115,17 +116,17 @@ __device__ __forceinline__ void mainloop(const T* __restrict__ A, const T* __res
   uint32_t aoff[AV], boff[BV];
 #pragma unroll
   for (int i = 0; i < AV; ++i) {
-    const int r = (tid + i * THREADS) / ROWV;
+    const int r = (tid + i * NT) / ROWV;
     const int gr = min(m0 + r, M - 1) - m0;
-    aoff[i] = (uint32_t)((gr * (int64_t)lda + ((tid + i * THREADS) % ROWV) * VEC) * (int64_t)sizeof(T));
+    aoff[i] = (uint32_t)((gr * (int64_t)lda + ((tid + i * NT) % ROWV) * VEC) * (int64_t)sizeof(T));
   }
 #pragma unroll
   for (int i = 0; i < BV; ++i) {
-    const int r = (tid + i * THREADS) / ROWV;
+    const int r = (tid + i * NT) / ROWV;
     const int gr = min(n0 + r, N - 1) - n0;
-    boff[i] = (uint32_t)((gr * (int64_t)ldb + ((tid + i * THREADS) % ROWV) * VEC) * (int64_t)sizeof(T));
+    boff[i] = (uint32_t)((gr * (int64_t)ldb + ((tid + i * NT) % ROWV) * VEC) * (int64_t)sizeof(T));
   }
-  const int kvec = (tid % ROWV) * VEC;  // same for every i since THREADS % ROWV == 0
+  const int kvec = (tid % ROWV) * VEC;  // same for every i since NT % ROWV == 0
 
   u32x4 ra[AV], rb[NBV];
   auto gload = [&](int kt) {
@@ -146,13 +147,13 @@ __device__ __forceinline__ void mainloop(const T* __restrict__ A, const T* __res
     char* base = smem + buf * STAGE;
 #pragma unroll
     for (int i = 0; i < AV; ++i) {
-      const int v = tid + i * THREADS;
+      const int v = tid + i * NT;
       *(u32x4*)(base + (v / ROWV) * LDS_ROW + (v % ROWV) * 16) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < NBV; ++i) {
       // lo plane rows follow the BN hi rows
-      const int v = tid + (i % BV) * THREADS;
+      const int v = tid + (i % BV) * NT;
       *(u32x4*)(base + (BM + (i / BV) * BN + v / ROWV) * LDS_ROW + (v % ROWV) * 16) = rb[i];
     }
   };
