@@ -250,12 +250,12 @@ hipError_t gemm_run(const GemmParams& p, int type, hipStream_t stream) {
   if (type == GEMM_BF16) {
     if (p.N <= 32) return launch_cfg<__bf16, 256, 32, 64, 32>(p, stream);
     if (p.M <= 32) return launch_cfg<__bf16, 32, 128, 32, 32>(p, stream);
-    // weight gradients (long K) run the large tile as eight waves of 64x64 (118 VGPRs, four waves
+    // weight gradients (long K) run the large tile as sixteen waves of 64x32 (64 VGPRs, eight waves
     // per SIMD with two workgroups per CU) rather than four of 128x64 (244 VGPRs, two per SIMD):
     // more waves to cover the K-step barriers and LDS round trips (layer-1 weight gradient at
-    // 30,000 samples 1.61 -> 1.47 ms, at J = 1024 and 2,560 samples 2.18 -> 1.64 ms).  The
-    // forward (K = 784) lost 17% that way and keeps four waves.
-    if (big && p.epi == EPI_GRAD) return launch_cfg<__bf16, 256, 128, 64, 64>(p, stream);
+    // 30,000 samples 1.61 ms with four waves, 1.53 with eight of 64x64, 1.46 with sixteen).  The
+    // forward (K = 784) lost 17% with eight waves and keeps four.
+    if (big && p.epi == EPI_GRAD) return launch_cfg<__bf16, 256, 128, 64, 32>(p, stream);
     return big ? launch_cfg<__bf16, 256, 128, 128, 64>(p, stream) : launch_cfg<__bf16, 128, 128, 64, 64>(p, stream);
   }
   if (p.N <= 32) return launch_cfg<float, 256, 32, 64, 32>(p, stream);

@@ -1,7 +1,7 @@
 // Matrix-core main loop shared by the batched GEMM (gemm.hip) and the fused
 // layer-1 + output-layer kernel (head.hip).
 //
-// Tiling: a workgroup of 4 or 8 wave64s computes a BM x BN tile; each wave
+// Tiling: a workgroup of 4, 8 or 16 wave64s computes a BM x BN tile; each wave
 // owns a WM x WN sub-tile made of 32x32 MFMA blocks.  Every K step stages a
 // 128-byte-deep slice of A and B (64 bf16 or 32 fp32) in LDS with a 16-byte row
 // pad (row stride 144 B, so the 16-byte fragment reads of 16 consecutive rows hit
@@ -103,7 +103,7 @@ __device__ __forceinline__ void mainloop(const T* __restrict__ A, const T* __res
   constexpr int BV = BN * ROWV / NT;
   constexpr int STAGE = stage_bytes<BM, BN, SB>();
   constexpr int NBV = SB ? 2 * BV : BV;  // B vectors per thread per stage (both planes)
-  static_assert(NT == 256 || NT == 512, "four or eight waves per workgroup");
+  static_assert(NT == 256 || NT == 512 || NT == 1024, "four, eight or sixteen waves per workgroup");
   static_assert(AV >= 1 && BV >= 1 && BM * ROWV % NT == 0 && BN * ROWV % NT == 0, "tile too small");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / NWN, wn = wave % NWN;
