@@ -256,6 +256,9 @@ hipError_t gemm_run(const GemmParams& p, int type, hipStream_t stream) {
     // 30,000 samples 1.61 ms with four waves, 1.53 with eight of 64x64, 1.46 with sixteen).  The
     // forward (K = 784) lost 17% with eight waves and keeps four.
     if (big && p.epi == EPI_GRAD) return launch_cfg<__bf16, 256, 128, 64, 32>(p, stream);
+    // smaller weight gradients: the 128x128 tile as eight waves of 64x32 (88 VGPRs, two workgroups
+    // per CU): the 784-256-256-10 network's layer-2 GEMM class 1.87 -> 1.79 ms
+    if (p.epi == EPI_GRAD) return launch_cfg<__bf16, 128, 128, 64, 32>(p, stream);
     return big ? launch_cfg<__bf16, 256, 128, 128, 64>(p, stream) : launch_cfg<__bf16, 128, 128, 64, 64>(p, stream);
   }
   if (p.N <= 32) return launch_cfg<float, 256, 32, 64, 32>(p, stream);

@@ -55,7 +55,11 @@ template <> struct Mf<float> {
 // layer-1 GEMMs).  Other tiles, and FP32 (whose weight-gradient GEMM lost 15% that way),
 // double-buffer with one workgroup per CU.
 constexpr int tile_nbuf(int bm, int bn, int esz) { return (bm == 256 && bn == 128 && esz == 2) ? 1 : 2; }
-constexpr int tile_minb(int bm, int bn, int esz) { return tile_nbuf(bm, bn, esz) == 1 ? 2 : 1; }
+// Workgroups per CU that a tile is compiled for (its register budget follows): the single-stage
+// BF16 256x128 tile and the double-buffered BF16 128x128 tile (74 KB) fit two.
+constexpr int tile_minb(int bm, int bn, int esz) {
+  return (tile_nbuf(bm, bn, esz) == 1 || (bm == 128 && bn == 128 && esz == 2)) ? 2 : 1;
+}
 
 // Host check: the main loop addresses a tile's rows by 32-bit byte offsets from its first
 // row, so 256 rows of the larger leading dimension must span less than 4 GiB.
