@@ -134,3 +134,36 @@ def test_deep_network_full_size_on_sampled_particles():
         print(f"particle {j}: ll {e_ll:.3g}, grad {e_g:.3g}", flush=True)
         assert e_ll < 2e-2, (j, e_ll)
         assert e_g < 3e-2, (j, e_g)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_weight_gradient_tiles_with_ragged_edges(precision):
+    """The large weight-gradient tiles (sixteen waves of 64x32 for 256x128, in BF16 and FP32) at
+    a ragged size: J = 257 particles give 25,700 unit rows (the last 256-row tile holds one
+    particle's 100 rows and 156 of clamped padding), 785 gradient columns (the last 128-wide
+    tile 17), and 3,001 samples (a ragged last K step); sampled particles, including the one in
+    the last row tile, against the oracle (Eq. approx-grad, unscaled)."""
+    cuda()
+    P = lib()
+    widths, J, M = [784, 100, 10], 257, 3001
+    X, y = smc_inputs.templates28(M, seed=4)
+    D = mlp.n_params(widths)
+    theta = smc_inputs.prior_draw(8, J, D, 0.05)
+    print_case("ragged-weight-gradient", J=J, M=M, prec=precision)
+    cfg = P.SMCConfig(widths=widths, n_particles=J, precision=precision, step_size=0.002)
+    td = to_dev(theta)
+    s = P.SMCSampler(cfg, to_dev(X), to_dev(y.astype(np.int32)), m0=M, lambda0=1.0, theta0=td)
+    ll, g = s.nn_backward(td, M)
+    torch.cuda.synchronize()
+    ll, g = ll.cpu().numpy(), g.cpu().numpy()
+    s.close()
+    assert np.all(np.isfinite(ll)) and np.all(np.isfinite(g))
+    Xo = X.astype(np.float64) if precision == "fp32" else bf16_round(X)
+    tol_g = 2e-4 if precision == "fp32" else 5e-3
+    for j in (0, 131, 255, 256):
+        ll_o, g_o = mlp.loglik_grad(theta[j:j + 1].astype(np.float64), Xo, y, widths, "relu")
+        e_ll = abs(ll[j] - ll_o[0]) / abs(ll_o[0])
+        e_g = np.max(np.abs(g[j] - g_o[0])) / np.max(np.abs(g_o[0]))
+        print(f"particle {j}: ll {e_ll:.3g}, grad {e_g:.3g}", flush=True)
+        assert e_ll < 1e-4, (j, e_ll)
+        assert e_g < tol_g, (j, e_g)
