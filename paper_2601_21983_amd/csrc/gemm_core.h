@@ -24,7 +24,6 @@
 namespace smc {
 namespace gcore {
 
-constexpr int THREADS = 256;
 constexpr int ROW_BYTES = 128;          // K slice per stage, in bytes
 constexpr int LDS_ROW = ROW_BYTES + 16; // padded LDS row stride
 constexpr int ROWV = ROW_BYTES / 16;    // 16-byte vectors per row
@@ -53,7 +52,8 @@ template <> struct Mf<float> {
 // The BF16 256x128 tile keeps one LDS stage so that two workgroups share a CU (one's
 // prologue and epilogue overlap the other's matrix-core loop; measured 1.3-1.6x on the
 // layer-1 GEMMs).  Other tiles, and FP32 (whose weight-gradient GEMM lost 15% that way),
-// double-buffer with one workgroup per CU.
+// double-buffer: two workgroups per CU for the BF16 128x128 tile (74 KB), one for FP32's
+// 256x128 (110 KB).
 constexpr int tile_nbuf(int bm, int bn, int esz) { return (bm == 256 && bn == 128 && esz == 2) ? 1 : 2; }
 // Workgroups per CU that a tile is compiled for (its register budget follows): the single-stage
 // BF16 256x128 tile and the double-buffered BF16 128x128 tile (74 KB) fit two.
