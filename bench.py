@@ -744,8 +744,8 @@ def run_library_gemm(P, dev, reps=5):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
-              "(particles would shard across GPUs, see the design notes)", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported: sharding the particles "
+              "across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2601_21983_amd as P

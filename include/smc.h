@@ -60,7 +60,7 @@ typedef enum smc_status {
   SMC_ERR_DEVICE = 3,       /* a HIP call failed */
   SMC_ERR_STATE = 4,        /* call not valid in the handle's current state */
   SMC_ERR_NONFINITE = 5,    /* every particle has a non-finite log-weight */
-  SMC_ERR_UNSUPPORTED = 6,  /* configuration not supported by this build */
+  SMC_ERR_UNSUPPORTED = 6,  /* configuration not supported by the library */
   SMC_ERR_NOLIB = 7         /* reserved for bindings: library not loaded */
 } smc_status;
 

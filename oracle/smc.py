@@ -14,7 +14,7 @@ Section 3 (batch inference and data annealing) step by step:
   when the ESS falls below J/2, weights reset to 1/J
 * posterior estimates E[f] ~ sum_j w~_j f(theta_j)
 
-Readings taken where the paper is silent (each is listed in the design notes):
+Readings taken where the paper is silent:
 * target: log pi_k(theta) = lambda_k * LL_k(theta) - |theta|^2 / (2 sigma_p^2),
   lambda_k = N / M_k scales both the log-likelihood and its gradient
   (Section 3: stochastic estimates of log-likelihoods and gradients);
