@@ -811,7 +811,7 @@ def main():
         target = ref_tr[-1][2] - 0.005
         target_mlp = ref_tr[-1][3] - 0.005
         # the templates are nearly separable, so every leg passes the accuracy target within a few
-        # iterations; the primary judge is the mean log predictive (the paper's test loss)
+        # iterations; the primary criterion is the mean log predictive (the paper's test loss)
         tta = {"reference_leg": ref, "primary": "mean_log_pred", "target_mean_log_pred": round(target_mlp, 5),
                "target_accuracy": round(target, 4)}
         for l, (tr, mess, jrep) in traces.items():
