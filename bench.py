@@ -197,9 +197,11 @@ def drive(s, leg, sizes, steps, judge=None, on_step=None, profiled=False):
     the sampler's own launches only."""
     learned = leg_parts(leg)[1] == "learned"
     for k in range(1, steps + 1):
-        want = learned or on_step is not None
+        # the step's statistics (a device-to-host copy) only while the judge still reads them
+        judging = learned and judge is not None and s.proposal == "learned"
+        want = judging or on_step is not None
         info = s.step(sizes[k], N_TRAIN / sizes[k], info=want)
-        if learned and judge is not None:
+        if judging:
             if profiled:
                 s.profile(False)
             judge.after_step(s, k, info["ess"])
