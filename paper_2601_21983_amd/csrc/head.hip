@@ -28,11 +28,14 @@
 // weights are split when loaded.  Data X (a network without hidden layer) stays
 // single BF16: its rounding is the same at every state and cancels in the
 // log-likelihood differences that enter the importance weights.
-// MFMA forms: bf16 v_mfma_f32_16x16x16_bf16 (a lane supplies 4 consecutive K
-// values), fp32 v_mfma_f32_16x16x4_f32 issued four times over a 4-wide K slice
-// (instruction t takes component t; lane groups cover K offsets 4g + t), so both
-// precisions read 4 consecutive K values per lane.  Accumulator layout: lane l
-// holds rows 4(l/16) + i, column l % 16.
+// MFMA forms: bf16 v_mfma_f32_16x16x32_bf16 over two 16-wide K blocks at once (a
+// lane supplies 4 consecutive K values of each block; a lone block, or a pair of
+// products of one block such as w_lo a_hi + w_hi a_hi, fills the same 8 slots)
+// and v_mfma_f32_16x16x16_bf16 for a block left over; fp32 v_mfma_f32_16x16x4_f32
+// issued four times over a 4-wide K slice (instruction t takes component t; lane
+// groups cover K offsets 4g + t), so both precisions read 4 consecutive K values
+// per lane and block.  Accumulator layout: lane l holds rows 4(l/16) + i,
+// column l % 16.
 // Log-likelihoods are summed in FP64 in a fixed order.
 #include "gemm_core.h"
 #include "kernels.h"
@@ -49,6 +52,7 @@ constexpr int MAXHB = 8;  // h-blocks per wave in the dW_L accumulator: Hp <= 4 
 constexpr int PF = 8;     // 8-byte chunks of the next activation tile prefetched per thread
 
 typedef __attribute__((__vector_size__(4 * sizeof(short)))) short s16x4;
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short s16x8;
 
 template <typename T> struct V4;
 template <> struct V4<__bf16> {
@@ -67,6 +71,21 @@ __device__ __forceinline__ f32x4 mma16(const f32x4& a, const f32x4& b, f32x4 c) 
   c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], c, 0, 0, 0);
   c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], c, 0, 0, 0);
   return c;
+}
+// Two 16-wide K blocks in one product: lane group g puts elements 4g..4g+3 of block 0 in K slots
+// 8g..8g+3 and those of block 1 in slots 8g+4..8g+7, so the sum over the 32 slots covers both
+// blocks.  BF16: one v_mfma_f32_16x16x32_bf16, which takes the matrix cores as long as one
+// 16x16x16 product; FP32: the two 16-wide products.
+__device__ __forceinline__ f32x4 mma16x2(const s16x4& a0, const s16x4& a1, const s16x4& b0, const s16x4& b1,
+                                         f32x4 c) {
+  const s16x8 a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+  const s16x8 b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+__device__ __forceinline__ f32x4 mma16x2(const f32x4& a0, const f32x4& a1, const f32x4& b0, const f32x4& b1,
+                                         f32x4 c) {
+  return mma16(a1, b1, mma16(a0, b0, c));
 }
 
 template <typename T>
@@ -220,19 +239,36 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
   // ---- 1. logits^T for this wave's 16 samples
   const T* arow = As + (w * 16 + cl) * AS + 4 * g;
   const T* wrow = Wc + cl * AS + 4 * g;
-  f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+  // two accumulators: products over pairs of K blocks, the second chain independent of the first
+  f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f}, z2 = {0.0f, 0.0f, 0.0f, 0.0f};
   if (SPL) {
+    // per block: w_lo a_hi + w_hi a_hi in one product; the w_hi a_lo terms over pairs of blocks
     const T* wrowlo = WcLo + cl * AS + 4 * g;
     const T* arowlo = AsLo + (w * 16 + cl) * AS + 4 * g;
     for (int kb = 0; kb < NHB; ++kb) {
       const typename V4<T>::type wv = ld4(wrow + kb * 16), av = ld4(arow + kb * 16);
-      z = mma16(ld4(wrowlo + kb * 16), av, z);
-      if (alo) z = mma16(wv, ld4(arowlo + kb * 16), z);
-      z = mma16(wv, av, z);
+      z = mma16x2(ld4(wrowlo + kb * 16), wv, av, av, z);
+    }
+    if (alo) {
+      int kb = 0;
+      for (; kb + 1 < NHB; kb += 2)
+        z2 = mma16x2(ld4(wrow + kb * 16), ld4(wrow + kb * 16 + 16), ld4(arowlo + kb * 16),
+                     ld4(arowlo + kb * 16 + 16), z2);
+      if (kb < NHB) z2 = mma16(ld4(wrow + kb * 16), ld4(arowlo + kb * 16), z2);
     }
   } else {
-    for (int kb = 0; kb < NHB; ++kb) z = mma16(ld4(wrow + kb * 16), ld4(arow + kb * 16), z);
+    int kb = 0;
+    for (; kb + 3 < NHB; kb += 4) {
+      z = mma16x2(ld4(wrow + kb * 16), ld4(wrow + kb * 16 + 16), ld4(arow + kb * 16), ld4(arow + kb * 16 + 16), z);
+      z2 = mma16x2(ld4(wrow + kb * 16 + 32), ld4(wrow + kb * 16 + 48), ld4(arow + kb * 16 + 32),
+                   ld4(arow + kb * 16 + 48), z2);
+    }
+    for (; kb + 1 < NHB; kb += 2)
+      z = mma16x2(ld4(wrow + kb * 16), ld4(wrow + kb * 16 + 16), ld4(arow + kb * 16), ld4(arow + kb * 16 + 16), z);
+    if (kb < NHB) z2 = mma16(ld4(wrow + kb * 16), ld4(arow + kb * 16), z2);
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) z[i] += z2[i];
 
   // ---- 2. likelihood and output error (sample cl, classes 4g + i)
   const int sl = w * 16 + cl;           // sample within the tile
@@ -300,8 +336,8 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
       const typename V4<T>::type bd = pack4<T>(d);
       for (int hb = 0; hb < NHB; ++hb) {
         f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (SPL) v = mma16(bd, ld4(WtLo + (hb * 16 + cl) * WT + 4 * g), v);
-        v = mma16(bd, ld4(Wt + (hb * 16 + cl) * WT + 4 * g), v);
+        if (SPL) v = mma16x2(bd, bd, ld4(WtLo + (hb * 16 + cl) * WT + 4 * g), ld4(Wt + (hb * 16 + cl) * WT + 4 * g), v);
+        else v = mma16(bd, ld4(Wt + (hb * 16 + cl) * WT + 4 * g), v);
         const int h = hb * 16 + cl;
         if (h < H) {
           const typename V4<T>::type ah = ld4(AsT + h * SS + sl0);
@@ -328,10 +364,10 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
       const int hb = w + 4 * q;
       if (hb >= NHB) break;
 #pragma unroll
-      for (int kb = 0; kb < HT / 16; ++kb) {
-        const typename V4<T>::type av = ld4(Dt + cl * DS + kb * 16 + 4 * g);
-        const typename V4<T>::type bv = ld4(AsT + (hb * 16 + cl) * SS + kb * 16 + 4 * g);
-        dacc[q] = mma16(av, bv, dacc[q]);
+      for (int kb = 0; kb < HT / 16; kb += 2) {
+        const T* dr = Dt + cl * DS + kb * 16 + 4 * g;
+        const T* ar = AsT + (hb * 16 + cl) * SS + kb * 16 + 4 * g;
+        dacc[q] = mma16x2(ld4(dr), ld4(dr + 16), ld4(ar), ld4(ar + 16), dacc[q]);
       }
     }
   } else if (MODE == HEAD_TRAIN) {
@@ -340,8 +376,8 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
       const typename V4<T>::type bd = pack4<T>(d);
       for (int hb = 0; hb < NHB; ++hb) {
         f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (SPL) v = mma16(ld4(WtLo + (hb * 16 + cl) * WT + 4 * g), bd, v);
-        v = mma16(ld4(Wt + (hb * 16 + cl) * WT + 4 * g), bd, v);
+        if (SPL) v = mma16x2(ld4(WtLo + (hb * 16 + cl) * WT + 4 * g), ld4(Wt + (hb * 16 + cl) * WT + 4 * g), bd, bd, v);
+        else v = mma16(ld4(Wt + (hb * 16 + cl) * WT + 4 * g), bd, v);
         // activations of sample sl at units hb*16 + 4g .. +3, one vector read per plane; the
         // ReLU derivative needs only the hi plane (a value and its BF16 rounding share a sign)
         const typename V4<T>::type ah = ld4(As + sl * AS + hb * 16 + 4 * g);
@@ -386,10 +422,10 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
       const int hb = w + 4 * q;
       if (hb >= NHB) break;
 #pragma unroll
-      for (int kb = 0; kb < HT / 16; ++kb) {
-        const typename V4<T>::type av = ld4(Dt + cl * DS + kb * 16 + 4 * g);
-        const typename V4<T>::type bv = gather4(As + (kb * 16 + 4 * g) * AS + hb * 16 + cl, AS);
-        dacc[q] = mma16(av, bv, dacc[q]);
+      for (int kb = 0; kb < HT / 16; kb += 2) {
+        const T* dr = Dt + cl * DS + kb * 16 + 4 * g;
+        const T* ar = As + (kb * 16 + 4 * g) * AS + hb * 16 + cl;
+        dacc[q] = mma16x2(ld4(dr), ld4(dr + 16), gather4(ar, AS), gather4(ar + 16 * AS, AS), dacc[q]);
       }
     }
   }
