@@ -73,10 +73,16 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64,
   // ------------------------------------------------------------------ epilogue
   // Staged path: one output whose columns are contiguous inside each column-split
   // segment goes through LDS, so each output row piece is written by consecutive
-  // lanes with the widest aligned vector stores (16, 8 or 4/2 bytes).
-  if (p.out0.cstr == 1 && (EPI == EPI_GRAD || (EPI == EPI_FWD && !p.out1.ptr))) {
-    typedef typename std::conditional<EPI == EPI_GRAD || (EPI == EPI_FWD && F32O), float, T>::type O;
+  // lanes with the widest aligned vector stores (16, 8 or 4/2 bytes).  The error
+  // epilogue keeps FP32 products in LDS and multiplies them by act'(a) while it writes
+  // them out, reading a (row-major like the output, no splits) with the same vectors.
+  const bool aux_rows = EPI == EPI_DELTA && p.aux.cstr == 1 && p.aux.rs >= (1 << 30) && p.aux.cs >= (1 << 30);
+  if (p.out0.cstr == 1 && (EPI == EPI_GRAD || ((EPI == EPI_FWD || aux_rows) && !p.out1.ptr))) {
+    // O: element of the LDS slab
+    typedef typename std::conditional<EPI == EPI_GRAD || EPI == EPI_DELTA || (EPI == EPI_FWD && F32O), float,
+                                      T>::type O;
     constexpr int OS = (int)sizeof(O);
+    constexpr int ES = EPI == EPI_DELTA ? (int)sizeof(T) : OS;  // element of the output
     constexpr int SROW = BN + 16 / OS;  // padded LDS row, in elements
     O* slab = (O*)smem;                 // [NWM*32][SROW]
     constexpr int NWM = BM / WM;
@@ -86,10 +92,13 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64,
     int64_t* colpart = rowaddr + NWM * 32;
     const OutDesc& d = p.out0;
     auto aligned = [&](int ve) {
-      return ((uintptr_t)d.ptr % (uintptr_t)(ve * OS)) == 0 && d.rstr % ve == 0 && d.sR % ve == 0 &&
-             d.sb % ve == 0 && d.sC % ve == 0 && d.cs % ve == 0;
+      bool ok = ((uintptr_t)d.ptr % (uintptr_t)(ve * ES)) == 0 && d.rstr % ve == 0 && d.sR % ve == 0 &&
+                d.sb % ve == 0 && d.sC % ve == 0 && d.cs % ve == 0;
+      if (EPI == EPI_DELTA)
+        ok = ok && ((uintptr_t)p.aux.ptr % (uintptr_t)(ve * ES)) == 0 && p.aux.rstr % ve == 0 && p.aux.sb % ve == 0;
+      return ok;
     };
-    const int vw = aligned(16 / OS) ? 16 / OS : (aligned(8 / OS) ? 8 / OS : 1);
+    const int vw = aligned(16 / ES) ? 16 / ES : (aligned(8 / ES) ? 8 / ES : 1);
     for (int lc = tid; lc < BN; lc += NT) {
       const int col = n0 + lc;
       colpart[lc] = col < N ? (int64_t)(col / d.cs) * d.sC + (col % d.cs) : -1;
@@ -118,6 +127,39 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64,
       }
       __syncthreads();
       const int vpr = BN / vw;  // vectors per slab row
+      if constexpr (EPI == EPI_DELTA) {
+        for (int e = tid; e < NWM * 32 * vpr; e += NT) {
+          const int lr = e / vpr, lc = (e - lr * vpr) * vw;
+          const int64_t ra = rowaddr[lr];
+          const int col = n0 + lc;
+          if (ra < 0 || col >= N) continue;
+          const int row = m0 + (lr >> 5) * WM + i * 32 + (lr & 31);
+          T* dst = (T*)d.ptr + ra + colpart[lc];
+          const T* ax = (const T*)p.aux.ptr + (int64_t)b * p.aux.sb + (int64_t)row * p.aux.rstr + col;
+          const float* src = slab + lr * SROW + lc;
+          auto one = [&](float v, T a) { return cvt_out<T>(v * act_deriv<ACT>(cvt_in<T>(a))); };
+          if (col + vw <= N && vw * ES == 16) {
+            typedef __attribute__((__vector_size__(16))) T TV;
+            const TV a = *(const TV*)ax;
+            TV o;
+#pragma unroll
+            for (int q = 0; q < 16 / ES; ++q) o[q] = one(src[q], a[q]);
+            *(TV*)dst = o;
+          } else if (col + vw <= N && vw * ES == 8) {
+            typedef __attribute__((__vector_size__(8))) T TV;
+            const TV a = *(const TV*)ax;
+            TV o;
+#pragma unroll
+            for (int q = 0; q < 8 / ES; ++q) o[q] = one(src[q], a[q]);
+            *(TV*)dst = o;
+          } else {
+            const int n = min(vw, N - col);
+            for (int q = 0; q < n; ++q) dst[q] = one(src[q], ax[q]);
+          }
+        }
+        __syncthreads();
+        continue;
+      }
       for (int e = tid; e < NWM * 32 * vpr; e += NT) {
         const int lr = e / vpr, lc = (e - lr * vpr) * vw;
         const int64_t ra = rowaddr[lr];
@@ -213,22 +255,29 @@ hipError_t launch_one(const GemmParams& p, dim3 grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int BM, int BN, int WM, int WN>
+// GRAD_ONLY: a tile shape that only the weight gradients use (the other epilogues are not
+// instantiated for it)
+template <typename T, int BM, int BN, int WM, int WN, bool GRAD_ONLY = false>
 hipError_t launch_cfg(const GemmParams& p, hipStream_t s) {
   const int64_t ntiles = (int64_t)((p.N + BN - 1) / BN) * ((p.M + BM - 1) / BM);
   if (ntiles > 0x7fffffff || p.batch > 65535) return hipErrorInvalidValue;
   dim3 grid((unsigned)ntiles, p.batch);
-  switch (p.epi) {
-    case EPI_FWD:
-      if (p.act == ACT_RELU) return launch_one<T, BM, BN, WM, WN, EPI_FWD, ACT_RELU>(p, grid, s);
-      if (p.act == ACT_TANH) return launch_one<T, BM, BN, WM, WN, EPI_FWD, ACT_TANH>(p, grid, s);
-      return launch_one<T, BM, BN, WM, WN, EPI_FWD, -1>(p, grid, s);
-    case EPI_GRAD: return launch_one<T, BM, BN, WM, WN, EPI_GRAD, -1>(p, grid, s);
-    case EPI_DELTA:
-      if (p.act == ACT_RELU) return launch_one<T, BM, BN, WM, WN, EPI_DELTA, ACT_RELU>(p, grid, s);
-      if (p.act == ACT_TANH) return launch_one<T, BM, BN, WM, WN, EPI_DELTA, ACT_TANH>(p, grid, s);
-      return hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
+  if constexpr (GRAD_ONLY) {
+    if (p.epi != EPI_GRAD) return hipErrorInvalidValue;
+    return launch_one<T, BM, BN, WM, WN, EPI_GRAD, -1>(p, grid, s);
+  } else {
+    switch (p.epi) {
+      case EPI_FWD:
+        if (p.act == ACT_RELU) return launch_one<T, BM, BN, WM, WN, EPI_FWD, ACT_RELU>(p, grid, s);
+        if (p.act == ACT_TANH) return launch_one<T, BM, BN, WM, WN, EPI_FWD, ACT_TANH>(p, grid, s);
+        return launch_one<T, BM, BN, WM, WN, EPI_FWD, -1>(p, grid, s);
+      case EPI_GRAD: return launch_one<T, BM, BN, WM, WN, EPI_GRAD, -1>(p, grid, s);
+      case EPI_DELTA:
+        if (p.act == ACT_RELU) return launch_one<T, BM, BN, WM, WN, EPI_DELTA, ACT_RELU>(p, grid, s);
+        if (p.act == ACT_TANH) return launch_one<T, BM, BN, WM, WN, EPI_DELTA, ACT_TANH>(p, grid, s);
+        return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
   }
 }
 
@@ -255,17 +304,17 @@ hipError_t gemm_run(const GemmParams& p, int type, hipStream_t stream) {
     // more waves to cover the K-step barriers and LDS round trips (layer-1 weight gradient at
     // 30,000 samples 1.61 ms with four waves, 1.53 with eight of 64x64, 1.46 with sixteen).  The
     // forward (K = 784) lost 17% with eight waves and keeps four.
-    if (big && p.epi == EPI_GRAD) return launch_cfg<__bf16, 256, 128, 64, 32>(p, stream);
+    if (big && p.epi == EPI_GRAD) return launch_cfg<__bf16, 256, 128, 64, 32, true>(p, stream);
     // smaller weight gradients: the 128x128 tile as eight waves of 64x32 (88 VGPRs, two workgroups
     // per CU): the 784-256-256-10 network's layer-2 GEMM class 1.87 -> 1.79 ms
-    if (p.epi == EPI_GRAD) return launch_cfg<__bf16, 128, 128, 64, 32>(p, stream);
+    if (p.epi == EPI_GRAD) return launch_cfg<__bf16, 128, 128, 64, 32, true>(p, stream);
     return big ? launch_cfg<__bf16, 256, 128, 128, 64>(p, stream) : launch_cfg<__bf16, 128, 128, 64, 64>(p, stream);
   }
   if (p.N <= 32) return launch_cfg<float, 256, 32, 64, 32>(p, stream);
   if (p.M <= 32) return launch_cfg<float, 32, 128, 32, 32>(p, stream);
   // FP32 weight gradients too (one double-buffered workgroup per CU): 101 TFLOP/s with four waves,
   // 105 with eight, 109 with sixteen (69% of the FP32 matrix-core peak)
-  if (big && p.epi == EPI_GRAD) return launch_cfg<float, 256, 128, 64, 32>(p, stream);
+  if (big && p.epi == EPI_GRAD) return launch_cfg<float, 256, 128, 64, 32, true>(p, stream);
   return big ? launch_cfg<float, 256, 128, 128, 64>(p, stream) : launch_cfg<float, 128, 128, 64, 64>(p, stream);
 }
 

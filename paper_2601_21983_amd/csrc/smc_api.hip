@@ -1228,8 +1228,34 @@ void grad_pass(smc_t h, const float* theta, int64_t m, double lambda, const doub
         }
         gemm(h, p, l == 0 ? SMC_K_GEMM_DW1 : SMC_K_GEMM_OTHER, 2.0 * J * nout * (double)(nin + 1) * mcv);
       }
-      if (l >= 1) {
+      if (l >= 1 && !h->lb[l - 1].dR && !h->split) {
+        // error of the layer below, (delta_l W_l) * act'(a_{l-1}), as its transpose
+        // W_l^T delta_l^T: rows are units and columns samples, so the error is written
+        // sample-contiguous through the staged epilogue and act' reads the transposed
+        // activations a_{l-1}^T row by row
+        GemmParams p;
+        p.epi = EPI_DELTA;
+        p.act = h->cfg.activation;
+        p.M = nin;
+        p.N = rows;
+        p.K = nout;
+        p.A = h->lb[l].wT;
+        p.lda = h->lb[l].ldwT;
+        p.sAb = (int64_t)nin * h->lb[l].ldwT;
+        p.B = h->lb[l].dR;
+        p.ldb = nout;
+        p.sBb = h->mc * nout;
+        p.batch = J;
+        p.aux.ptr = h->lb[l - 1].actT;
+        p.aux.sb = (int64_t)(nin + 1) * h->mc;
+        p.aux.rstr = h->mc;
+        p.out0.ptr = h->lb[l - 1].dT;
+        p.out0.sb = (int64_t)nin * h->mc;
+        p.out0.rstr = h->mc;
+        gemm(h, p, SMC_K_GEMM_OTHER, 2.0 * J * nout * (double)nin * mcv);
+      } else if (l >= 1) {
         // error of the layer below: (delta_l W_l) * act'(a_{l-1}), written sample-contiguous
+        // here and sample-major to dR for the layer below it
         GemmParams p;
         p.epi = EPI_DELTA;
         p.act = h->cfg.activation;
