@@ -76,8 +76,12 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64,
   // lanes with the widest aligned vector stores (16, 8 or 4/2 bytes).  The error
   // epilogue keeps FP32 products in LDS and multiplies them by act'(a) while it writes
   // them out, reading a (row-major like the output, no splits) with the same vectors.
+  // A forward's second output may be transposed (rows contiguous): it is written from the
+  // same slab, each column's runs of 32 rows as 16-byte vectors.
   const bool aux_rows = EPI == EPI_DELTA && p.aux.cstr == 1 && p.aux.rs >= (1 << 30) && p.aux.cs >= (1 << 30);
-  if (p.out0.cstr == 1 && (EPI == EPI_GRAD || ((EPI == EPI_FWD || aux_rows) && !p.out1.ptr))) {
+  const bool out1_cols = EPI == EPI_FWD && p.out1.ptr && p.out1.rstr == 1 && p.out1.rs >= (1 << 30);
+  if (p.out0.cstr == 1 &&
+      (EPI == EPI_GRAD || (EPI == EPI_FWD && (!p.out1.ptr || out1_cols)) || (aux_rows && !p.out1.ptr))) {
     // O: element of the LDS slab
     typedef typename std::conditional<EPI == EPI_GRAD || EPI == EPI_DELTA || (EPI == EPI_FWD && F32O), float,
                                       T>::type O;
@@ -192,6 +196,32 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64,
           for (int q = 0; q < n; ++q) {
             if (EPI == EPI_GRAD) dst[q] = p.beta ? dst[q] + src[q] : src[q];
             else dst[q] = src[q];
+          }
+        }
+      }
+      if (EPI == EPI_FWD && p.out1.ptr) {
+        // transposed second output: thread (column, run of 32 rows, vector) with the vector index
+        // fastest, so neighbouring lanes fill one column's contiguous run
+        const OutDesc& d1 = p.out1;
+        constexpr int V1 = 16 / OS, CPR = 32 / V1;
+        const bool a1 = ((uintptr_t)d1.ptr % 16) == 0 && d1.sb % V1 == 0 && d1.sC % V1 == 0 && d1.cstr % V1 == 0;
+        for (int e = tid; e < BN * NWM * CPR; e += NT) {
+          const int c = e % CPR, r = (e / CPR) % NWM, lc = e / (CPR * NWM);
+          const int col = n0 + lc;
+          const int row0 = m0 + r * WM + i * 32 + c * V1;
+          if (col >= N || row0 >= M) continue;
+          O* dst = (O*)d1.ptr + (int64_t)b * d1.sb + (int64_t)(col / d1.cs) * d1.sC + (int64_t)(col % d1.cs) * d1.cstr +
+                   row0;
+          const O* src = slab + (r * 32 + c * V1) * SROW + lc;
+          if (a1 && row0 + V1 <= M) {
+            typedef __attribute__((__vector_size__(16))) O OV;
+            OV v;
+#pragma unroll
+            for (int t = 0; t < V1; ++t) v[t] = src[t * SROW];
+            *(OV*)dst = v;
+          } else {
+            const int n = min(V1, M - row0);
+            for (int t = 0; t < n; ++t) dst[t] = src[t * SROW];
           }
         }
       }
