@@ -372,6 +372,7 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
     }
   } else if (MODE == HEAD_TRAIN) {
     // ---- 3. delta_{L-1}^T = W^T delta^T (times act'), staged for sample-contiguous stores
+    const bool dr_vec = a.dR && ((uintptr_t)a.dR % (4 * sizeof(T))) == 0 && a.sdRj % 4 == 0 && a.sdRm % 4 == 0;
     if (a.dT) {
       const typename V4<T>::type bd = pack4<T>(d);
       for (int hb = 0; hb < NHB; ++hb) {
@@ -384,15 +385,26 @@ __device__ __forceinline__ void head_tile(const HeadArgs& a, const HeadLayout& L
         const bool need_lo = alo && a.act != ACT_RELU;
         typename V4<T>::type al = ah;
         if (need_lo) al = ld4(AsLo + sl * AS + hb * 16 + 4 * g);
+        float dv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int h = hb * 16 + 4 * g + i;
           if (h < H) {
             const float av = v4_at<T>(ah, i) + (need_lo ? v4_at<T>(al, i) : 0.0f);
-            const float dv = v[i] * act_grad_from_out(av, a.act);
-            if (Lo.stage) St[h * SS + sl] = cvt_out<T>(dv);
-            else ((T*)a.dT)[(int64_t)j * a.sdTj + (int64_t)h * a.sdTh + sg] = cvt_out<T>(dv);
-            if (a.dR) ((T*)a.dR)[(int64_t)j * a.sdRj + (int64_t)sg * a.sdRm + h] = cvt_out<T>(dv);
+            dv[i] = v[i] * act_grad_from_out(av, a.act);
+            if (Lo.stage) St[h * SS + sl] = cvt_out<T>(dv[i]);
+            else ((T*)a.dT)[(int64_t)j * a.sdTj + (int64_t)h * a.sdTh + sg] = cvt_out<T>(dv[i]);
+          }
+        }
+        if (a.dR) {
+          // sample-major copy: the lane's four consecutive units as one vector when they are all real
+          T* r = (T*)a.dR + (int64_t)j * a.sdRj + (int64_t)sg * a.sdRm + hb * 16 + 4 * g;
+          if (dr_vec && hb * 16 + 4 * g + 3 < H) {
+            *(typename V4<T>::type*)r = pack4<T>(dv);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (hb * 16 + 4 * g + i < H) r[i] = cvt_out<T>(dv[i]);
           }
         }
       }
