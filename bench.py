@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--library-gemm", action="store_true",
                     help="instead of the benchmark: the layer-1 products of this library against torch.matmul "
                          "(hipBLASLt) on the same shapes")
+    ap.add_argument("--deep-only", action="store_true",
+                    help="instead of the benchmark: only the 784-256-256-10, J = 1024 workload")
     ap.add_argument("--sda-iters", type=int, default=SDA_MAX_ITERS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference kernel for HBM counters)")
@@ -776,6 +778,9 @@ def main():
         del a, b
     if args.library_gemm:
         print(json.dumps(run_library_gemm(P, dev)), flush=True)
+        return
+    if args.deep_only:
+        print(json.dumps(run_config3(P, dev, args.seed)), flush=True)
         return
     if args.lenet_pass:
         for Jl in (TABLE1_J, 256):
