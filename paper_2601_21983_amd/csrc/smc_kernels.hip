@@ -115,10 +115,13 @@ __global__ __launch_bounds__(256) void move_kernel(const MoveArgs a) {
     }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const double v0 = wave_sum((double)s_xi), v1 = wave_sum((double)s_th), v2 = wave_sum((double)s_pe);
+  // each mode owns its rows: FIRST |xi|^2 and |theta|^2, MID |theta|^2, LAST |P_end|^2 (only
+  // those are reduced)
+  const double v0 = a.mode == MOVE_FIRST ? wave_sum((double)s_xi) : 0.0;
+  const double v1 = a.mode != MOVE_LAST ? wave_sum((double)s_th) : 0.0;
+  const double v2 = a.mode == MOVE_LAST ? wave_sum((double)s_pe) : 0.0;
   if (lane == 0) { red[0][wid] = v0; red[1][wid] = v1; red[2][wid] = v2; }
   __syncthreads();
-  // each mode owns its rows: FIRST |xi|^2 and |theta|^2, MID |theta|^2, LAST |P_end|^2
   const int w = threadIdx.x;
   const bool own = (a.mode == MOVE_FIRST && w < 2) || (a.mode == MOVE_MID && w == 1) || (a.mode == MOVE_LAST && w == 2);
   if (w < 3 && own) {
