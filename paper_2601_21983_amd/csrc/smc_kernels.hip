@@ -87,14 +87,31 @@ __global__ __launch_bounds__(256) void move_kernel(const MoveArgs a) {
     }
   }
   const float h = a.h, hh = 0.5f * a.h;
+  // all four parameters' loads first: the stores below could alias later loads as far as the
+  // compiler knows, which would otherwise serialise the four round trips
+  float tv[4], gv[4], pv[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t e = e0 + 256 * i;
+    const bool in = e < D;
+    tv[i] = in ? th[e] : 0.0f;
+    gv[i] = in ? g[e] : 0.0f;
+    pv[i] = 0.0f;
+    if (a.mode == MOVE_FIRST) {
+      if (a.noise) pv[i] = in ? a.noise[(int64_t)j * D + e] : 0.0f;
+      else pv[i] = nz[i];
+    } else {
+      pv[i] = in ? P[e] : 0.0f;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t e = e0 + 256 * i;
     if (e >= D) break;
-    float t = th[e];
-    const float gf = g[e] - t * a.inv_prior_var;
+    float t = tv[i];
+    const float gf = gv[i] - t * a.inv_prior_var;
     if (a.mode == MOVE_FIRST) {
-      const float xi = a.noise ? a.noise[(int64_t)j * D + e] : nz[i];
+      const float xi = pv[i];
       s_xi += xi * xi;
       const float p = xi + hh * gf;
       t = t + h * p;
@@ -103,14 +120,14 @@ __global__ __launch_bounds__(256) void move_kernel(const MoveArgs a) {
       s_th += t * t;
       if (a.cast) cast_any(a.net, j, e, t);
     } else if (a.mode == MOVE_MID) {
-      const float p = P[e] + h * gf;
+      const float p = pv[i] + h * gf;
       t = t + h * p;
       P[e] = p;
       th[e] = t;
       s_th += t * t;
       if (a.cast) cast_any(a.net, j, e, t);
     } else {
-      const float p = P[e] + hh * gf;
+      const float p = pv[i] + hh * gf;
       s_pe += p * p;
     }
   }
@@ -523,12 +540,21 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(int64_t D, const int32
   const int p = placement[j];
   if (p == j) return;
   const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + threadIdx.x;  // coalesced, as in cast_kernel
+  // loads first (destination rows are never source rows, but the compiler cannot know that)
+  float v0[4], v1[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t e = e0 + 256 * i;
+    const bool in = e < D;
+    v0[i] = in ? a0[(int64_t)p * D + e] : 0.0f;
+    v1[i] = in && a1 ? a1[(int64_t)p * D + e] : 0.0f;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t e = e0 + 256 * i;
     if (e >= D) break;
-    a0[(int64_t)j * D + e] = a0[(int64_t)p * D + e];
-    if (a1) a1[(int64_t)j * D + e] = a1[(int64_t)p * D + e];
+    a0[(int64_t)j * D + e] = v0[i];
+    if (a1) a1[(int64_t)j * D + e] = v1[i];
   }
 }
 
