@@ -39,10 +39,13 @@ __global__ __launch_bounds__(256) void cast_kernel(const NetShape n, const float
   // consecutive lanes take consecutive parameters (coalesced loads and copy stores)
   const int64_t e0 = (int64_t)blockIdx.x * MOVE_ELEMS + threadIdx.x;
   const float* th = theta + (int64_t)j * n.D;
+  float v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = e0 + 256 * i < n.D ? th[e0 + 256 * i] : 0.0f;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t e = e0 + 256 * i;
-    if (e < n.D) cast_any(n, j, e, th[e]);
+    if (e < n.D) cast_any(n, j, e, v[i]);
   }
 }
 
