@@ -182,8 +182,46 @@ __device__ V block_exclusive_scan(V v, V* wsum, V& total) {
 // ------------------------------------------------------------------ weights
 __global__ __launch_bounds__(1024) void weight_kernel(const WeightArgs a) {
   __shared__ double red[16];
+  __shared__ double psum[3][MAX_J];  // each particle's summed move partials
   constexpr int NPT = MAX_J / 1024;
   const int J = a.J, tid = threadIdx.x;
+  if (a.part) {
+    // tpp neighbouring threads per particle (up to 8, as many as the block holds), each summing
+    // every tpp-th partial with four accumulators, then a butterfly over the group: a fixed
+    // order, so the result is reproducible, with several loads in flight per thread
+    int tpp = 1;
+    while (tpp < 8 && J * tpp * 2 <= 1024) tpp *= 2;
+    const int sub = tid % tpp, nslot = 1024 / tpp;
+    for (int base = 0; base < J; base += nslot) {
+      const int j = base + tid / tpp;
+      double s0[4] = {0, 0, 0, 0}, st[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};
+      if (j < J) {
+        const double* p0 = a.part + (int64_t)j * a.nblk;
+        const double* p1 = a.part + ((int64_t)J + j) * a.nblk;
+        const double* p2 = a.part + ((int64_t)2 * J + j) * a.nblk;
+        int u = 0;
+        for (int b = sub; b < a.nblk; b += tpp, u = (u + 1) & 3) {
+          s0[u] += p0[b];
+          st[u] += p1[b];
+          s1[u] += p2[b];
+        }
+      }
+      double x0 = (s0[0] + s0[1]) + (s0[2] + s0[3]);
+      double xt = (st[0] + st[1]) + (st[2] + st[3]);
+      double x1 = (s1[0] + s1[1]) + (s1[2] + s1[3]);
+      for (int o = 1; o < tpp; o <<= 1) {  // every lane of the block takes part
+        x0 += __shfl_xor(x0, o, 64);
+        xt += __shfl_xor(xt, o, 64);
+        x1 += __shfl_xor(x1, o, 64);
+      }
+      if (j < J && sub == 0) {
+        psum[0][j] = x0;
+        psum[1][j] = xt;
+        psum[2][j] = x1;
+      }
+    }
+    __syncthreads();
+  }
   double lwn[NPT];
   double mx = -INFINITY, llsum = 0.0, llmax = -INFINITY;
   double nbad = 0.0, nfin = 0.0;
@@ -194,29 +232,9 @@ __global__ __launch_bounds__(1024) void weight_kernel(const WeightArgs a) {
     if (j >= J) continue;
     double k0 = 0.0, kt = a.tsq ? a.tsq[j] : 0.0, k1 = 0.0;
     if (a.part) {
-      const double* p0 = a.part + (int64_t)j * a.nblk;
-      const double* p1 = a.part + ((int64_t)J + j) * a.nblk;
-      const double* p2 = a.part + ((int64_t)2 * J + j) * a.nblk;
-      // eight independent accumulators per sum keep 24 loads in flight (a plain running sum
-      // waits for each load in turn); fixed order, so the result is reproducible
-      double s0[8] = {0, 0, 0, 0, 0, 0, 0, 0}, st[8] = {0, 0, 0, 0, 0, 0, 0, 0}, s1[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      int b = 0;
-      for (; b + 8 <= a.nblk; b += 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          s0[u] += p0[b + u];
-          st[u] += p1[b + u];
-          s1[u] += p2[b + u];
-        }
-      }
-      for (int u = 0; b < a.nblk; ++b, ++u) {
-        s0[u] += p0[b];
-        st[u] += p1[b];
-        s1[u] += p2[b];
-      }
-      k0 += ((s0[0] + s0[1]) + (s0[2] + s0[3])) + ((s0[4] + s0[5]) + (s0[6] + s0[7]));
-      kt += ((st[0] + st[1]) + (st[2] + st[3])) + ((st[4] + st[5]) + (st[6] + st[7]));
-      k1 += ((s1[0] + s1[1]) + (s1[2] + s1[3])) + ((s1[4] + s1[5]) + (s1[6] + s1[7]));
+      k0 += psum[0][j];
+      kt += psum[1][j];
+      k1 += psum[2][j];
       if (a.no_kinetic) { k0 = 0.0; k1 = 0.0; }
     }
     const double ll = a.ll[j];
