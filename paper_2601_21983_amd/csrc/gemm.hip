@@ -41,18 +41,34 @@ __device__ __forceinline__ float act_deriv(float a) {
   else return 1.0f - a * a;
 }
 
+// LDS stages and workgroups per CU: the BF16 128x128 tile as four waves of 64x64 (the short-K
+// products of the hidden layers) keeps one stage (37 KB) and is compiled for three workgroups per
+// CU; the others follow gemm_core.h
+template <typename T, int BM, int BN, int WM, int WN>
+constexpr bool short_k_tile() {
+  return sizeof(T) == 2 && BM == 128 && BN == 128 && WM == 64 && WN == 64;
+}
+template <typename T, int BM, int BN, int WM, int WN>
+constexpr int gemm_nbuf() {
+  return short_k_tile<T, BM, BN, WM, WN>() ? 1 : tile_nbuf(BM, BN, (int)sizeof(T));
+}
+template <typename T, int BM, int BN, int WM, int WN>
+constexpr int gemm_minb() {
+  return short_k_tile<T, BM, BN, WM, WN>() ? 3 : tile_minb(BM, BN, (int)sizeof(T));
+}
+
 // ACT: activation of the FWD epilogue / derivative of the DELTA epilogue (-1: none)
 // F32O: the FWD epilogue stores FP32 values (BF16 operands only)
 template <typename T, int BM, int BN, int WM, int WN, int EPI, int ACT, bool F32O>
-// the second bound is waves per SIMD: tile_minb workgroups per CU of NT / 256 waves per SIMD each
+// the second bound is waves per SIMD: gemm_minb workgroups per CU of NT / 256 waves per SIMD each
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64,
-                             tile_minb(BM, BN, (int)sizeof(T)) * (BM / WM) * (BN / WN) / 4) void gemm_nt(
+                             (gemm_minb<T, BM, BN, WM, WN>()) * (BM / WM) * (BN / WN) / 4) void gemm_nt(
     const GemmParams p) {
   constexpr int NT = (BM / WM) * (BN / WN) * 64;  // one wave per WM x WN sub-tile
   constexpr int NWN = BN / WN;
   constexpr int FM = WM / 32, FN = WN / 32;
   constexpr int STAGE = (BM + BN) * LDS_ROW;
-  constexpr int NBUF = tile_nbuf(BM, BN, (int)sizeof(T));
+  constexpr int NBUF = gemm_nbuf<T, BM, BN, WM, WN>();
   // the staged epilogue's slab ([BM/WM * 32 rows][BN + pad] floats plus row and column tables) may
   // need more than the main loop's stages when the waves are stacked four deep
   constexpr int SLAB_NEED = (BM / WM) * 32 * (BN + 4) * 4 + ((BM / WM) * 32 + BN) * 8;
